@@ -1,0 +1,201 @@
+/*
+ * spmesl.h -- C ABI of the MI355X (gfx950) SPMESL library.
+ *
+ * SPMESL estimates a sparse precision matrix by p column-wise scaled-lasso
+ * regressions (Lee, Kim & Yu, arXiv 2203.15031; Sun & Zhang's scaled lasso).
+ * For data X (n x p) the library
+ *   1. centres every column and scales it to x_k^T x_k = n (Section 2.2,
+ *      the paragraph after Eq. (eq:spmesl));
+ *   2. forms the sample covariance S = X^T X / n of the standardised data;
+ *   3. for every column k solves the scaled lasso of Eq. (eq:spmesl),
+ *        min_{beta: beta_kk = 0, sigma > 0}
+ *            ||x_k - X beta||^2 / (2 n sigma) + sigma / 2 + lambda0 ||beta||_1,
+ *      by the block coordinate descent of Section 2.1 / Algorithm 1:
+ *      a lasso step at lambda = sigma * lambda0 solved by cyclic coordinate
+ *      descent in ascending order (Section 3.1), then the noise update
+ *      sigma = ||x_k - X beta||_2 / sqrt(n) (Eq. (eq:sigma)), repeated until
+ *      |delta sigma| < tol;
+ *   4. forms Omega_1 = -B D with D = diag(sigma^-2) (Eq. (eq:relation)) and
+ *      applies the min-magnitude symmetrisation of Eq. (eq:symm);
+ *   5. maps the result back to the scale of the data (Proposition 1) unless
+ *      the standardised scale is asked for.
+ *
+ * Conventions
+ *   - Every pointer in a problem or result struct is a DEVICE pointer owned
+ *     by the caller unless the field says "host".  Matrices are row-major.
+ *   - B is p x p with B[j*p + k] = beta_jk: column k holds the regression
+ *     coefficients of response k, and the diagonal is 0 (the beta_kk = 0
+ *     convention of Section 3.3).
+ *   - Omega is p x p, symmetric bit for bit.
+ *   - Calls are enqueued on the context's HIP stream.  spmesl_solve returns
+ *     after the stream work it enqueued has finished and the status has
+ *     been read back.
+ *   - Functions return 0 (SPMESL_OK) or a negative SPMESL_E* code.  No C++
+ *     exception crosses this interface.  After an error other than
+ *     SPMESL_ENOCONV the outputs are undefined.  spmesl_last_error()
+ *     returns a message for the last failing call on a context.
+ *   - A context is not thread-safe; use one context per host thread/stream.
+ */
+#ifndef SPMESL_H
+#define SPMESL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPMESL_VERSION_MAJOR 0
+#define SPMESL_VERSION_MINOR 1
+
+/* ---- status codes ----------------------------------------------------- */
+#define SPMESL_OK 0
+#define SPMESL_EINVAL (-1)      /* bad argument: NULL, n < 2, p < 2, ldx < p,
+                                   lambda0 <= 0, tol <= 0, unknown enum */
+#define SPMESL_ENONFINITE (-2)  /* NaN or Inf in X */
+#define SPMESL_EZEROVAR (-3)    /* a column of X has zero variance, so the
+                                   scale of Proposition 1 is undefined */
+#define SPMESL_EDEGENERATE (-4) /* some sigma_k^2 fell to <= 1e-12 of the
+                                   standardised variance (perfect fit) */
+#define SPMESL_ENOCONV (-5)     /* an iteration cap was reached; outputs hold
+                                   the last iterate and stats flag the columns */
+#define SPMESL_EHIP (-6)        /* HIP runtime error */
+#define SPMESL_ENOMEM (-7)      /* workspace allocation failed or the caller's
+                                   workspace is too small */
+#define SPMESL_EWORKSET (-8)    /* a column's working set exceeded
+                                   SPMESL_MAX_WORKING_SET variables */
+
+/* Largest working set (candidate variables of one regression) supported. */
+#define SPMESL_MAX_WORKING_SET 128
+
+/* ---- enums -------------------------------------------------------------- */
+/* Arithmetic of the solve. */
+#define SPMESL_FP64 0   /* S, coordinate descent and checks in double */
+#define SPMESL_FP32 1   /* S and coordinate descent in float; tolerance
+                           floored at SPMESL_FP32_TOL_FLOOR */
+#define SPMESL_MIXED 2  /* S from a two-term bfloat16 split on the matrix
+                           cores with float accumulation, float coordinate
+                           descent, then a double-precision polish of every
+                           column (its scaled-lasso fixed point and its KKT
+                           conditions) so that results meet tol in double */
+
+#define SPMESL_FP32_TOL_FLOOR 1e-6
+
+/* Scale of the outputs. */
+#define SPMESL_SCALE_ORIGINAL 0     /* Proposition 1: Omega^o = C Omega C with
+                                       C = diag(s_jj^-1/2); b^o_jk = (c_j/c_k) b_jk;
+                                       sigma^o_k = sigma_k / c_k */
+#define SPMESL_SCALE_STANDARDIZED 1 /* results of the standardised problem */
+
+/* ---- structs ----------------------------------------------------------- */
+typedef struct spmesl_ctx spmesl_ctx;
+
+typedef struct {
+    const double *X; /* device, n x p row-major, row stride ldx (elements) */
+    int64_t n;       /* samples, >= 2 */
+    int64_t p;       /* variables, >= 2 */
+    int64_t ldx;     /* >= p */
+} spmesl_problem;
+
+typedef struct {
+    double lambda0;      /* penalty level lambda0 > 0 of Eq. (eq:spmesl) */
+    double tol;          /* delta of Algorithms 1-3: inner stop when the
+                            largest coefficient change of a sweep is < tol,
+                            outer stop when |delta sigma| < tol */
+    int32_t max_outer;   /* cap on sigma updates per column (<= 0: 1000) */
+    int32_t max_sweeps;  /* cap on sweeps of one lasso step (<= 0: 100000) */
+    int32_t max_rounds;  /* cap on working-set growth rounds (<= 0: 64) */
+    int32_t precision;   /* SPMESL_FP64 | SPMESL_FP32 | SPMESL_MIXED */
+    int32_t output_scale;/* SPMESL_SCALE_ORIGINAL | SPMESL_SCALE_STANDARDIZED */
+    int32_t flags;       /* bit 0: record per-phase times in stats */
+} spmesl_options;
+
+#define SPMESL_FLAG_TIMING 1
+
+typedef struct {
+    /* host-side counters filled by a solve */
+    int64_t columns;          /* p */
+    int64_t total_outer;      /* sum over columns of sigma updates */
+    int64_t max_outer;        /* largest per-column count of sigma updates */
+    int64_t total_sweeps;     /* sum over columns of coordinate sweeps */
+    int64_t total_updates;    /* nonzero coordinate changes */
+    int64_t total_rounds;     /* working-set rounds summed over columns */
+    int64_t max_working_set;  /* largest working set of any column */
+    int64_t nnz_B;            /* nonzero off-diagonal coefficients */
+    int64_t columns_noconv;   /* columns that hit a cap */
+    int64_t polish_kkt_checks;/* double-precision KKT checks (mixed form) */
+    int64_t polish_added;     /* variables the polish added (mixed form) */
+    /* phase times in milliseconds (only with SPMESL_FLAG_TIMING) */
+    double ms_standardize, ms_covariance, ms_solve, ms_polish, ms_output, ms_total;
+} spmesl_stats;
+
+typedef struct {
+    double *B;           /* device p x p or NULL (not written) */
+    double *sigma;       /* device p or NULL */
+    double *Omega;       /* device p x p or NULL */
+    spmesl_stats *stats; /* HOST pointer or NULL */
+} spmesl_result;
+
+/* ---- lifetime ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The context owns a workspace that
+ * grows on demand (hipMalloc) unless the caller supplies one. */
+int spmesl_create(spmesl_ctx **ctx, int device, void *hip_stream);
+void spmesl_destroy(spmesl_ctx *ctx);
+int spmesl_set_stream(spmesl_ctx *ctx, void *hip_stream);
+const char *spmesl_last_error(const spmesl_ctx *ctx);
+const char *spmesl_version(void);
+
+/* Workspace (device bytes) a solve of this shape and precision needs. */
+int spmesl_workspace_size(const spmesl_problem *prob, const spmesl_options *opt,
+                          size_t *bytes);
+/* Hand the context a caller-owned device workspace (NULL releases it, and the
+ * context goes back to allocating its own).  The memory must stay valid
+ * until replaced or the context is destroyed. */
+int spmesl_set_workspace(spmesl_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* ---- the solve ------------------------------------------------------------ */
+
+/* Full SPMESL (steps 1-5 above) of one data matrix.  Output arrays that are
+ * NULL are skipped.  Returns SPMESL_OK, SPMESL_ENOCONV (with the last
+ * iterate), or an error code. */
+int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob,
+                 const spmesl_options *opt, spmesl_result *res);
+
+/* Solve `count` independent problems (uneven n, p) with the same options.
+ * status[i] (host) receives each problem's code; the return value is the
+ * first non-OK code, or SPMESL_OK. */
+int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
+                       const spmesl_options *opt, spmesl_result *res, int *status);
+
+/* ---- single steps (each is also a step of spmesl_solve) ---------------- */
+
+/* Steps 1-2: standardise X and form S.  S is p x p row-major, double when
+ * precision is SPMESL_FP64 and float (S_out must then point to floats)
+ * otherwise; its diagonal is exactly 1.  mean and scale (c_k = s_kk^-1/2 of
+ * the centred data), device arrays of p doubles, may be NULL. */
+int spmesl_covariance(spmesl_ctx *ctx, const spmesl_problem *prob, int precision,
+                      void *S_out, double *mean, double *scale);
+
+/* Step 4's symmetrisation alone (Eq. (eq:symm)): Omega = symm(Omega1), p x p
+ * row-major device arrays; for j < k both entries become the one of smaller
+ * magnitude, and on a tie the upper entry Omega1[j*p+k]. */
+int spmesl_symmetrize(spmesl_ctx *ctx, int64_t p, const double *Omega1,
+                      double *Omega);
+
+/* ---- penalty levels (host, pure; Section 2.2) --------------------------- */
+/* lambda_univ = sqrt(2 log(p-1) / n). */
+double spmesl_lambda_univ(double n, double p);
+/* lambda_ub = sqrt(4 log p / n): the union bound over p scaled lassos. */
+double spmesl_lambda_ub(double n, double p);
+/* lambda_pb = sqrt(2) L_n(k/p), L_n(t) = n^-1/2 Phi^-1(1 - t), with k the
+ * root in (0, p/2) of k = L_1^4(k/p) + 2 L_1^2(k/p).  Writes lambda_pb and
+ * (if k_out != NULL) k.  Returns SPMESL_OK or SPMESL_EINVAL. */
+int spmesl_lambda_pb(double n, double p, double *lambda_out, double *k_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMESL_H */

@@ -1,0 +1,377 @@
+"""Pins of the CPU oracle to things other than itself (no GPU needed).
+
+Each test checks the oracle against something the paper or mathematics
+fixes: the worked example of Section 2.2, closed forms derived from Eq. (1),
+an exact enumeration of supports and signs (which solves the scaled lasso's
+optimality conditions in closed form per support), invariants (KKT, the sigma
+identity, symmetry), and the equivariances of Proposition 1 and of column
+permutations and sign flips.  The last test plants mistakes in the oracle
+(a C macro) and checks that the pins catch every one of them.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.api import load as oracle_load
+from paper_2203_15031_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# independent references used by the pins
+# ---------------------------------------------------------------------------
+
+def centred_moments(X):
+    """S (1/n) of the centred data, without any scaling."""
+    Xc = X - X.mean(axis=0, keepdims=True)
+    return Xc.T @ Xc / X.shape[0]
+
+
+def scaled_lasso_enumerate(S, k, lambda0, w=None):
+    """Exact scaled lasso of column k by enumeration of supports and signs.
+
+    Solves min_b,sigma  R(b)/(2 sigma) + sigma/2 + lambda0 sum_j w_j |b_j|,
+    R(b) = S_kk - 2 s^T b + b^T S b, b_k = 0.  For a support A and signs z
+    the stationarity conditions give b_A = S_AA^-1 (s_A - lambda0 sigma (w z)_A)
+    and sigma^2 = R(b), whose solution is
+    sigma^2 = (S_kk - s_A^T u) / (1 - lambda0^2 (wz)^T v), u = S_AA^-1 s_A,
+    v = S_AA^-1 (wz)_A.  The valid (A, z) -- signs consistent, and
+    |g_j| <= lambda0 sigma w_j off A -- is the unique minimiser.
+    """
+    p = S.shape[0]
+    w = np.ones(p) if w is None else np.asarray(w)
+    idx = [j for j in range(p) if j != k]
+    s = S[:, k]
+    yy = S[k, k]
+    sols = []
+    for m in range(len(idx) + 1):
+        for A in itertools.combinations(idx, m):
+            A = list(A)
+            for z in itertools.product([-1.0, 1.0], repeat=m):
+                z = np.array(z)
+                b = np.zeros(p)
+                if m:
+                    SA = S[np.ix_(A, A)]
+                    u = np.linalg.solve(SA, s[A])
+                    v = np.linalg.solve(SA, w[A] * z)
+                    num = yy - s[A] @ u
+                    den = 1.0 - lambda0 ** 2 * ((w[A] * z) @ v)
+                    if num <= 0 or den <= 0:
+                        continue
+                    sig = math.sqrt(num / den)
+                    bA = u - lambda0 * sig * v
+                    if np.any(np.sign(bA) != z):
+                        continue
+                    b[A] = bA
+                else:
+                    sig = math.sqrt(yy)
+                g = s - S @ b
+                off = [j for j in idx if j not in A]
+                lam = lambda0 * sig
+                if any(abs(g[j]) > lam * w[j] * (1 + 1e-10) + 1e-13 for j in off):
+                    continue
+                sols.append((b, sig))
+    assert len(sols) == 1, f"expected a unique valid support, got {len(sols)}"
+    return sols[0]
+
+
+def spmesl_enumerate(X, lambda0, original_scale):
+    """SPMESL by enumeration: the Proposition 1 problem on the raw centred
+    data (weights sqrt(s_jj)) when original_scale, else the problem on the
+    standardised data; then Omega_1 = -B D and the min-magnitude rule."""
+    S = centred_moments(X)
+    p = S.shape[0]
+    if original_scale:
+        Sw, w = S, np.sqrt(np.diag(S))
+    else:
+        d = 1.0 / np.sqrt(np.diag(S))
+        Sw, w = S * d[:, None] * d[None, :], np.ones(p)
+    B = np.zeros((p, p))
+    sig = np.zeros(p)
+    for k in range(p):
+        B[:, k], sig[k] = scaled_lasso_enumerate(Sw, k, lambda0, w)
+    Om1 = -B / sig[None, :] ** 2
+    Om1[np.diag_indices(p)] = 1.0 / sig ** 2
+    Om = symmetrize_definition(Om1)
+    return B, sig, Om
+
+
+def symmetrize_definition(M):
+    """Eq. (eq:symm): for j < k both entries become the smaller-magnitude one,
+    the upper entry on a tie."""
+    U = np.triu(M, 1)
+    L = np.triu(M.T, 1)
+    pick = np.where(np.abs(U) <= np.abs(L), U, L)
+    return pick + pick.T + np.diag(np.diag(M))
+
+
+def tiny_problem(seed, n=14, p=6, rho=0.6, scales=True):
+    rng = np.random.default_rng(seed)
+    X = W.sample_from_cov(n, W.ar_cov(p, rho), rng, centre=False)
+    if scales:
+        X = X * rng.uniform(0.3, 3.0, size=p)[None, :] + rng.uniform(-2, 2, size=p)[None, :]
+    return X
+
+
+# ---------------------------------------------------------------------------
+# pins
+# ---------------------------------------------------------------------------
+
+def test_penalty_levels_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "penalty_levels.json")))
+    n, p, tol = g["n"], g["p"], 0.5 * 10 ** -g["printed_decimals"]
+    assert abs(oracle.lambda_ub(n, p) - g["lambda_ub"]) <= tol
+    assert abs(oracle.lambda_univ(n, p) - g["lambda_univ"]) <= tol
+    lam, k = oracle.lambda_pb(n, p)
+    assert abs(lam - g["lambda_pb"]) <= tol
+    assert abs(k - g["k"]) <= tol
+
+
+def test_lambda_pb_root_equation():
+    # the root satisfies k = L^4 + 2 L^2 with L = Phi^-1(1 - k/p)
+    from scipy.stats import norm
+    for p in (100, 500, 1000, 5000):
+        lam, k = oracle.lambda_pb(250, p)
+        L = norm.ppf(1 - k / p)
+        assert abs(k - (L ** 4 + 2 * L ** 2)) < 1e-8 * k
+        assert 0 < k < p / 2
+        assert abs(lam - math.sqrt(2) * L / math.sqrt(250)) < 1e-12
+
+
+def test_standardize():
+    X = tiny_problem(3, n=30, p=5)
+    Xs, mean, c = oracle.standardize(X)
+    np.testing.assert_allclose(mean, X.mean(0), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(c, 1 / X.std(0), rtol=1e-14)
+    np.testing.assert_allclose((Xs ** 2).sum(0), X.shape[0], rtol=1e-14)
+    np.testing.assert_allclose(Xs.mean(0), 0, atol=1e-14)
+
+
+@pytest.mark.parametrize("r,lam0", [(0.6, 0.3), (-0.45, 0.2), (0.9, 0.5), (0.25, 0.3), (-0.1, 0.15)])
+def test_scaled_lasso_one_predictor_closed_form(r, lam0):
+    # One standardised predictor with correlation r: Eq. (1) gives
+    # sigma^2 = (1 - r^2) / (1 - lam0^2), beta = r - sign(r) lam0 sigma when
+    # |r| > lam0, and beta = 0, sigma = 1 otherwise.
+    rng = np.random.default_rng(11)
+    X = W.orthogonal_pairs_design(40, [r], rng)
+    y, x = X[:, 0], X[:, 1:2]
+    b, s, _, _, st = oracle.scaled_lasso(x, y, lam0, tol=1e-14)
+    assert st == 0
+    if abs(r) > lam0:
+        sig = math.sqrt((1 - r * r) / (1 - lam0 * lam0))
+        beta = r - math.copysign(lam0 * sig, r)
+    else:
+        sig, beta = 1.0, 0.0
+    assert abs(s - sig) < 1e-12
+    assert abs(b[0] - beta) < 1e-12
+
+
+def test_scaled_lasso_y_scale_equivariance():
+    # Section 2.1: beta(X, a y) = a beta(X, y), sigma(X, a y) = |a| sigma(X, y)
+    X = tiny_problem(5, n=40, p=8, scales=False)
+    Xs, _, _ = oracle.standardize(X)
+    y = Xs[:, 0]
+    D = Xs[:, 1:]
+    b1, s1, *_ = oracle.scaled_lasso(D, y, 0.2, tol=1e-14)
+    for a in (-2.5, 0.3, 7.0):
+        b2, s2, *_ = oracle.scaled_lasso(D, a * y, 0.2, tol=1e-14)
+        np.testing.assert_allclose(b2, a * b1, rtol=1e-9, atol=1e-12)
+        assert abs(s2 - abs(a) * s1) < 1e-10 * abs(a)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_spmesl_matches_enumeration_original_scale(seed):
+    X = tiny_problem(seed)
+    lam0 = 0.3
+    r = oracle.spmesl(X, lam0, tol=1e-14, original_scale=True)
+    assert r["status"] == 0
+    B, sig, Om = spmesl_enumerate(X, lam0, original_scale=True)
+    assert (B != 0).sum() >= 4, "the case must have a non-trivial support"
+    np.testing.assert_allclose(r["sigma"], sig, rtol=1e-10)
+    np.testing.assert_allclose(r["B"], B, rtol=0, atol=1e-10 * np.abs(B).max())
+    np.testing.assert_allclose(r["Omega"], Om, rtol=0, atol=1e-10 * np.abs(Om).max())
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_spmesl_matches_enumeration_standardized(seed):
+    X = tiny_problem(seed, p=7)
+    lam0 = 0.25
+    r = oracle.spmesl(X, lam0, tol=1e-14, original_scale=False)
+    B, sig, Om = spmesl_enumerate(X, lam0, original_scale=False)
+    np.testing.assert_allclose(r["sigma"], sig, rtol=1e-10)
+    np.testing.assert_allclose(r["B"], B, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(r["Omega"], Om, rtol=0, atol=1e-10 * np.abs(Om).max())
+
+
+def test_spmesl_pairs_closed_form():
+    # Columns in exactly-correlated pairs, uncorrelated across pairs: each
+    # pair is the one-predictor case, so omega_kk = (1 - lam0^2)/(1 - r^2)
+    # when |r| > lam0 (else 1), omega_jk = -beta/sigma^2, zero across pairs.
+    rng = np.random.default_rng(7)
+    rs = [0.6, -0.5, 0.2, 0.85]
+    lam0 = 0.3
+    X = W.orthogonal_pairs_design(60, rs, rng)
+    r = oracle.spmesl(X, lam0, tol=1e-14, original_scale=False)
+    p = X.shape[1]
+    Om = np.zeros((p, p))
+    for i, rr in enumerate(rs):
+        a, b = 2 * i, 2 * i + 1
+        if abs(rr) > lam0:
+            s2 = (1 - rr * rr) / (1 - lam0 * lam0)
+            beta = rr - math.copysign(lam0 * math.sqrt(s2), rr)
+        else:
+            s2, beta = 1.0, 0.0
+        Om[a, a] = Om[b, b] = 1 / s2
+        Om[a, b] = Om[b, a] = -beta / s2
+    np.testing.assert_allclose(r["Omega"], Om, rtol=0, atol=1e-11)
+    assert np.array_equal(r["Omega"], r["Omega"].T)
+
+
+def test_null_case_gives_scaled_identity():
+    # lambda0 >= max |s_jk| -> beta = 0, sigma = 1, Omega = diag(1/s_kk)
+    X = tiny_problem(9, n=50, p=6)
+    S = centred_moments(X)
+    d = 1 / np.sqrt(np.diag(S))
+    R = S * d[:, None] * d[None, :]
+    lam0 = np.abs(R - np.eye(6)).max() * 1.01
+    r = oracle.spmesl(X, lam0, tol=1e-12, original_scale=True)
+    assert np.all(r["B"] == 0)
+    np.testing.assert_allclose(r["Omega"], np.diag(1 / np.diag(S)), rtol=1e-13, atol=0)
+    np.testing.assert_allclose(r["sigma"], np.sqrt(np.diag(S)), rtol=1e-13)
+
+
+def test_kkt_and_sigma_identity_workload1():
+    w = W.workload("ar1_n100_p200")
+    X = W.generate(w.name)
+    lam0 = w.lambda0
+    r = oracle.spmesl(X, lam0, tol=1e-12, original_scale=False)
+    assert r["status"] == 0
+    Xs = (X - X.mean(0)) / X.std(0)
+    n = X.shape[0]
+    S = Xs.T @ Xs / n
+    B, sig = r["B"], r["sigma"]
+    G = S - S @ B                       # g_jk = x_j^T (x_k - X b_k) / n
+    lam = lam0 * sig[None, :]
+    off = np.ones_like(B, bool)
+    np.fill_diagonal(off, False)
+    on = (B != 0) & off
+    zero = (B == 0) & off
+    assert np.abs(G[on] - lam.repeat(B.shape[0], 0)[on] * np.sign(B[on])).max() < 1e-9
+    assert (np.abs(G[zero]) - np.broadcast_to(lam, B.shape)[zero]).max() < 1e-9
+    res = Xs - Xs @ B
+    np.testing.assert_allclose(sig, np.sqrt((res ** 2).sum(0) / n), rtol=1e-10)
+    ident = 1 - (S * B).sum(0) - lam0 * sig * np.abs(B).sum(0)
+    np.testing.assert_allclose(sig ** 2, ident, rtol=0, atol=1e-9)
+    # Omega: exact symmetry, AND-rule support, min-magnitude entries
+    Om, Om1 = r["Omega"], r["Omega1"]
+    assert np.array_equal(Om, Om.T)
+    np.testing.assert_array_equal(Om, symmetrize_definition(Om1))
+    both = (B != 0) & (B.T != 0)
+    assert np.array_equal((Om != 0) & off, both)
+    np.testing.assert_allclose(np.diag(Om), 1 / sig ** 2, rtol=1e-15)
+
+
+def test_permutation_and_sign_equivariance():
+    X = W.generate("ar1_n100_p200", n=60, p=40)
+    lam0 = 0.3
+    base = oracle.spmesl(X, lam0, tol=1e-13)
+    rng = np.random.default_rng(2)
+    perm = rng.permutation(40)
+    rp = oracle.spmesl(X[:, perm], lam0, tol=1e-13)
+    np.testing.assert_allclose(rp["Omega"], base["Omega"][np.ix_(perm, perm)], rtol=0, atol=1e-9)
+    flip = rng.choice([-1.0, 1.0], size=40)
+    rf = oracle.spmesl(X * flip, lam0, tol=1e-13)
+    np.testing.assert_allclose(rf["Omega"], base["Omega"] * flip[:, None] * flip[None, :],
+                               rtol=0, atol=1e-9)
+
+
+def test_proposition1_column_scaling():
+    # scaling column k by a_k maps Omega^o -> diag(a)^-1 Omega^o diag(a)^-1,
+    # B^o_jk -> (a_k / a_j) B^o_jk, sigma^o_k -> a_k sigma^o_k
+    X = W.generate("ar1_n100_p200", n=60, p=30)
+    lam0 = 0.3
+    a = np.random.default_rng(4).uniform(0.2, 5.0, size=30)
+    r0 = oracle.spmesl(X, lam0, tol=1e-13)
+    r1 = oracle.spmesl(X * a, lam0, tol=1e-13)
+    np.testing.assert_allclose(r1["Omega"], r0["Omega"] / a[:, None] / a[None, :],
+                               rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(r1["B"], r0["B"] * a[None, :] / a[:, None], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(r1["sigma"], r0["sigma"] * a, rtol=1e-10)
+
+
+def test_symmetrize_rule_with_ties():
+    M = np.array([[1.0, -0.2, 0.5, 0.0],
+                  [0.3, 2.0, -0.1, 0.4],
+                  [-0.5, 0.1, 3.0, 0.0],
+                  [0.0, -0.7, 0.2, 4.0]])
+    out = oracle.symmetrize(M)
+    expect = np.array([[1.0, -0.2, 0.5, 0.0],    # tie |0.5| = |-0.5| keeps the upper 0.5
+                       [-0.2, 2.0, -0.1, 0.4],    # tie |-0.1| = |0.1| keeps the upper -0.1
+                       [0.5, -0.1, 3.0, 0.0],
+                       [0.0, 0.4, 0.0, 4.0]])
+    np.testing.assert_array_equal(out, expect)
+    rng = np.random.default_rng(0)
+    R = rng.standard_normal((9, 9))
+    np.testing.assert_array_equal(oracle.symmetrize(R), symmetrize_definition(R))
+
+
+def test_iteration_cap_reports_noconv():
+    X = W.generate("ar1_n100_p200", n=60, p=30)
+    r = oracle.spmesl(X, 0.2, tol=1e-12, max_outer=1)
+    assert r["status"] == -3
+    assert (r["col_status"] == -3).any()
+
+
+def test_zero_variance_column_rejected():
+    X = W.generate("ar1_n100_p200", n=30, p=8)
+    X[:, 3] = 1.5
+    with pytest.raises(oracle.api.OracleError) as e:
+        oracle.spmesl(X, 0.3)
+    assert e.value.code == -2
+
+
+def test_columns_subset_matches_full():
+    X = W.generate("ar1_n100_p200", n=60, p=40)
+    full = oracle.spmesl(X, 0.3, tol=1e-10, original_scale=False)
+    cols = np.array([0, 7, 39, 12])
+    sub = oracle.spmesl_columns(X, 0.3, cols, tol=1e-10)
+    np.testing.assert_array_equal(sub["B"], full["B"][:, cols])
+    np.testing.assert_array_equal(sub["sigma"], full["sigma"][cols])
+
+
+# ---------------------------------------------------------------------------
+# the pins catch planted mistakes
+# ---------------------------------------------------------------------------
+
+def _pins_pass(lib):
+    """The fast pins, run against an alternative build of the oracle."""
+    X = tiny_problem(1)
+    lam0 = 0.3
+    try:
+        r = oracle.spmesl(X, lam0, tol=1e-13, original_scale=True, lib=lib)
+    except oracle.api.OracleError:
+        return False
+    B, sig, Om = spmesl_enumerate(X, lam0, original_scale=True)
+    ok = (np.allclose(r["sigma"], sig, rtol=1e-8) and
+          np.allclose(r["B"], B, atol=1e-8) and
+          np.allclose(r["Omega"], Om, atol=1e-8))
+    Mt = np.array([[1.0, 0.3, -0.2], [0.1, 1.0, 0.5], [0.4, -0.6, 1.0]])
+    ok = ok and np.array_equal(oracle.symmetrize(Mt, lib=lib), symmetrize_definition(Mt))
+    return ok
+
+
+@pytest.mark.parametrize("mutant", range(1, 10))
+def test_pins_catch_planted_mistake(mutant, tmp_path):
+    lib = oracle_load(0)
+    assert _pins_pass(lib)
+    path = str(tmp_path / f"liboracle_m{mutant}.so")
+    oracle.api.build(mutant=mutant, out=path)
+    import ctypes
+    mlib = oracle.api._setup(ctypes.CDLL(path))
+    assert not _pins_pass(mlib), f"planted mistake {mutant} went unnoticed"
