@@ -1,0 +1,339 @@
+// colsolve_dev.hpp -- device routines of the per-column scaled-lasso solver,
+// shared by the float/double solve and the double-precision polish.
+#pragma once
+#include "common.hpp"
+
+namespace spmesl {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T> struct DegenerateFloor;
+template <> struct DegenerateFloor<double> { static constexpr double v = 1e-12; };
+template <> struct DegenerateFloor<float> { static constexpr float v = 1e-6f; };
+
+// LDS of one wave.
+template <typename T, int LW>
+struct WaveSm {
+    T sww[LW * LW];      // sww[q * LW + i] = S[W_i][W_q]
+    int widx[LW];        // W, ascending
+    T wbeta[LW];
+    int tidx[LW];        // merge scratch
+    T tbeta[LW];
+    int sidx[LW];        // support (nonzero beta), ascending
+    T sval[LW];
+    int pend[kPendMax];  // violators found by the last KKT pass, ascending
+};
+
+template <typename T, int LW>
+struct ColState {
+    static constexpr int NS = (LW + kWave - 1) / kWave;  // slots per lane
+    T g[NS], b[NS], sv[NS];
+    int w;
+    T sigma, lam_used;
+};
+
+// lower_bound over an ascending int array in LDS
+__device__ __forceinline__ int lds_lower_bound(const int *a, int n, int v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// KKT pass over all p coordinates of column k.
+//   g_j = s_jk - sum_{l in supp} S_jl beta_l, streamed from rows of S.
+//   violators: j != k, j not in W, |g_j| > thr    -> sm.pend (ascending)
+//   band     : j != k, beta_j == 0, |g_j| > bthr -> band_idx (when recording)
+// Returns the number of violators (may exceed kPendMax; only the first
+// kPendMax are stored).
+// ---------------------------------------------------------------------------
+template <typename TS, typename T, int LW>
+__device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
+                        int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
+{
+    constexpr int CH = 8;
+    const int lane = lane_id();
+    const TS *Sk = S + k * p;
+    int npend = 0, nband = 0;
+    for (int64_t base = 0; base < p; base += (int64_t)kWave * CH) {
+        T acc[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            int64_t j = base + c * kWave + lane;
+            acc[c] = j < p ? (T)Sk[j] : T(0);
+        }
+        for (int t = 0; t < ns; t += 4) {
+            const TS *rows[4];
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bool ok = t + u < ns;
+                int l = ok ? sm.sidx[t + u] : (int)k;
+                v[u] = ok ? sm.sval[t + u] : T(0);
+                rows[u] = S + (int64_t)l * p;
+            }
+            T x[4][CH];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    int64_t j = base + c * kWave + lane;
+                    x[u][c] = j < p ? (T)rows[u][j] : T(0);
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < CH; ++c) acc[c] -= v[u] * x[u][c];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            int64_t j = base + c * kWave + lane;
+            T aa = acc[c] < T(0) ? -acc[c] : acc[c];
+            bool live = j < p && j != k;
+            bool viol = live && aa > thr;
+            bool bnd = record_band && live && aa > bthr;
+            if (viol) {
+                int pos = lds_lower_bound(sm.widx, w, (int)j);
+                viol = !(pos < w && sm.widx[pos] == (int)j);
+            }
+            if (bnd) {
+                int pos = lds_lower_bound(sm.sidx, ns, (int)j);
+                bnd = !(pos < ns && sm.sidx[pos] == (int)j);
+            }
+            unsigned long long m = __ballot(viol);
+            if (m) {
+                int pos = npend + lanes_below(m);
+                if (viol && pos < kPendMax) sm.pend[pos] = (int)j;
+                npend += __popcll(m);
+            }
+            if (record_band) {
+                unsigned long long mb = __ballot(bnd);
+                if (mb) {
+                    int pos = nband + lanes_below(mb);
+                    if (bnd && pos < kBandMax) band_idx[k * kBandMax + pos] = (int)j;
+                    nband += __popcll(mb);
+                }
+            }
+        }
+    }
+    if (record_band && lane == 0) band_cnt[k] = nband;
+    wave_sync();
+    return npend;
+}
+
+// Support list (nonzero coefficients, ascending) from the slot registers.
+template <typename T, int LW>
+__device__ int build_support(WaveSm<T, LW> &sm, const ColState<T, LW> &st)
+{
+    const int lane = lane_id();
+    int ns = 0;
+#pragma unroll
+    for (int s = 0; s < ColState<T, LW>::NS; ++s) {
+        int q = s * kWave + lane;
+        bool nz = q < st.w && st.b[s] != T(0);
+        unsigned long long m = __ballot(nz);
+        if (nz) {
+            int pos = ns + lanes_below(m);
+            sm.sidx[pos] = sm.widx[q];
+            sm.sval[pos] = st.b[s];
+        }
+        ns += __popcll(m);
+    }
+    wave_sync();
+    return ns;
+}
+
+// Merge the np (ascending) pending violators into W (ascending), with
+// coefficient 0 for the new ones.  Requires w + np <= LW.
+template <typename T, int LW>
+__device__ void merge_pending(WaveSm<T, LW> &sm, ColState<T, LW> &st, int np)
+{
+    const int lane = lane_id();
+    const int w = st.w;
+#pragma unroll
+    for (int s = 0; s < ColState<T, LW>::NS; ++s) {
+        int q = s * kWave + lane;
+        if (q < w) {
+            int v = sm.widx[q];
+            int pos = q + lds_lower_bound(sm.pend, np, v);
+            sm.tidx[pos] = v;
+            sm.tbeta[pos] = st.b[s];
+        }
+    }
+    for (int i = lane; i < np; i += kWave) {
+        int v = sm.pend[i];
+        int pos = i + lds_lower_bound(sm.widx, w, v);
+        sm.tidx[pos] = v;
+        sm.tbeta[pos] = T(0);
+    }
+    wave_sync();
+    st.w = w + np;
+    for (int q = lane; q < st.w; q += kWave) {
+        sm.widx[q] = sm.tidx[q];
+        sm.wbeta[q] = sm.tbeta[q];
+    }
+    wave_sync();
+}
+
+// Load s_W, beta (from sm.wbeta) and S_WW (LDS) for the current W from S.
+template <typename T, int LW>
+__device__ void load_working_set(const T *__restrict__ S, int64_t p, int64_t k,
+                                 WaveSm<T, LW> &sm, ColState<T, LW> &st)
+{
+    const int lane = lane_id();
+    const int w = st.w;
+#pragma unroll
+    for (int s = 0; s < ColState<T, LW>::NS; ++s) {
+        int q = s * kWave + lane;
+        if (q < w) {
+            int j = sm.widx[q];
+            st.sv[s] = S[k * p + j];
+            st.b[s] = sm.wbeta[q];
+        } else {
+            st.sv[s] = T(0);
+            st.b[s] = T(0);
+        }
+        st.g[s] = T(0);
+    }
+    const int tot = w * w;
+    for (int e = lane; e < tot; e += kWave) {
+        int qj = e / w, qi = e - qj * w;
+        sm.sww[qj * LW + qi] = S[(int64_t)sm.widx[qj] * p + sm.widx[qi]];
+    }
+    wave_sync();
+}
+
+// g = s_W - S_WW beta, from scratch.
+template <typename T, int LW>
+__device__ void fresh_gradient(WaveSm<T, LW> &sm, ColState<T, LW> &st)
+{
+    constexpr int NS = ColState<T, LW>::NS;
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) st.g[s] = st.sv[s];
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+        unsigned long long m = __ballot(s2 * kWave + lane < st.w && st.b[s2] != T(0));
+        while (m) {
+            int l = __builtin_ffsll((long long)m) - 1;
+            m &= m - 1;
+            int qq = s2 * kWave + l;
+            T bq = bcast(st.b[s2], l);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                int q = s * kWave + lane;
+                if (q < LW) st.g[s] -= sm.sww[qq * LW + q] * bq;
+            }
+        }
+    }
+}
+
+struct SolveCounts {
+    int outer, sweeps, updates;
+};
+
+// Algorithm 1 on the working set: outer sigma loop around cyclic sweeps.
+// Returns kColOk, kColNoconv or kColDegenerate.
+template <typename T, int LW>
+__device__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st, T lambda0, T tol,
+                              int max_outer, int max_sweeps, SolveCounts &cnt)
+{
+    constexpr int NS = ColState<T, LW>::NS;
+    const int lane = lane_id();
+    for (;;) {
+        if (cnt.outer >= max_outer) return kColNoconv;
+        ++cnt.outer;
+        const T lam = st.sigma * lambda0;
+        fresh_gradient(sm, st);
+        bool inner_ok = false;
+        for (int m = 0; m < max_sweeps; ++m) {
+            ++cnt.sweeps;
+            T maxd = T(0);
+            int cur = -1;
+            for (;;) {
+                T nb[NS], d[NS];
+                int qstar = -1;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int q = s * kWave + lane;
+                    nb[s] = soft_threshold(st.g[s] + st.b[s], lam);
+                    d[s] = nb[s] - st.b[s];
+                    bool nz = q < st.w && q > cur && d[s] != T(0);
+                    unsigned long long mk = __ballot(nz);
+                    if (qstar < 0 && mk) qstar = s * kWave + __builtin_ffsll((long long)mk) - 1;
+                }
+                if (qstar < 0) break;
+                const int ss = qstar / kWave, ls = qstar % kWave;
+                T dd = T(0);
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (s == ss) {
+                        dd = bcast(d[s], ls);
+                        if (lane == ls) st.b[s] = nb[s];
+                    }
+                T ad = dd < T(0) ? -dd : dd;
+                maxd = ad > maxd ? ad : maxd;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int q = s * kWave + lane;
+                    if (q < LW) st.g[s] -= sm.sww[qstar * LW + q] * dd;
+                }
+                cur = qstar;
+                ++cnt.updates;
+            }
+            if (maxd < tol) {
+                inner_ok = true;
+                break;
+            }
+        }
+        T part = T(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (s * kWave + lane < st.w) part += st.b[s] * (st.sv[s] + st.g[s]);
+        T dot = wave_sum(part);
+        T s2 = T(1) - dot;
+        st.lam_used = lam;
+        if (!(s2 > DegenerateFloor<T>::v)) {
+            st.sigma = s2 > T(0) ? sqrt(s2) : T(0);
+            return kColDegenerate;
+        }
+        T sn = sqrt(s2);
+        T ds = sn - st.sigma;
+        ds = ds < T(0) ? -ds : ds;
+        st.sigma = sn;
+        if (!inner_ok) return kColNoconv;
+        if (ds < tol) return kColOk;
+    }
+}
+
+template <typename T, int LW>
+__device__ void store_column(const ColArgs<T> &A, int64_t k, WaveSm<T, LW> &sm,
+                             const ColState<T, LW> &st, int status)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 0; s < ColState<T, LW>::NS; ++s) {
+        int q = s * kWave + lane;
+        if (q < st.w) {
+            A.w_idx[k * kWMax + q] = sm.widx[q];
+            A.w_beta[k * kWMax + q] = st.b[s];
+        }
+    }
+    if (lane == 0) {
+        A.w_cnt[k] = st.w;
+        A.sigma[k] = (double)st.sigma;
+        A.lam_used[k] = (double)st.lam_used;
+        A.col_status[k] = status;
+    }
+}
+
+} // namespace spmesl

@@ -1,0 +1,199 @@
+// common.hpp -- device helpers and internal declarations shared by the
+// SPMESL kernels and the host orchestration.  gfx950 only: wave64, MFMA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace spmesl {
+
+constexpr int kWave = 64;
+// Largest working set of one regression (matches SPMESL_MAX_WORKING_SET).
+constexpr int kWMax = 128;
+// Violators one KKT pass may hand to the next round of a column.
+constexpr int kPendMax = 64;
+// Near-threshold candidates a float solve records for the double polish.
+constexpr int kBandMax = 32;
+
+// Per-solve counters, accumulated with 64-bit atomics.
+enum Counter : int {
+    kCntOuter = 0,
+    kCntSweeps,
+    kCntUpdates,
+    kCntRounds,
+    kCntMaxW,
+    kCntMaxOuter,
+    kCntNoconv,
+    kCntEscalated,
+    kCntPolishChecks,
+    kCntPolishAdded,
+    kCntBandOverflow,
+    kNumCounters
+};
+
+// Column status codes written by the kernels (mirror the public codes).
+enum ColStatus : int {
+    kColOk = 0,
+    kColDegenerate = -4,
+    kColNoconv = -5,
+    kColWorkset = -8,
+};
+
+// ---------------------------------------------------------------------------
+// wave-level primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ float bcast(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ double bcast(double v, int lane)
+{
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int bcast(int v, int lane)
+{
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        T o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Soft_lambda(a) = sign(a) (|a| - lambda)_+ ; 0 at |a| == lambda.
+template <typename T>
+__device__ __forceinline__ T soft_threshold(T a, T lam)
+{
+    return a > lam ? a - lam : (a < -lam ? a + lam : T(0));
+}
+
+// ---------------------------------------------------------------------------
+// launcher declarations (definitions live in the .hip files)
+// ---------------------------------------------------------------------------
+
+// Standardisation.  X: n x p row-major (ld = ldx).  partial: workspace of
+// 2 * rchunks * p doubles.  flags[0] |= 1 on a non-finite value, |= 2 on a
+// zero-variance column.
+void launch_colstats(const double *X, int64_t n, int64_t p, int64_t ldx, double *partial,
+                     int rchunks, double *mean, double *scale, int *flags, hipStream_t s);
+int colstats_rchunks(int64_t n, int64_t p);
+
+// Xs = (X - mean) * scale, n x p row-major (ld p), double.
+void launch_standardize_f64(const double *X, int64_t n, int64_t p, int64_t ldx,
+                            const double *mean, const double *scale, double *Xs, hipStream_t s);
+// float copy of the standardised data, n x p row-major.
+void launch_standardize_f32(const double *X, int64_t n, int64_t p, int64_t ldx,
+                            const double *mean, const double *scale, float *Xs, hipStream_t s);
+// Transposed standardised data for the mixed form: Xt (p x n double) and
+// the two-term bfloat16 split hi/lo of float(x), p x npad (npad = n padded
+// to a multiple of 32, zero-filled).
+void launch_standardize_split(const double *X, int64_t n, int64_t p, int64_t ldx,
+                              const double *mean, const double *scale, double *Xt,
+                              uint16_t *hi, uint16_t *lo, int64_t npad, hipStream_t s);
+
+// S = Xs^T Xs / n with unit diagonal (p x p row-major, full).
+void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, hipStream_t s);
+void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, hipStream_t s);
+void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
+                        int64_t p, float *S, hipStream_t s);
+
+// Per-column working-set scaled lasso (see colsolve.hip).
+template <typename T>
+struct ColArgs {
+    const T *S;          // p x p row-major, symmetric, unit diagonal
+    int64_t p;
+    T lambda0;
+    T tol;               // delta: inner stop on max |change|, outer on |d sigma|
+    T kkt_tol;           // a variable outside the working set violates when |g| > lambda + kkt_tol
+    T band;              // record j outside W with |g| > lambda - band (0: off)
+    int max_outer, max_sweeps, max_rounds;
+    int *w_cnt;          // [p]
+    int *w_idx;          // [p * kWMax], sorted
+    T *w_beta;           // [p * kWMax]
+    double *sigma;       // [p]
+    double *lam_used;    // [p] lambda the stored coefficients solve
+    int *col_status;     // [p]
+    int *band_cnt;       // [p] or null
+    int *band_idx;       // [p * kBandMax] or null
+    int *esc_cnt;        // escalation queue (tier 1 -> tier 2)
+    int *esc_list;       // [p]
+    int resume;          // tier 2: process esc_list[0 .. *esc_cnt) from stored state
+    unsigned long long *counters;
+    int *status_bits;    // |= 1 no convergence, 2 degenerate, 4 working set overflow
+    const int *flags;    // nonzero: bad input, every wave exits at once
+};
+template <typename T>
+void launch_colsolve(const ColArgs<T> &a, hipStream_t s);
+
+// Double-precision polish of the float solution (mixed form).
+struct PolishArgs {
+    const double *Xt;       // p x n standardised data (double)
+    const float *S32;       // p x p float covariance (for full KKT passes)
+    int64_t n, p;
+    double lambda0, tol;
+    int max_outer, max_sweeps, max_rounds;
+    float band;             // band the float solve recorded
+    const int *w_cnt32;     // float solution
+    const int *w_idx32;
+    const float *w_beta32;
+    const double *sigma32;
+    const double *lam32;
+    const int *band_cnt;
+    const int *band_idx;
+    const int *col_status32;
+    double eps;             // bound on |g32 - g64| per unit of (1 + ||beta||_1)
+    int *esc_cnt;           // escalation queue (32 -> 128 working set)
+    int *esc_list;
+    int *w_cnt;             // double solution (output)
+    int *w_idx;
+    double *w_beta;
+    double *sigma;
+    double *lam_used;
+    int *col_status;
+    unsigned long long *counters;
+    int *status_bits;
+    const int *flags;
+};
+void launch_polish(const PolishArgs &a, hipStream_t s);
+
+// Zero n 32-bit words (a kernel, so it is safe inside captured graphs).
+void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s);
+
+// Outputs.
+void launch_fill_zero(double *A, int64_t count, hipStream_t s);
+template <typename T>
+void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta,
+                            const double *sigma, const double *scale, int original_scale,
+                            double *B, double *sig_out, double *Omega, hipStream_t s);
+void launch_symmetrize_dense(int64_t p, const double *Om1, double *Om, hipStream_t s);
+
+} // namespace spmesl

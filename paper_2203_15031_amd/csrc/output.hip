@@ -1,0 +1,164 @@
+// output.hip -- B, sigma and the symmetrised Omega from the per-column
+// coefficient lists.
+//
+// Omega_1 = -B D with D = diag(sigma^-2) (Eq. (eq:relation)), then the
+// min-magnitude symmetrisation of Eq. (eq:symm): for j < k both entries
+// become the one of smaller magnitude, the upper entry omega_jk on a tie.
+// Because an entry of Omega_1 is zero wherever the coefficient is, the
+// symmetrised off-diagonal entry is nonzero only where both beta_jk and
+// beta_kj are, so the dense outputs are a zero fill (the HBM-bound part) and
+// a scatter of the few nonzeros.  Proposition 1 maps back to the data's
+// scale: b^o_jk = (c_j / c_k) b_jk, sigma^o_k = sigma_k / c_k,
+// omega^o_jk = c_j c_k omega_jk.
+#include "common.hpp"
+
+namespace spmesl {
+
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t *__restrict__ a, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0u;
+}
+
+void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, s, a, n);
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ A, int64_t count)
+{
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    int64_t nvec = count / 2;
+    dv2 *A2 = reinterpret_cast<dv2 *>(A);
+    const dv2 z = {0.0, 0.0};
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
+        __builtin_nontemporal_store(z, &A2[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (count & 1)) A[count - 1] = 0.0;
+}
+
+void launch_fill_zero(double *A, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    if (((uintptr_t)A & 15u) != 0) {
+        // caller's array is only 8-byte aligned: clear one element, then the
+        // rest is 16-byte aligned
+        launch_zero_words((uint32_t *)A, 2, s);
+        ++A;
+        --count;
+        if (count <= 0) return;
+    }
+    int64_t nvec = count / 2;
+    int64_t blocks = (nvec + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, A, count);
+}
+
+// one wave per column k; lanes walk the column's list
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(int64_t p, const int *__restrict__ w_cnt,
+                                                 const int *__restrict__ w_idx,
+                                                 const T *__restrict__ w_beta,
+                                                 const double *__restrict__ sigma,
+                                                 const double *__restrict__ scale, int original,
+                                                 double *__restrict__ B,
+                                                 double *__restrict__ sig_out,
+                                                 double *__restrict__ Om)
+{
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= p) return;
+    const int wk = w_cnt[k];
+    const double sk = sigma[k];
+    const double ck = original ? scale[k] : 1.0;
+    const double dk = 1.0 / (sk * sk);
+    for (int q = lane; q < wk; q += kWave) {
+        const int j = w_idx[k * kWMax + q];
+        const double b = (double)w_beta[k * kWMax + q];
+        if (b == 0.0) continue;
+        const double cj = original ? scale[j] : 1.0;
+        if (B) B[(int64_t)j * p + k] = b * (cj / ck);
+        if (Om && j < k) {
+            // the pair (j, k) belongs to its larger index k
+            const int *lj = w_idx + (int64_t)j * kWMax;
+            int lo = 0, hi = w_cnt[j];
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (lj[mid] < (int)k) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < w_cnt[j] && lj[lo] == (int)k) {
+                const double bkj = (double)w_beta[(int64_t)j * kWMax + lo];
+                if (bkj != 0.0) {
+                    const double sj = sigma[j];
+                    const double ojk = -b * dk;               // omega_jk,1 (column k)
+                    const double okj = -bkj / (sj * sj);      // omega_kj,1 (column j)
+                    double v = fabs(ojk) <= fabs(okj) ? ojk : okj;
+                    v *= cj * ck;
+                    Om[(int64_t)j * p + k] = v;
+                    Om[k * p + j] = v;
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        if (Om) Om[k * p + k] = dk * ck * ck;
+        if (sig_out) sig_out[k] = sk / ck;
+    }
+}
+
+template <typename T>
+void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta,
+                            const double *sigma, const double *scale, int original_scale,
+                            double *B, double *sig_out, double *Omega, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((p + 3) / 4)), dim3(256), 0, s, p, w_cnt,
+                       w_idx, w_beta, sigma, scale, original_scale, B, sig_out, Omega);
+}
+
+template void launch_scatter_outputs<double>(int64_t, const int *, const int *, const double *,
+                                             const double *, const double *, int, double *,
+                                             double *, double *, hipStream_t);
+template void launch_scatter_outputs<float>(int64_t, const int *, const int *, const float *,
+                                            const double *, const double *, int, double *,
+                                            double *, double *, hipStream_t);
+
+// Dense symmetrisation of a given Omega_1 (32 x 32 tiles; the partner tile
+// is read transposed through LDS so both reads are coalesced).
+__global__ __launch_bounds__(256) void k_symmetrize_dense(int64_t p, const double *__restrict__ M,
+                                                          double *__restrict__ O)
+{
+    __shared__ double tr[32][33];
+    const int64_t tj = blockIdx.y, tk = blockIdx.x;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // partner tile (tk, tj), stored transposed: tr[c][r] = M[tk*32 + r][tj*32 + c]
+    for (int r = ty; r < 32; r += 8) {
+        int64_t row = tk * 32 + r, col = tj * 32 + tx;
+        tr[tx][r] = (row < p && col < p) ? M[row * p + col] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        int64_t j = tj * 32 + r, k = tk * 32 + tx;
+        if (j >= p || k >= p) continue;
+        double a = M[j * p + k];   // omega_jk,1
+        double b = tr[r][tx];      // omega_kj,1
+        double v;
+        if (j < k) v = fabs(a) <= fabs(b) ? a : b;
+        else if (j > k) v = fabs(b) <= fabs(a) ? b : a;
+        else v = a;
+        O[j * p + k] = v;
+    }
+}
+
+void launch_symmetrize_dense(int64_t p, const double *Om1, double *Om, hipStream_t s)
+{
+    unsigned t = (unsigned)((p + 31) / 32);
+    hipLaunchKernelGGL(k_symmetrize_dense, dim3(t, t), dim3(256), 0, s, p, Om1, Om);
+}
+
+} // namespace spmesl

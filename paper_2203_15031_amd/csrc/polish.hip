@@ -1,0 +1,271 @@
+// polish.hip -- double-precision finish of the mixed-precision solve.
+//
+// The float solve (covariance from a bfloat16 split, float coordinate
+// descent) stops at a float-reachable tolerance.  For each column the polish
+// re-solves the scaled lasso of Eq. (eq:spmesl) in double on a small working
+// set W' = (float support) U (float near-threshold band), with S restricted
+// to W' formed in double directly from the standardised data, to the
+// caller's tolerance.  It then proves that no coordinate outside W' violates
+// the lasso KKT conditions in double:
+//   for j outside the band, |g32_j| <= lambda32 - band was observed, and
+//   |g64_j(beta64) - g32_j(beta32)| <= ||beta64 - beta32||_1
+//                                     + (eps_S + eps_f)(1 + ||beta32||_1),
+//   (|S_jl| <= 1 for a correlation matrix), so if that bound plus
+//   max(0, lambda32 - lambda64) stays below the band no j outside W' can
+//   violate.  Otherwise a full pass over the float S with the double
+//   coefficients flags every j within the error margin of lambda64, adds
+//   them to W' (where the double solve decides them exactly), and repeats.
+#include "colsolve_dev.hpp"
+
+namespace spmesl {
+
+// S_W'W' (LDS) and s_W' (registers) in double from Xt (p x n, standardised).
+template <int LW>
+__device__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t k,
+                                    WaveSm<double, LW> &sm, ColState<double, LW> &st)
+{
+    constexpr int NS = ColState<double, LW>::NS;
+    const int lane = lane_id();
+    const int w = st.w;
+    const int ntri = w * (w - 1) / 2;
+    const int P = ntri + w;
+    const double invn = 1.0 / (double)n;
+    const double *xk = Xt + k * n;
+    for (int t0 = 0; t0 < P; t0 += 4) {
+        const double *ra[4], *rb[4];
+        int qa[4], qb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int t = t0 + u;
+            qa[u] = -1;
+            qb[u] = -1;
+            ra[u] = xk;
+            rb[u] = xk;
+            if (t < ntri) {
+                // t = qj (qj - 1) / 2 + qi, qi < qj
+                int qj = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+                while (qj * (qj - 1) / 2 > t) --qj;
+                while ((qj + 1) * qj / 2 <= t) ++qj;
+                int qi = t - qj * (qj - 1) / 2;
+                qa[u] = qi;
+                qb[u] = qj;
+                ra[u] = Xt + (int64_t)sm.widx[qi] * n;
+                rb[u] = Xt + (int64_t)sm.widx[qj] * n;
+            } else if (t < P) {
+                qa[u] = t - ntri;
+                ra[u] = Xt + (int64_t)sm.widx[t - ntri] * n;
+            }
+        }
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t i = lane; i < n; i += kWave) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += ra[u][i] * rb[u][i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double v = wave_sum(acc[u]) * invn;
+            if (lane == 0 && qa[u] >= 0) {
+                if (qb[u] >= 0) {
+                    sm.sww[qb[u] * LW + qa[u]] = v;
+                    sm.sww[qa[u] * LW + qb[u]] = v;
+                } else {
+                    sm.tbeta[qa[u]] = v;  // s_W' entry, staged
+                }
+            }
+        }
+    }
+    for (int q = lane; q < w; q += kWave) sm.sww[q * LW + q] = 1.0;
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int q = s * kWave + lane;
+        st.sv[s] = q < w ? sm.tbeta[q] : 0.0;
+        st.b[s] = q < w ? sm.wbeta[q] : 0.0;
+        st.g[s] = 0.0;
+    }
+    wave_sync();
+}
+
+// beta32 of variable j in column k's float list (0 if absent)
+__device__ __forceinline__ double beta32_of(const PolishArgs &A, int64_t k, int j)
+{
+    const int *idx = A.w_idx32 + k * kWMax;
+    int lo = 0, hi = A.w_cnt32[k];
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (idx[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < A.w_cnt32[k] && idx[lo] == j) ? (double)A.w_beta32[k * kWMax + lo] : 0.0;
+}
+
+template <int LW, int NW>
+__global__ __launch_bounds__(kWave *NW) void k_polish(PolishArgs A, int tier2)
+{
+    constexpr int NS = ColState<double, LW>::NS;
+    __shared__ WaveSm<double, LW> smem[NW];
+    const int wv = threadIdx.x / kWave;
+    const int lane = lane_id();
+    WaveSm<double, LW> &sm = smem[wv];
+    const int64_t gw = (int64_t)blockIdx.x * NW + wv;
+    if (*A.flags) return;
+    int64_t k;
+    if (tier2) {
+        if (gw >= *A.esc_cnt) return;
+        k = A.esc_list[gw];
+    } else {
+        if (gw >= A.p) return;
+        k = gw;
+    }
+    const int64_t p = A.p;
+    ColState<double, LW> st;
+    SolveCounts cnt = {0, 0, 0};
+    int status = kColOk, rounds = 0, checks = 0, added = 0;
+
+    // --- W' = float support U float band --------------------------------
+    const int w32 = A.w_cnt32[k];
+    int nb = A.band_cnt[k];
+    bool full = nb > kBandMax || A.col_status32[k] != kColOk;
+    nb = nb < kBandMax ? nb : kBandMax;
+    double norm32 = 0.0;
+    int ns = 0;
+    for (int q0 = 0; q0 < w32; q0 += kWave) {
+        int q = q0 + lane;
+        float b = q < w32 ? A.w_beta32[k * kWMax + q] : 0.0f;
+        bool nz = b != 0.0f;
+        unsigned long long m = __ballot(nz);
+        int pos = ns + lanes_below(m);
+        if (nz && pos < LW) {
+            sm.widx[pos] = A.w_idx32[k * kWMax + q];
+            sm.wbeta[pos] = (double)b;
+        }
+        norm32 += nz ? fabs((double)b) : 0.0;
+        ns += __popcll(m);
+    }
+    norm32 = wave_sum(norm32);
+    for (int i = lane; i < nb; i += kWave) sm.pend[i] = A.band_idx[k * kBandMax + i];
+    wave_sync();
+    if (ns + nb > LW) {
+        if (!tier2) {
+            if (lane == 0) {
+                int pos = atomicAdd(A.esc_cnt, 1);
+                A.esc_list[pos] = (int)k;
+            }
+            return;
+        }
+        status = kColWorkset;
+        nb = ns < LW ? (LW - ns < nb ? LW - ns : nb) : 0;
+        ns = ns < LW ? ns : LW;
+    }
+    st.w = ns;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int q = s * kWave + lane;
+        st.b[s] = q < ns ? sm.wbeta[q] : 0.0;
+    }
+    wave_sync();
+    merge_pending(sm, st, nb);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int q = s * kWave + lane;
+        st.b[s] = q < st.w ? sm.wbeta[q] : 0.0;
+    }
+    st.sigma = A.sigma32[k];
+    st.lam_used = A.lam32[k];
+    const double lam32 = A.lam32[k];
+
+    while (status == kColOk) {
+        load_working_set_xt(A.Xt, A.n, k, sm, st);
+        status = scaled_lasso_W(sm, st, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+        if (status != kColOk) break;
+        // bound on the change of any gradient outside W'
+        double part = 0.0, nrm = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            int q = s * kWave + lane;
+            if (q < st.w) {
+                part += fabs(st.b[s] - beta32_of(A, k, sm.widx[q]));
+                nrm += fabs(st.b[s]);
+            }
+        }
+        double l1d = wave_sum(part);
+        double norm64 = wave_sum(nrm);
+        double lamdrop = lam32 - st.lam_used;
+        lamdrop = lamdrop > 0.0 ? lamdrop : 0.0;
+        double bound = l1d + A.eps * (1.0 + norm32) + lamdrop;
+        if (!full && bound < (double)A.band) break;
+        // full pass: every j whose float-S gradient is within the error
+        // margin of lambda64 joins W'
+        int nsup = build_support(sm, st);
+        double margin = A.eps * (1.0 + norm64);
+        ++checks;
+        int npend = kkt_pass<float, double, LW>(A.S32, p, k, sm, st.w, nsup, st.lam_used - margin,
+                                               false, 0.0, nullptr, nullptr);
+        if (npend == 0) break;
+        if (rounds >= A.max_rounds) {
+            status = kColNoconv;
+            break;
+        }
+        ++rounds;
+        int np = npend < kPendMax ? npend : kPendMax;
+        if (st.w + np > LW) {
+            if (!tier2) {
+                if (lane == 0) {
+                    int pos = atomicAdd(A.esc_cnt, 1);
+                    A.esc_list[pos] = (int)k;
+                }
+                return;
+            }
+            np = LW - st.w;
+            if (np <= 0) {
+                status = kColWorkset;
+                break;
+            }
+        }
+        // keep the double coefficients across the merge
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            int q = s * kWave + lane;
+            if (q < st.w) sm.wbeta[q] = st.b[s];
+        }
+        wave_sync();
+        merge_pending(sm, st, np);
+        added += np;
+        full = true;
+    }
+    // store the double lists
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int q = s * kWave + lane;
+        if (q < st.w) {
+            A.w_idx[k * kWMax + q] = sm.widx[q];
+            A.w_beta[k * kWMax + q] = st.b[s];
+        }
+    }
+    if (lane == 0) {
+        A.w_cnt[k] = st.w;
+        A.sigma[k] = st.sigma;
+        A.lam_used[k] = st.lam_used;
+        A.col_status[k] = status;
+        atomicAdd(&A.counters[kCntPolishChecks], (unsigned long long)checks);
+        atomicAdd(&A.counters[kCntPolishAdded], (unsigned long long)added);
+        atomicAdd(&A.counters[kCntOuter], (unsigned long long)cnt.outer);
+        atomicAdd(&A.counters[kCntSweeps], (unsigned long long)cnt.sweeps);
+        atomicAdd(&A.counters[kCntUpdates], (unsigned long long)cnt.updates);
+        atomicMax(&A.counters[kCntMaxW], (unsigned long long)st.w);
+        if (status != kColOk) {
+            atomicAdd(&A.counters[kCntNoconv], 1ull);
+            atomicOr(A.status_bits, status == kColWorkset ? 4 : (status == kColDegenerate ? 2 : 1));
+        }
+    }
+}
+
+void launch_polish(const PolishArgs &a, hipStream_t s)
+{
+    constexpr int NW = 4;
+    hipLaunchKernelGGL((k_polish<32, NW>), dim3((unsigned)((a.p + NW - 1) / NW)),
+                       dim3(kWave * NW), 0, s, a, 0);
+    hipLaunchKernelGGL((k_polish<kWMax, 1>), dim3((unsigned)a.p), dim3(kWave), 0, s, a, 1);
+}
+
+} // namespace spmesl

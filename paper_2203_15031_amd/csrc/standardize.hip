@@ -1,0 +1,178 @@
+// standardize.hip -- centring and scaling of the data matrix.
+//
+// Section 2.2 of the paper assumes columns centred and scaled so that
+// x_k^T x_k = n (s_kk = 1).  These kernels compute the column means and the
+// scales c_k = (sum_i (x_ik - mean_k)^2 / n)^{-1/2} (the C of Proposition 1)
+// and write the standardised data in the layout the covariance kernel of each
+// precision reads.  All are single HBM passes over X.
+#include "common.hpp"
+
+namespace spmesl {
+
+// Column sums about a shift (the column's first entry, which keeps the
+// one-pass variance accurate): partial[(2r) * p + j] = sum (x - K_j),
+// partial[(2r+1) * p + j] = sum (x - K_j)^2 over row chunk r.
+__global__ __launch_bounds__(256) void k_colstats_partial(const double *__restrict__ X,
+                                                          int64_t n, int64_t p, int64_t ldx,
+                                                          int64_t rows_per,
+                                                          double *__restrict__ partial)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int r = blockIdx.y;
+    if (j >= p) return;
+    double K = X[j];
+    int64_t i0 = (int64_t)r * rows_per;
+    int64_t i1 = i0 + rows_per < n ? i0 + rows_per : n;
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        double d = X[i * ldx + j] - K;
+        s1 += d;
+        s2 += d * d;
+    }
+    partial[(2 * (int64_t)r) * p + j] = s1;
+    partial[(2 * (int64_t)r + 1) * p + j] = s2;
+}
+
+// Combine the chunks in a fixed order; mean_j = K + s1/n,
+// var_j = (s2 - s1^2/n)/n, scale_j = var_j^{-1/2}.
+__global__ __launch_bounds__(256) void k_colstats_final(const double *__restrict__ X, int64_t n,
+                                                        int64_t p, int rchunks,
+                                                        const double *__restrict__ partial,
+                                                        double *__restrict__ mean,
+                                                        double *__restrict__ scale,
+                                                        int *__restrict__ flags)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int r = 0; r < rchunks; ++r) {
+        s1 += partial[(2 * (int64_t)r) * p + j];
+        s2 += partial[(2 * (int64_t)r + 1) * p + j];
+    }
+    double K = X[j];
+    double nn = (double)n;
+    if (!isfinite(s1) || !isfinite(s2) || !isfinite(K)) {
+        atomicOr(flags, 1);
+        mean[j] = 0.0;
+        scale[j] = 1.0;
+        return;
+    }
+    double ss = s2 - s1 * s1 / nn;
+    if (!(ss > 0.0)) {
+        atomicOr(flags, 2);
+        mean[j] = K;
+        scale[j] = 1.0;
+        return;
+    }
+    mean[j] = K + s1 / nn;
+    scale[j] = 1.0 / sqrt(ss / nn);
+}
+
+int colstats_rchunks(int64_t n, int64_t p)
+{
+    // enough blocks to cover the machine, each thread summing >= 8 rows
+    int64_t colblocks = (p + 255) / 256;
+    int64_t want = (2048 + colblocks - 1) / colblocks;
+    int64_t maxr = (n + 7) / 8;
+    int64_t r = want < maxr ? want : maxr;
+    if (r < 1) r = 1;
+    if (r > 256) r = 256;
+    return (int)r;
+}
+
+void launch_colstats(const double *X, int64_t n, int64_t p, int64_t ldx, double *partial,
+                     int rchunks, double *mean, double *scale, int *flags, hipStream_t s)
+{
+    int64_t rows_per = (n + rchunks - 1) / rchunks;
+    dim3 g((unsigned)((p + 255) / 256), (unsigned)rchunks);
+    hipLaunchKernelGGL(k_colstats_partial, g, dim3(256), 0, s, X, n, p, ldx, rows_per, partial);
+    hipLaunchKernelGGL(k_colstats_final, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, s, X, n,
+                       p, rchunks, partial, mean, scale, flags);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_standardize(const double *__restrict__ X, int64_t n,
+                                                     int64_t p, int64_t ldx,
+                                                     const double *__restrict__ mean,
+                                                     const double *__restrict__ scale,
+                                                     T *__restrict__ Xs)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = blockIdx.y;
+    if (j >= p) return;
+    for (; i < n; i += gridDim.y) Xs[i * p + j] = (T)((X[i * ldx + j] - mean[j]) * scale[j]);
+}
+
+void launch_standardize_f64(const double *X, int64_t n, int64_t p, int64_t ldx,
+                            const double *mean, const double *scale, double *Xs, hipStream_t s)
+{
+    unsigned gy = (unsigned)(n < 1024 ? n : 1024);
+    hipLaunchKernelGGL(k_standardize<double>, dim3((unsigned)((p + 255) / 256), gy), dim3(256), 0,
+                       s, X, n, p, ldx, mean, scale, Xs);
+}
+
+void launch_standardize_f32(const double *X, int64_t n, int64_t p, int64_t ldx,
+                            const double *mean, const double *scale, float *Xs, hipStream_t s)
+{
+    unsigned gy = (unsigned)(n < 1024 ? n : 1024);
+    hipLaunchKernelGGL(k_standardize<float>, dim3((unsigned)((p + 255) / 256), gy), dim3(256), 0,
+                       s, X, n, p, ldx, mean, scale, Xs);
+}
+
+// round-to-nearest-even float -> bfloat16 bits (finite inputs)
+__device__ __forceinline__ uint16_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Transposing standardisation for the mixed form.  Block: 64 (j) x 4 (i
+// lanes); tile 64 samples x 64 variables staged through LDS so that both
+// the read of X (rows) and the writes of Xt/hi/lo (variable-major) are
+// coalesced.
+__global__ __launch_bounds__(256) void k_standardize_split(
+    const double *__restrict__ X, int64_t n, int64_t p, int64_t ldx,
+    const double *__restrict__ mean, const double *__restrict__ scale, double *__restrict__ Xt,
+    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int64_t npad)
+{
+    __shared__ double tile[64][65];
+    int64_t i0 = (int64_t)blockIdx.x * 64;
+    int64_t j0 = (int64_t)blockIdx.y * 64;
+    int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    int64_t j = j0 + tx;
+    double m = j < p ? mean[j] : 0.0, c = j < p ? scale[j] : 0.0;
+    for (int r = ty; r < 64; r += 4) {
+        int64_t i = i0 + r;
+        tile[r][tx] = (i < n && j < p) ? (X[i * ldx + j] - m) * c : 0.0;
+    }
+    __syncthreads();
+    // write: thread tx walks samples, ty walks variables
+    for (int v = ty; v < 64; v += 4) {
+        int64_t jj = j0 + v;
+        int64_t ii = i0 + tx;
+        if (jj >= p) continue;
+        double x = tile[tx][v];
+        if (ii < n) Xt[jj * n + ii] = x;
+        if (ii < npad) {
+            float f = (float)x;
+            uint16_t h = bf16_bits(f);
+            uint16_t l = bf16_bits(f - bf16_value(h));
+            hi[jj * npad + ii] = ii < n ? h : (uint16_t)0;
+            lo[jj * npad + ii] = ii < n ? l : (uint16_t)0;
+        }
+    }
+}
+
+void launch_standardize_split(const double *X, int64_t n, int64_t p, int64_t ldx,
+                              const double *mean, const double *scale, double *Xt,
+                              uint16_t *hi, uint16_t *lo, int64_t npad, hipStream_t s)
+{
+    dim3 g((unsigned)((npad + 63) / 64), (unsigned)((p + 63) / 64));
+    hipLaunchKernelGGL(k_standardize_split, g, dim3(256), 0, s, X, n, p, ldx, mean, scale, Xt,
+                       hi, lo, npad);
+}
+
+} // namespace spmesl

@@ -1,0 +1,257 @@
+// syrk.hip -- the sample covariance S = Xs^T Xs / n on the matrix cores.
+//
+// S is the only dense contraction of the method (n p^2 multiply-adds).  Only
+// the upper triangle of 64x64 (or 128x128) tiles is computed; each tile is
+// written twice, once as is and once transposed, so S is stored full and
+// every row of S is a contiguous read for the solver.  The diagonal is set
+// to exactly 1 (s_jj = 1 for standardised columns, Section 2.2), which the
+// coordinate update relies on.
+//
+// Three forms:
+//   * double: v_mfma_f64_16x16x4f64, Xs row-major n x p;
+//   * float : v_mfma_f32_16x16x4f32, same layout;
+//   * mixed : two-term bfloat16 split x = hi + lo of float(x), products
+//             hi*hi + hi*lo + lo*hi accumulated in float by
+//             v_mfma_f32_16x16x32_bf16 from variable-major hi/lo panels.
+//
+// Operand layout of the 16x16xK MFMAs used here (wave64): lane l supplies
+// row l%16 of A and column l%16 of B, at k-block l/16; accumulator element r
+// of lane l is D[4*(l/16) + r][l%16].
+#include "common.hpp"
+
+namespace spmesl {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4 type; };
+template <> struct Acc<float> { typedef f4 type; };
+
+// Map a linear block id to an upper-triangle tile (bj <= bk), with blocks
+// that share a row panel kept on the same XCD (blocks are dispatched to
+// the 8 XCDs round-robin).
+__device__ __forceinline__ void tile_of_block(int T, int *bj, int *bk)
+{
+    int nb = gridDim.x, bid = blockIdx.x;
+    int x = bid & 7, q = nb >> 3, r = nb & 7;
+    int t = x * q + (x < r ? x : r) + (bid >> 3);
+    int row = 0;
+    while (t >= T - row) {
+        t -= T - row;
+        ++row;
+    }
+    *bj = row;
+    *bk = row + t;
+}
+
+constexpr int kSyrkKC = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int64_t n, int64_t p,
+                                                   T *__restrict__ S, int Tt, T invn)
+{
+    typedef typename Acc<T>::type AccT;
+    __shared__ union {
+        struct {
+            T a[kSyrkKC][64];
+            T b[kSyrkKC][64];
+        } in;
+        T out[64][65];
+    } sm;
+    int bj, bk;
+    tile_of_block(Tt, &bj, &bk);
+    const int64_t j0 = (int64_t)bj * 64, k0 = (int64_t)bk * 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    AccT acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+
+    // loader mapping: 16 rows x 64 columns, 4 consecutive columns per thread
+    const int lr = tid >> 4, lc = (tid & 15) * 4;
+    for (int64_t i0 = 0; i0 < n; i0 += kSyrkKC) {
+        int64_t i = i0 + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int64_t ja = j0 + lc + e, kb = k0 + lc + e;
+            sm.in.a[lr][lc + e] = (i < n && ja < p) ? Xs[i * p + ja] : T(0);
+            sm.in.b[lr][lc + e] = (i < n && kb < p) ? Xs[i * p + kb] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kSyrkKC; kk += 4) {
+            T av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = sm.in.a[kk + (lane >> 4)][32 * wm + 16 * a + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = sm.in.b[kk + (lane >> 4)][32 * wn + 16 * b + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+    // stage the tile (scaled by 1/n) for coalesced direct and mirrored writes
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sm.out[32 * wm + 16 * a + 4 * (lane >> 4) + r][32 * wn + 16 * b + (lane & 15)] =
+                    acc[a][b][r] * invn;
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+        int rr = e >> 6, cc = e & 63;
+        int64_t j = j0 + rr, k = k0 + cc;
+        if (j < p && k < p) S[j * p + k] = (j == k) ? T(1) : sm.out[rr][cc];
+    }
+    if (bj != bk) {
+        for (int e = tid; e < 64 * 64; e += 256) {
+            int rr = e >> 6, cc = e & 63;  // row of the mirrored tile = k index
+            int64_t k = k0 + rr, j = j0 + cc;
+            if (j < p && k < p) S[k * p + j] = sm.out[cc][rr];
+        }
+    }
+}
+
+template <typename T>
+static void launch_syrk_t(const T *Xs, int64_t n, int64_t p, T *S, hipStream_t s)
+{
+    int Tt = (int)((p + 63) / 64);
+    int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
+    hipLaunchKernelGGL(k_syrk_mfma<T>, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
+                       (T)(1.0 / (double)n));
+}
+
+void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, hipStream_t s)
+{
+    launch_syrk_t<double>(Xs, n, p, S, s);
+}
+void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, hipStream_t s)
+{
+    launch_syrk_t<float>(Xs, n, p, S, s);
+}
+
+// ---------------------------------------------------------------------------
+// mixed form: bf16 split, 128 x 128 tiles, 64 samples per stage
+// ---------------------------------------------------------------------------
+constexpr int kBfKC = 64;            // samples per LDS stage
+constexpr int kBfLd = kBfKC + 8;     // padded row (bf16 elements)
+
+__global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict__ hi,
+                                                     const uint16_t *__restrict__ lo,
+                                                     int64_t npad, int64_t p,
+                                                     float *__restrict__ S, int Tt, float invn)
+{
+    __shared__ union {
+        uint16_t in[4][128 * kBfLd];  // hi_J, lo_J, hi_K, lo_K ; [var][sample]
+        float out[128][129];
+    } sm;
+    int bj, bk;
+    tile_of_block(Tt, &bj, &bk);
+    const int64_t j0 = (int64_t)bj * 128, k0 = (int64_t)bk * 128;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+    // loader: 128 vars x 64 samples per panel; thread -> (var = tid/2, half)
+    const int lv = tid >> 1, lh = (tid & 1) * 32;
+    for (int64_t i0 = 0; i0 < npad; i0 += kBfKC) {
+#pragma unroll
+        for (int pnl = 0; pnl < 4; ++pnl) {
+            const uint16_t *src = (pnl & 1) ? lo : hi;
+            int64_t v = ((pnl < 2) ? j0 : k0) + lv;
+            uint4 q0 = {0, 0, 0, 0}, q1 = q0, q2 = q0, q3 = q0;
+            if (v < p) {
+                const uint4 *g = reinterpret_cast<const uint4 *>(src + v * npad + i0 + lh);
+                q0 = g[0];
+                q1 = g[1];
+                q2 = g[2];
+                q3 = g[3];
+            }
+            uint4 *d = reinterpret_cast<uint4 *>(&sm.in[pnl][lv * kBfLd + lh]);
+            d[0] = q0;
+            d[1] = q1;
+            d[2] = q2;
+            d[3] = q3;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBfKC; kk += 32) {
+            bf8 ha[4], la[4], hb[4], lb[4];
+            const int ko = kk + 8 * (lane >> 4);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                int r = 64 * wm + 16 * a + (lane & 15);
+                ha[a] = *reinterpret_cast<const bf8 *>(&sm.in[0][r * kBfLd + ko]);
+                la[a] = *reinterpret_cast<const bf8 *>(&sm.in[1][r * kBfLd + ko]);
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                int c = 64 * wn + 16 * b + (lane & 15);
+                hb[b] = *reinterpret_cast<const bf8 *>(&sm.in[2][c * kBfLd + ko]);
+                lb[b] = *reinterpret_cast<const bf8 *>(&sm.in[3][c * kBfLd + ko]);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sm.out[64 * wm + 16 * a + 4 * (lane >> 4) + r][64 * wn + 16 * b + (lane & 15)] =
+                    acc[a][b][r] * invn;
+    __syncthreads();
+    for (int e = tid; e < 128 * 128; e += 256) {
+        int rr = e >> 7, cc = e & 127;
+        int64_t j = j0 + rr, k = k0 + cc;
+        if (j < p && k < p) S[j * p + k] = (j == k) ? 1.0f : sm.out[rr][cc];
+    }
+    if (bj != bk) {
+        for (int e = tid; e < 128 * 128; e += 256) {
+            int rr = e >> 7, cc = e & 127;
+            int64_t k = k0 + rr, j = j0 + cc;
+            if (j < p && k < p) S[k * p + j] = sm.out[cc][rr];
+        }
+    }
+}
+
+void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
+                        int64_t p, float *S, hipStream_t s)
+{
+    int Tt = (int)((p + 127) / 128);
+    int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
+    hipLaunchKernelGGL(k_syrk_bf16x3, dim3((unsigned)ntiles), dim3(256), 0, s, hi, lo, npad, p, S,
+                       Tt, (float)(1.0 / (double)n));
+}
+
+} // namespace spmesl

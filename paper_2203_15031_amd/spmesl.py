@@ -1,0 +1,347 @@
+"""Python binding of libspmesl.so (the C ABI in include/spmesl.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory (inputs, outputs, workspace) and the
+current HIP stream.  There is no fallback path: if the library is not built
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmesl.so")
+
+OK = 0
+EINVAL = -1
+ENONFINITE = -2
+EZEROVAR = -3
+EDEGENERATE = -4
+ENOCONV = -5
+EHIP = -6
+ENOMEM = -7
+EWORKSET = -8
+
+FP64, FP32, MIXED = 0, 1, 2
+SCALE_ORIGINAL, SCALE_STANDARDIZED = 0, 1
+FLAG_TIMING = 1
+MAX_WORKING_SET = 128
+
+_PRECISION = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+_SCALE = {"original": SCALE_ORIGINAL, "standardized": SCALE_STANDARDIZED}
+_NAMES = {OK: "OK", EINVAL: "EINVAL", ENONFINITE: "ENONFINITE", EZEROVAR: "EZEROVAR",
+          EDEGENERATE: "EDEGENERATE", ENOCONV: "ENOCONV", EHIP: "EHIP", ENOMEM: "ENOMEM",
+          EWORKSET: "EWORKSET"}
+
+
+class SpmeslError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("n", C.c_int64), ("p", C.c_int64), ("ldx", C.c_int64)]
+
+
+class Options(C.Structure):
+    _fields_ = [("lambda0", C.c_double), ("tol", C.c_double), ("max_outer", C.c_int32),
+                ("max_sweeps", C.c_int32), ("max_rounds", C.c_int32), ("precision", C.c_int32),
+                ("output_scale", C.c_int32), ("flags", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in (
+        "columns", "total_outer", "max_outer", "total_sweeps", "total_updates", "total_rounds",
+        "max_working_set", "nnz_B", "columns_noconv", "polish_kkt_checks", "polish_added")] + \
+        [(f, C.c_double) for f in (
+            "ms_standardize", "ms_covariance", "ms_solve", "ms_polish", "ms_output", "ms_total")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Result(C.Structure):
+    _fields_ = [("B", C.c_void_p), ("sigma", C.c_void_p), ("Omega", C.c_void_p),
+                ("stats", C.POINTER(Stats))]
+
+
+_lib = None
+
+
+def load():
+    """Load libspmesl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2203_15031_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64 = C.c_void_p, C.c_int64
+    lib.spmesl_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    lib.spmesl_create.restype = C.c_int
+    lib.spmesl_destroy.argtypes = [vp]
+    lib.spmesl_destroy.restype = None
+    lib.spmesl_set_stream.argtypes = [vp, vp]
+    lib.spmesl_set_stream.restype = C.c_int
+    lib.spmesl_last_error.argtypes = [vp]
+    lib.spmesl_last_error.restype = C.c_char_p
+    lib.spmesl_version.argtypes = []
+    lib.spmesl_version.restype = C.c_char_p
+    lib.spmesl_workspace_size.argtypes = [C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_size_t)]
+    lib.spmesl_workspace_size.restype = C.c_int
+    lib.spmesl_set_workspace.argtypes = [vp, vp, C.c_size_t]
+    lib.spmesl_set_workspace.restype = C.c_int
+    lib.spmesl_solve.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result)]
+    lib.spmesl_solve.restype = C.c_int
+    lib.spmesl_solve_batch.argtypes = [vp, C.c_int, C.POINTER(Problem), C.POINTER(Options),
+                                       C.POINTER(Result), C.POINTER(C.c_int)]
+    lib.spmesl_solve_batch.restype = C.c_int
+    lib.spmesl_covariance.argtypes = [vp, C.POINTER(Problem), C.c_int, vp, vp, vp]
+    lib.spmesl_covariance.restype = C.c_int
+    lib.spmesl_symmetrize.argtypes = [vp, i64, vp, vp]
+    lib.spmesl_symmetrize.restype = C.c_int
+    for f in ("spmesl_lambda_univ", "spmesl_lambda_ub"):
+        getattr(lib, f).argtypes = [C.c_double, C.c_double]
+        getattr(lib, f).restype = C.c_double
+    lib.spmesl_lambda_pb.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+    lib.spmesl_lambda_pb.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# penalty levels (host)
+# ---------------------------------------------------------------------------
+
+def lambda_univ(n, p):
+    return load().spmesl_lambda_univ(float(n), float(p))
+
+
+def lambda_ub(n, p):
+    return load().spmesl_lambda_ub(float(n), float(p))
+
+
+def lambda_pb(n, p):
+    """Returns (lambda_pb, k)."""
+    lam, k = C.c_double(), C.c_double()
+    st = load().spmesl_lambda_pb(float(n), float(p), C.byref(lam), C.byref(k))
+    if st != OK:
+        raise SpmeslError(st, "lambda_pb")
+    return lam.value, k.value
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _check_X(X):
+    if not isinstance(X, torch.Tensor) or X.dtype != torch.float64 or not X.is_cuda:
+        raise TypeError("X must be a float64 CUDA tensor")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be 2-D with unit column stride (row-major)")
+
+
+@dataclass
+class SolveResult:
+    B: torch.Tensor | None
+    sigma: torch.Tensor | None
+    Omega: torch.Tensor | None
+    status: int
+    stats: dict
+
+
+class Context:
+    """One library context bound to a device; enqueues on torch's current stream."""
+
+    def __init__(self, device: int | None = None):
+        lib = load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+            st = lib.spmesl_create(C.byref(self._h), self.device, C.c_void_p(stream))
+        if st != OK:
+            raise SpmeslError(st, "spmesl_create")
+        self._ws = None
+
+    def close(self):
+        if self._h:
+            load().spmesl_destroy(self._h)
+            self._h = C.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers ------------------------------------------------------------
+    def _err(self):
+        return load().spmesl_last_error(self._h).decode()
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        load().spmesl_set_stream(self._h, C.c_void_p(s))
+
+    def _workspace(self, nbytes: int):
+        """Workspace from torch's allocator, grown on demand."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+            base = self._ws.data_ptr()
+            off = (-base) % 256
+            st = load().spmesl_set_workspace(self._h, C.c_void_p(base + off), nbytes + 256 - off)
+            if st != OK:
+                raise SpmeslError(st, self._err())
+
+    @staticmethod
+    def options(lambda0, tol=1e-8, precision="fp64", output_scale="original", max_outer=0,
+                max_sweeps=0, max_rounds=0, timing=False):
+        return Options(float(lambda0), float(tol), int(max_outer), int(max_sweeps),
+                       int(max_rounds), _PRECISION[precision] if isinstance(precision, str) else int(precision),
+                       _SCALE[output_scale] if isinstance(output_scale, str) else int(output_scale),
+                       FLAG_TIMING if timing else 0)
+
+    @staticmethod
+    def problem(X):
+        _check_X(X)
+        n, p = X.shape
+        return Problem(X.data_ptr(), n, p, X.stride(0))
+
+    def workspace_size(self, X, opt):
+        prob = self.problem(X)
+        sz = C.c_size_t()
+        st = load().spmesl_workspace_size(C.byref(prob), C.byref(opt), C.byref(sz))
+        if st != OK:
+            raise SpmeslError(st, "workspace_size")
+        return sz.value
+
+    # -- entry points -------------------------------------------------------
+    def solve(self, X, lambda0, tol=1e-8, precision="fp64", output_scale="original",
+              want=("B", "sigma", "Omega"), out=None, max_outer=0, max_sweeps=0, max_rounds=0,
+              timing=False, check=True) -> SolveResult:
+        """Full SPMESL of X (n x p float64 CUDA tensor).
+
+        Returns B (p x p, column k = beta of response k), sigma (p) and the
+        symmetrised Omega (p x p).  `out` may hold preallocated output
+        tensors.  Raises SpmeslError on any code other than OK and (when
+        check is False) ENOCONV."""
+        opt = self.options(lambda0, tol, precision, output_scale, max_outer, max_sweeps,
+                           max_rounds, timing)
+        prob = self.problem(X)
+        p = prob.p
+        dev = X.device
+        out = dict(out or {})
+        for name, shape in (("B", (p, p)), ("sigma", (p,)), ("Omega", (p, p))):
+            if name in want and out.get(name) is None:
+                out[name] = torch.empty(shape, dtype=torch.float64, device=dev)
+        for name in ("B", "sigma", "Omega"):
+            if name in out and out[name] is not None:
+                t = out[name]
+                if t.dtype != torch.float64 or not t.is_contiguous() or t.device != dev:
+                    raise ValueError(f"{name} must be a contiguous float64 tensor on {dev}")
+        stats = Stats()
+        res = Result(_ptr(out.get("B")).value, _ptr(out.get("sigma")).value,
+                     _ptr(out.get("Omega")).value, C.pointer(stats))
+        self._workspace(self.workspace_size(X, opt) + 4096)
+        self._bind_stream()
+        st = load().spmesl_solve(self._h, C.byref(prob), C.byref(opt), C.byref(res))
+        if st != OK and (check or st != ENOCONV):
+            raise SpmeslError(st, self._err())
+        return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), st, stats.as_dict())
+
+    def solve_batch(self, Xs, lambda0s, tol=1e-8, precision="fp64", output_scale="original",
+                    check=True):
+        """Solve several datasets (uneven n, p); lambda0s is one value or one
+        per dataset.  Datasets that share lambda0 go in one library call."""
+        if not isinstance(lambda0s, (list, tuple)):
+            lambda0s = [lambda0s] * len(Xs)
+        results = [None] * len(Xs)
+        groups = {}
+        for i, lam in enumerate(lambda0s):
+            groups.setdefault(float(lam), []).append(i)
+        for lam, idx in groups.items():
+            opt = self.options(lam, tol, precision, output_scale)
+            probs = (Problem * len(idx))(*[self.problem(Xs[i]) for i in idx])
+            stats = [Stats() for _ in idx]
+            outs = []
+            ress = (Result * len(idx))()
+            need = 0
+            for j, i in enumerate(idx):
+                p = Xs[i].shape[1]
+                o = dict(B=torch.empty((p, p), dtype=torch.float64, device=Xs[i].device),
+                         sigma=torch.empty((p,), dtype=torch.float64, device=Xs[i].device),
+                         Omega=torch.empty((p, p), dtype=torch.float64, device=Xs[i].device))
+                outs.append(o)
+                ress[j] = Result(o["B"].data_ptr(), o["sigma"].data_ptr(), o["Omega"].data_ptr(),
+                                 C.pointer(stats[j]))
+                need = max(need, self.workspace_size(Xs[i], opt))
+            self._workspace(need + 4096 * (len(idx) + 1))
+            self._bind_stream()
+            status = (C.c_int * len(idx))()
+            st = load().spmesl_solve_batch(self._h, len(idx), probs, C.byref(opt), ress, status)
+            if st != OK and (check or st != ENOCONV):
+                raise SpmeslError(st, self._err())
+            for j, i in enumerate(idx):
+                o = outs[j]
+                results[i] = SolveResult(o["B"], o["sigma"], o["Omega"], status[j], stats[j].as_dict())
+        return results
+
+    def covariance(self, X, precision="fp64"):
+        """Standardise X and form S; returns (S, mean, scale)."""
+        prec = _PRECISION[precision] if isinstance(precision, str) else int(precision)
+        prob = self.problem(X)
+        p = prob.p
+        dt = torch.float64 if prec == FP64 else torch.float32
+        S = torch.empty((p, p), dtype=dt, device=X.device)
+        mean = torch.empty((p,), dtype=torch.float64, device=X.device)
+        scale = torch.empty((p,), dtype=torch.float64, device=X.device)
+        opt = self.options(1.0, 1.0, prec)
+        self._workspace(self.workspace_size(X, opt) + 4096)
+        self._bind_stream()
+        st = load().spmesl_covariance(self._h, C.byref(prob), prec, _ptr(S), _ptr(mean), _ptr(scale))
+        if st != OK:
+            raise SpmeslError(st, self._err())
+        return S, mean, scale
+
+    def symmetrize(self, Omega1):
+        if Omega1.dtype != torch.float64 or not Omega1.is_cuda or not Omega1.is_contiguous():
+            raise TypeError("Omega1 must be a contiguous float64 CUDA tensor")
+        p = Omega1.shape[0]
+        out = torch.empty_like(Omega1)
+        self._bind_stream()
+        st = load().spmesl_symmetrize(self._h, p, _ptr(Omega1), _ptr(out))
+        if st != OK:
+            raise SpmeslError(st, self._err())
+        return out
+
+
+_default = {}
+
+
+def context(device: int | None = None) -> Context:
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _default:
+        _default[d] = Context(d)
+    return _default[d]
+
+
+def solve(X, lambda0, tol=1e-8, precision="fp64", **kw) -> SolveResult:
+    """spmesl_solve on X's device with a cached context."""
+    return context(X.device.index).solve(X, lambda0, tol, precision, **kw)

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Inputs are the seeded workloads; the oracle runs in its exact mode
+(tol 1e-12) as the reference minimiser.  Full-size workloads are checked on
+sampled columns the oracle computes one by one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2203_15031_amd import workloads as W
+from tests.parity import omega_invariants, rel_err, standardized_cov, support_mismatch
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def sp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_15031_amd import spmesl
+    return spmesl
+
+
+@pytest.fixture(scope="module")
+def ctx(sp):
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+def gpu(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).to(DEV)
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# single steps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p", [(100, 200), (37, 131), (400, 64), (3, 2), (130, 257)])
+def test_covariance_fp64(ctx, n, p):
+    rng = np.random.default_rng(n * 1000 + p)
+    X = rng.standard_normal((n, p)) * rng.uniform(0.5, 3, p) + rng.uniform(-5, 5, p)
+    S, mean, scale = ctx.covariance(gpu(X), "fp64")
+    Sref = standardized_cov(X)
+    np.fill_diagonal(Sref, 1.0)
+    assert np.abs(host(S) - Sref).max() < 1e-13
+    assert np.array_equal(np.diag(host(S)), np.ones(p))
+    np.testing.assert_allclose(host(mean), X.mean(0), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(host(scale), 1 / X.std(0), rtol=1e-12)
+    assert np.array_equal(host(S), host(S).T)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("n,p", [(100, 200), (37, 131), (400, 300)])
+def test_covariance_reduced(ctx, prec, n, p):
+    rng = np.random.default_rng(7 + n + p)
+    X = rng.standard_normal((n, p)) @ np.linalg.cholesky(W.ar_cov(p, 0.5)).T
+    S, _, _ = ctx.covariance(gpu(X), prec)
+    Sref = standardized_cov(X)
+    np.fill_diagonal(Sref, 1.0)
+    err = np.abs(host(S).astype(np.float64) - Sref).max()
+    # per-entry bound: float accumulation over n terms (+ the bf16 split)
+    bound = (n + 2) * 2.0 ** -24 + (3 * 2.0 ** -16 if prec == "mixed" else 2 * 2.0 ** -24)
+    assert err <= bound, (err, bound)
+    assert np.array_equal(host(S), host(S).T)
+
+
+def test_symmetrize_matches_oracle_with_ties(ctx):
+    rng = np.random.default_rng(3)
+    p = 77
+    M = rng.standard_normal((p, p))
+    # exact ties in magnitude, both signs
+    M[3, 9], M[9, 3] = 0.5, -0.5
+    M[10, 2], M[2, 10] = 0.25, 0.25
+    M[rng.random((p, p)) < 0.3] = 0.0
+    out = host(ctx.symmetrize(gpu(M)))
+    np.testing.assert_array_equal(out, oracle.symmetrize(M))
+
+
+# ---------------------------------------------------------------------------
+# full solves against the oracle
+# ---------------------------------------------------------------------------
+
+def _check_full(ctx, X, lam0, prec, bar, tol=1e-8):
+    ref = oracle.spmesl(X, lam0, tol=1e-12, original_scale=True)
+    ref_std = oracle.spmesl(X, lam0, tol=1e-12, original_scale=False)
+    Xg = gpu(X)
+    r = ctx.solve(Xg, lam0, tol=tol, precision=prec)
+    rs = ctx.solve(Xg, lam0, tol=tol, precision=prec, output_scale="standardized")
+    B, sig, Om = host(r.B), host(r.sigma), host(r.Omega)
+    errs = dict(B=rel_err(B, ref["B"]), sigma=rel_err(sig, ref["sigma"]), Omega=rel_err(Om, ref["Omega"]))
+    assert max(errs.values()) <= bar, errs
+    S = standardized_cov(X)
+    mism, excl = support_mismatch(host(rs.B), ref_std["B"], S, ref_std["sigma"], lam0, bar)
+    assert mism == 0, (mism, excl)
+    omega_invariants(Om, B)
+    return errs, r.stats
+
+
+def test_solve_ar1_n100_p200_fp64(ctx):
+    w = W.workload("ar1_n100_p200")
+    X = W.generate(w.name)
+    errs, st = _check_full(ctx, X, w.lambda0, "fp64", 1e-6)
+    assert st["columns_noconv"] == 0
+
+
+def test_solve_ar1_n100_p200_mixed(ctx):
+    w = W.workload("ar1_n100_p200")
+    X = W.generate(w.name)
+    _check_full(ctx, X, w.lambda0, "mixed", 1e-4)
+
+
+def test_solve_ar1_n100_p200_fp32(ctx):
+    # float throughout; its error is reported against the oracle, with a bar
+    # set by the float tolerance floor (1e-6) times the problem's conditioning
+    w = W.workload("ar1_n100_p200")
+    X = W.generate(w.name)
+    ref = oracle.spmesl(X, w.lambda0, tol=1e-12)
+    r = ctx.solve(gpu(X), w.lambda0, tol=1e-8, precision="fp32")
+    assert rel_err(host(r.Omega), ref["Omega"]) < 1e-3
+    assert rel_err(host(r.sigma), ref["sigma"]) < 1e-4
+
+
+def test_solve_er_n200_p1000_fp64_and_mixed(ctx):
+    w = W.workload("er_n200_p1000")
+    X = W.generate(w.name)
+    _check_full(ctx, X, w.lambda0, "fp64", 1e-6)
+    _check_full(ctx, X, w.lambda0, "mixed", 1e-4)
+
+
+@pytest.mark.parametrize("n,p,lam", [(23, 67, 0.35), (64, 129, 0.25), (200, 65, 0.2), (5, 2, 0.1)])
+def test_solve_ragged_shapes(ctx, n, p, lam):
+    rng = np.random.default_rng(n + 3 * p)
+    X = W.sample_from_cov(n, W.ar_cov(p, 0.6), rng, centre=False) * rng.uniform(0.2, 4, p)
+    _check_full(ctx, X, lam, "fp64", 1e-6)
+
+
+def test_solve_large_working_sets_escalate(ctx):
+    # small lambda0 on strongly correlated data: working sets beyond 32
+    rng = np.random.default_rng(5)
+    n, p = 300, 120
+    X = W.sample_from_cov(n, W.ar_cov(p, 0.9), rng) + 0.3 * rng.standard_normal((n, p))
+    lam = 0.03
+    errs, st = _check_full(ctx, X, lam, "fp64", 1e-6)
+    assert st["max_working_set"] > 32
+
+
+def test_null_case(ctx):
+    X = W.generate("ar1_n100_p200", n=80, p=30)
+    S = standardized_cov(X)
+    lam = np.abs(S - np.eye(30)).max() * 1.01
+    r = ctx.solve(gpu(X), lam)
+    assert np.all(host(r.B) == 0)
+    np.testing.assert_allclose(host(r.Omega), np.diag(1 / X.var(0)), rtol=1e-13)
+
+
+def test_deterministic(ctx):
+    w = W.workload("er_n200_p1000")
+    X = gpu(W.generate(w.name))
+    for prec in ("fp64", "mixed"):
+        a = ctx.solve(X, w.lambda0, precision=prec)
+        b = ctx.solve(X, w.lambda0, precision=prec)
+        assert torch.equal(a.Omega, b.Omega) and torch.equal(a.B, b.B) and torch.equal(a.sigma, b.sigma)
+
+
+# ---------------------------------------------------------------------------
+# errors and options
+# ---------------------------------------------------------------------------
+
+def test_errors(ctx, sp):
+    X = W.generate("ar1_n100_p200", n=40, p=20)
+    Xn = X.copy()
+    Xn[5, 3] = np.nan
+    with pytest.raises(sp.SpmeslError) as e:
+        ctx.solve(gpu(Xn), 0.3)
+    assert e.value.code == sp.ENONFINITE
+    Xz = X.copy()
+    Xz[:, 7] = 2.0
+    with pytest.raises(sp.SpmeslError) as e:
+        ctx.solve(gpu(Xz), 0.3)
+    assert e.value.code == sp.EZEROVAR
+    with pytest.raises(sp.SpmeslError) as e:
+        ctx.solve(gpu(X), -1.0)
+    assert e.value.code == sp.EINVAL
+    r = ctx.solve(gpu(X), 0.1, tol=1e-12, max_outer=1, check=False)
+    assert r.status == sp.ENOCONV and r.stats["columns_noconv"] > 0
+    # the library still works after errors
+    ctx.solve(gpu(X), 0.3)
+
+
+def test_strided_input_and_skipped_outputs(ctx):
+    X = W.generate("ar1_n100_p200", n=60, p=40)
+    big = np.zeros((60, 57))
+    big[:, :40] = X
+    Xg = gpu(big)[:, :40]
+    assert Xg.stride(0) == 57
+    ref = oracle.spmesl(X, 0.3, tol=1e-12)
+    r = ctx.solve(Xg, 0.3, want=("Omega",))
+    assert r.B is None and r.sigma is None
+    assert rel_err(host(r.Omega), ref["Omega"]) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# the p = 5000 workload, sampled columns
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,bar", [("mixed", 1e-4), ("fp64", 1e-6)])
+def test_blockar_p5000_sampled_columns(ctx, prec, bar):
+    w = W.workload("blockar_n400_p5000")
+    X = W.generate(w.name)
+    r = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision=prec, output_scale="standardized")
+    B = host(r.B)
+    sig = host(r.sigma)
+    rng = np.random.default_rng(0)
+    cols = np.sort(rng.choice(w.p, size=24, replace=False))
+    ref = oracle.spmesl_columns(X, w.lambda0, cols, tol=1e-12, nthreads=0)
+    assert ref["status"] == 0
+    Bref = ref["B"]
+    for i, k in enumerate(cols):
+        assert rel_err(B[:, k], Bref[:, i]) <= bar
+        assert abs(sig[k] - ref["sigma"][i]) <= bar * ref["sigma"][i]
+        nz_ref = np.abs(Bref[:, i]) > bar
+        assert np.all(B[nz_ref, k] != 0)
+    # Omega invariants hold on the whole matrix
+    rO = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision=prec, want=("Omega",))
+    Om = host(rO.Omega)
+    assert np.array_equal(Om, Om.T)
