@@ -344,16 +344,18 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     if (L.prec == SPMESL_FP64)
         launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
                                        (const double *)(ws + L.wbeta), (const double *)(ws + L.sigma),
-                                       scale, original, res->B, res->sigma, res->Omega, s);
+                                       scale, original, res->B, res->sigma, res->Omega,
+                                       &dctl->flags, s);
     else if (L.prec == SPMESL_FP32)
         launch_scatter_outputs<float>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
                                       (const float *)(ws + L.wbeta), (const double *)(ws + L.sigma),
-                                      scale, original, res->B, res->sigma, res->Omega, s);
+                                      scale, original, res->B, res->sigma, res->Omega,
+                                       &dctl->flags, s);
     else
         launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt64), (const int *)(ws + L.widx64),
                                        (const double *)(ws + L.wbeta64),
                                        (const double *)(ws + L.sigma64), scale, original, res->B,
-                                       res->sigma, res->Omega, s);
+                                       res->sigma, res->Omega, &dctl->flags, s);
     if (ev) HIPTRY(ctx, hipEventRecord(ev[5], s));
     HIPTRY(ctx, hipGetLastError());
     return SPMESL_OK;

@@ -40,7 +40,6 @@ __global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A)
     const int lane = lane_id();
     WaveSm<T, LW> &sm = smem[wv];
     const int64_t gw = (int64_t)blockIdx.x * NW + wv;
-    if (*A.flags) return;
     int64_t k;
     if (A.resume) {
         if (gw >= *A.esc_cnt) return;
@@ -48,6 +47,17 @@ __global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A)
     } else {
         if (gw >= A.p) return;
         k = gw;
+    }
+    if (*A.flags) {
+        // bad input: leave an empty, well-formed list for every consumer
+        if (lane == 0) {
+            A.w_cnt[k] = 0;
+            A.sigma[k] = 1.0;
+            A.lam_used[k] = (double)A.lambda0;
+            A.col_status[k] = kColOk;
+            if (A.band_cnt) A.band_cnt[k] = 0;
+        }
+        return;
     }
     const int64_t p = A.p;
     ColState<T, LW> st;

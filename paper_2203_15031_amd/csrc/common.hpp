@@ -193,7 +193,8 @@ void launch_fill_zero(double *A, int64_t count, hipStream_t s);
 template <typename T>
 void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta,
                             const double *sigma, const double *scale, int original_scale,
-                            double *B, double *sig_out, double *Omega, hipStream_t s);
+                            double *B, double *sig_out, double *Omega, const int *flags,
+                            hipStream_t s);
 void launch_symmetrize_dense(int64_t p, const double *Om1, double *Om, hipStream_t s);
 
 } // namespace spmesl

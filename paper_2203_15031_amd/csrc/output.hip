@@ -68,31 +68,35 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t p, const int *__restric
                                                  const double *__restrict__ scale, int original,
                                                  double *__restrict__ B,
                                                  double *__restrict__ sig_out,
-                                                 double *__restrict__ Om)
+                                                 double *__restrict__ Om,
+                                                 const int *__restrict__ flags)
 {
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (k >= p) return;
-    const int wk = w_cnt[k];
+    if (k >= p || *flags) return;
+    int wk = w_cnt[k];
+    wk = wk < 0 ? 0 : (wk > kWMax ? kWMax : wk);
     const double sk = sigma[k];
     const double ck = original ? scale[k] : 1.0;
     const double dk = 1.0 / (sk * sk);
     for (int q = lane; q < wk; q += kWave) {
         const int j = w_idx[k * kWMax + q];
         const double b = (double)w_beta[k * kWMax + q];
-        if (b == 0.0) continue;
+        if (b == 0.0 || j < 0 || (int64_t)j >= p) continue;
         const double cj = original ? scale[j] : 1.0;
         if (B) B[(int64_t)j * p + k] = b * (cj / ck);
         if (Om && j < k) {
             // the pair (j, k) belongs to its larger index k
             const int *lj = w_idx + (int64_t)j * kWMax;
-            int lo = 0, hi = w_cnt[j];
+            int wj = w_cnt[j];
+            wj = wj < 0 ? 0 : (wj > kWMax ? kWMax : wj);
+            int lo = 0, hi = wj;
             while (lo < hi) {
                 int mid = (lo + hi) >> 1;
                 if (lj[mid] < (int)k) lo = mid + 1;
                 else hi = mid;
             }
-            if (lo < w_cnt[j] && lj[lo] == (int)k) {
+            if (lo < wj && lj[lo] == (int)k) {
                 const double bkj = (double)w_beta[(int64_t)j * kWMax + lo];
                 if (bkj != 0.0) {
                     const double sj = sigma[j];
@@ -115,18 +119,19 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t p, const int *__restric
 template <typename T>
 void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta,
                             const double *sigma, const double *scale, int original_scale,
-                            double *B, double *sig_out, double *Omega, hipStream_t s)
+                            double *B, double *sig_out, double *Omega, const int *flags,
+                            hipStream_t s)
 {
     hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((p + 3) / 4)), dim3(256), 0, s, p, w_cnt,
-                       w_idx, w_beta, sigma, scale, original_scale, B, sig_out, Omega);
+                       w_idx, w_beta, sigma, scale, original_scale, B, sig_out, Omega, flags);
 }
 
 template void launch_scatter_outputs<double>(int64_t, const int *, const int *, const double *,
                                              const double *, const double *, int, double *,
-                                             double *, double *, hipStream_t);
+                                             double *, double *, const int *, hipStream_t);
 template void launch_scatter_outputs<float>(int64_t, const int *, const int *, const float *,
                                             const double *, const double *, int, double *,
-                                            double *, double *, hipStream_t);
+                                            double *, double *, const int *, hipStream_t);
 
 // Dense symmetrisation of a given Omega_1 (32 x 32 tiles; the partner tile
 // is read transposed through LDS so both reads are coalesced).

@@ -90,13 +90,15 @@ __device__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, in
 __device__ __forceinline__ double beta32_of(const PolishArgs &A, int64_t k, int j)
 {
     const int *idx = A.w_idx32 + k * kWMax;
-    int lo = 0, hi = A.w_cnt32[k];
+    int w = A.w_cnt32[k];
+    w = w < 0 ? 0 : (w > kWMax ? kWMax : w);
+    int lo = 0, hi = w;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
         if (idx[mid] < j) lo = mid + 1;
         else hi = mid;
     }
-    return (lo < A.w_cnt32[k] && idx[lo] == j) ? (double)A.w_beta32[k * kWMax + lo] : 0.0;
+    return (lo < w && idx[lo] == j) ? (double)A.w_beta32[k * kWMax + lo] : 0.0;
 }
 
 template <int LW, int NW>
@@ -108,7 +110,6 @@ __global__ __launch_bounds__(kWave *NW) void k_polish(PolishArgs A, int tier2)
     const int lane = lane_id();
     WaveSm<double, LW> &sm = smem[wv];
     const int64_t gw = (int64_t)blockIdx.x * NW + wv;
-    if (*A.flags) return;
     int64_t k;
     if (tier2) {
         if (gw >= *A.esc_cnt) return;
@@ -117,14 +118,25 @@ __global__ __launch_bounds__(kWave *NW) void k_polish(PolishArgs A, int tier2)
         if (gw >= A.p) return;
         k = gw;
     }
+    if (*A.flags) {
+        if (lane == 0) {
+            A.w_cnt[k] = 0;
+            A.sigma[k] = 1.0;
+            A.lam_used[k] = A.lambda0;
+            A.col_status[k] = kColOk;
+        }
+        return;
+    }
     const int64_t p = A.p;
     ColState<double, LW> st;
     SolveCounts cnt = {0, 0, 0};
     int status = kColOk, rounds = 0, checks = 0, added = 0;
 
     // --- W' = float support U float band --------------------------------
-    const int w32 = A.w_cnt32[k];
+    int w32 = A.w_cnt32[k];
+    w32 = w32 < 0 ? 0 : (w32 > kWMax ? kWMax : w32);
     int nb = A.band_cnt[k];
+    nb = nb < 0 ? 0 : nb;
     bool full = nb > kBandMax || A.col_status32[k] != kColOk;
     nb = nb < kBandMax ? nb : kBandMax;
     double norm32 = 0.0;

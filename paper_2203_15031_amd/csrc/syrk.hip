@@ -15,8 +15,9 @@
 //             v_mfma_f32_16x16x32_bf16 from variable-major hi/lo panels.
 //
 // Operand layout of the 16x16xK MFMAs used here (wave64): lane l supplies
-// row l%16 of A and column l%16 of B, at k-block l/16; accumulator element r
-// of lane l is D[4*(l/16) + r][l%16].
+// row l%16 of A and column l%16 of B, at k-block l/16.  Accumulator element r
+// of lane l is D[4*(l/16) + r][l%16] for the float-output MFMAs and
+// D[4*r + l/16][l%16] for the double one (checked on the device).
 #include "common.hpp"
 
 namespace spmesl {
@@ -37,6 +38,11 @@ __device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
 template <typename T> struct Acc;
 template <> struct Acc<double> { typedef d4 type; };
 template <> struct Acc<float> { typedef f4 type; };
+
+// row of accumulator element r of `lane` within a 16x16 block
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return 4 * r + (lane >> 4); }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
 
 // Map a linear block id to an upper-triangle tile (bj <= bk), with blocks
 // that share a row panel kept on the same XCD (blocks are dispatched to
@@ -112,13 +118,17 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                sm.out[32 * wm + 16 * a + 4 * (lane >> 4) + r][32 * wn + 16 * b + (lane & 15)] =
+                sm.out[32 * wm + 16 * a + acc_row<T>(lane, r)][32 * wn + 16 * b + (lane & 15)] =
                     acc[a][b][r] * invn;
     __syncthreads();
+    // a diagonal tile takes its upper triangle for both halves, so S is
+    // symmetric bit for bit whatever the accumulation order
+    const bool diag = bj == bk;
     for (int e = tid; e < 64 * 64; e += 256) {
         int rr = e >> 6, cc = e & 63;
         int64_t j = j0 + rr, k = k0 + cc;
-        if (j < p && k < p) S[j * p + k] = (j == k) ? T(1) : sm.out[rr][cc];
+        if (j < p && k < p)
+            S[j * p + k] = (j == k) ? T(1) : ((diag && rr > cc) ? sm.out[cc][rr] : sm.out[rr][cc]);
     }
     if (bj != bk) {
         for (int e = tid; e < 64 * 64; e += 256) {
@@ -231,10 +241,12 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
                 sm.out[64 * wm + 16 * a + 4 * (lane >> 4) + r][64 * wn + 16 * b + (lane & 15)] =
                     acc[a][b][r] * invn;
     __syncthreads();
+    const bool diag = bj == bk;
     for (int e = tid; e < 128 * 128; e += 256) {
         int rr = e >> 7, cc = e & 127;
         int64_t j = j0 + rr, k = k0 + cc;
-        if (j < p && k < p) S[j * p + k] = (j == k) ? 1.0f : sm.out[rr][cc];
+        if (j < p && k < p)
+            S[j * p + k] = (j == k) ? 1.0f : ((diag && rr > cc) ? sm.out[cc][rr] : sm.out[rr][cc]);
     }
     if (bj != bk) {
         for (int e = tid; e < 128 * 128; e += 256) {
