@@ -32,22 +32,28 @@
 
 namespace spmesl {
 
+template <typename T, int LW>
+__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k);
+
 template <typename T, int LW, int NW>
 __global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A)
 {
     __shared__ WaveSm<T, LW> smem[NW];
     const int wv = threadIdx.x / kWave;
-    const int lane = lane_id();
     WaveSm<T, LW> &sm = smem[wv];
-    const int64_t gw = (int64_t)blockIdx.x * NW + wv;
-    int64_t k;
-    if (A.resume) {
-        if (gw >= *A.esc_cnt) return;
-        k = A.esc_list[gw];
-    } else {
-        if (gw >= A.p) return;
-        k = gw;
+    const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
+    // tier 2 walks the escalation queue with a small grid
+    const int64_t nwork = A.resume ? (int64_t)*A.esc_cnt : A.p;
+    for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
+        const int64_t k = A.resume ? (int64_t)A.esc_list[gw] : gw;
+        solve_column<T, LW>(A, sm, k);
     }
+}
+
+template <typename T, int LW>
+__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k)
+{
+    const int lane = lane_id();
     if (*A.flags) {
         // bad input: leave an empty, well-formed list for every consumer
         if (lane == 0) {
@@ -138,9 +144,9 @@ void launch_colsolve(const ColArgs<T> &a, hipStream_t s)
         unsigned blocks = (unsigned)((a.p + NW - 1) / NW);
         hipLaunchKernelGGL((k_colsolve<T, 32, NW>), dim3(blocks), dim3(kWave * NW), 0, s, a);
     } else {
-        // one wave per block; the grid covers the worst case and waves past
-        // the queue length exit at once
-        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1>), dim3((unsigned)a.p), dim3(kWave), 0, s, a);
+        // one wave per block walking the (short) escalation queue
+        unsigned blocks = (unsigned)(a.p < 256 ? a.p : 256);
+        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1>), dim3(blocks), dim3(kWave), 0, s, a);
     }
 }
 

@@ -101,23 +101,28 @@ __device__ __forceinline__ double beta32_of(const PolishArgs &A, int64_t k, int 
     return (lo < w && idx[lo] == j) ? (double)A.w_beta32[k * kWMax + lo] : 0.0;
 }
 
+template <int LW>
+__device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64_t k, int tier2);
+
 template <int LW, int NW>
 __global__ __launch_bounds__(kWave *NW) void k_polish(PolishArgs A, int tier2)
 {
-    constexpr int NS = ColState<double, LW>::NS;
     __shared__ WaveSm<double, LW> smem[NW];
     const int wv = threadIdx.x / kWave;
-    const int lane = lane_id();
     WaveSm<double, LW> &sm = smem[wv];
-    const int64_t gw = (int64_t)blockIdx.x * NW + wv;
-    int64_t k;
-    if (tier2) {
-        if (gw >= *A.esc_cnt) return;
-        k = A.esc_list[gw];
-    } else {
-        if (gw >= A.p) return;
-        k = gw;
+    const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
+    const int64_t nwork = tier2 ? (int64_t)*A.esc_cnt : A.p;
+    for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
+        const int64_t k = tier2 ? (int64_t)A.esc_list[gw] : gw;
+        polish_column<LW>(A, sm, k, tier2);
     }
+}
+
+template <int LW>
+__device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64_t k, int tier2)
+{
+    constexpr int NS = ColState<double, LW>::NS;
+    const int lane = lane_id();
     if (*A.flags) {
         if (lane == 0) {
             A.w_cnt[k] = 0;
@@ -277,7 +282,8 @@ void launch_polish(const PolishArgs &a, hipStream_t s)
     constexpr int NW = 4;
     hipLaunchKernelGGL((k_polish<32, NW>), dim3((unsigned)((a.p + NW - 1) / NW)),
                        dim3(kWave * NW), 0, s, a, 0);
-    hipLaunchKernelGGL((k_polish<kWMax, 1>), dim3((unsigned)a.p), dim3(kWave), 0, s, a, 1);
+    hipLaunchKernelGGL((k_polish<kWMax, 1>), dim3((unsigned)(a.p < 256 ? a.p : 256)), dim3(kWave), 0,
+                       s, a, 1);
 }
 
 } // namespace spmesl
