@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspmesl.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["standardize.hip", "syrk.hip", "colsolve.hip", "polish.hip", "output.hip",
+SOURCES = ["standardize.hip", "syrk.hip", "colsolve.hip", "kkt.hip", "polish.hip", "output.hip",
            "api.hip", "penalty.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPMESL_ARCH", "gfx950")
@@ -30,8 +30,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-    if src.endswith(".cpp"):
-        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"),
+    if src.endswith(".cpp"):  # host-only C++
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"),
                "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/spmesl.h"
+#include "spmesl.h"
 #include "common.hpp"
 
 using namespace spmesl;
@@ -29,9 +29,11 @@ struct Ctl {
     int flags;        // colstats: 1 non-finite, 2 zero variance
     int status1;      // status bits of the final phase (the polish in the mixed form)
     int status2;      // status bits of the float phase of the mixed form
-    int esc1;         // escalation queue length, solve
-    int esc2;         // escalation queue length, polish
-    int pad[3];
+    int esc_a;        // escalations of the first solves
+    int dirty;        // columns the row-tiled KKT pass flagged
+    int esc_c;        // escalations of the flagged columns' re-solves
+    int esc_polish;   // escalations of the polish
+    int pad[1];
 };
 static_assert(sizeof(Ctl) % 4 == 0, "Ctl is zeroed as 32-bit words");
 static_assert(kNumCounters <= 16, "counter slots");
@@ -45,6 +47,7 @@ struct Plan {
     int prec = 0, rchunks = 1;
     size_t mean, scale, partial, xs, xt, hi, lo, S;
     size_t wcnt, widx, wbeta, sigma, lam, cstat, esclist, bandcnt, bandidx;
+    size_t suppcnt, suppidx, suppval, pendcnt, pendidx, dirtylist, esclist2, colinfo, polinfo;
     size_t wcnt64, widx64, wbeta64, sigma64, lam64, cstat64, esclist64;
     size_t total = 0;
 };
@@ -89,6 +92,15 @@ Plan make_plan(int64_t n, int64_t p, int prec)
     L.lam = b.take(8 * P);
     L.cstat = b.take(4 * P);
     L.esclist = b.take(4 * P);
+    L.suppcnt = b.take(4 * P);
+    L.suppidx = b.take(4 * P * kWMax);
+    L.suppval = b.take(tsz * P * kWMax);
+    L.pendcnt = b.take(4 * P);
+    L.pendidx = b.take(4 * P * kPendMax);
+    L.dirtylist = b.take(4 * P);
+    L.esclist2 = b.take(4 * P);
+    L.colinfo = b.take(16 * P);
+    L.polinfo = prec == SPMESL_MIXED ? b.take(32 * P) : 0;
     L.bandcnt = L.bandidx = 0;
     L.wcnt64 = L.widx64 = L.wbeta64 = L.sigma64 = L.lam64 = L.cstat64 = L.esclist64 = 0;
     if (prec == SPMESL_MIXED) {
@@ -206,6 +218,87 @@ static int validate(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
     return SPMESL_OK;
 }
 
+// The p regressions: first solves (screen + one working-set solve), the
+// escalations, the row-tiled KKT pass over every column, and the re-solves of
+// the columns it flagged.  When one row of S does not fit in LDS the first
+// solves run their own in-wave KKT passes instead.
+template <typename T>
+static void enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt,
+                            double tol, double band, int max_outer, int max_sweeps, int max_rounds,
+                            hipStream_t s)
+{
+    const int64_t p = L.p;
+    const int rj = kkt_rows_per_block(p, sizeof(T), (size_t)80 * 1024) > 0
+                       ? kkt_rows_per_block(p, sizeof(T), (size_t)80 * 1024)
+                       : kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
+    ColArgs<T> a{};
+    a.S = (const T *)(ws + L.S);
+    a.p = p;
+    a.lambda0 = (T)opt->lambda0;
+    a.tol = (T)tol;
+    a.kkt_tol = (T)tol;
+    a.band = (T)band;
+    a.max_outer = max_outer;
+    a.max_sweeps = max_sweeps;
+    a.max_rounds = max_rounds;
+    a.w_cnt = (int *)(ws + L.wcnt);
+    a.w_idx = (int *)(ws + L.widx);
+    a.w_beta = (T *)(ws + L.wbeta);
+    a.sigma = (double *)(ws + L.sigma);
+    a.lam_used = (double *)(ws + L.lam);
+    a.col_status = (int *)(ws + L.cstat);
+    a.supp_cnt = (int *)(ws + L.suppcnt);
+    a.supp_idx = (int *)(ws + L.suppidx);
+    a.supp_val = (T *)(ws + L.suppval);
+    a.pend_cnt = (int *)(ws + L.pendcnt);
+    a.pend_idx = (int *)(ws + L.pendidx);
+    a.band_cnt = band > 0.0 ? (int *)(ws + L.bandcnt) : nullptr;
+    a.band_idx = band > 0.0 ? (int *)(ws + L.bandidx) : nullptr;
+    a.colinfo = (int *)(ws + L.colinfo);
+    a.counters = dctl->counters;
+    a.flags = &dctl->flags;
+    // first solves
+    a.mode = 0;
+    a.defer_kkt = rj > 0;
+    a.esc_cnt = &dctl->esc_a;
+    a.esc_list = (int *)(ws + L.esclist);
+    launch_colsolve(a, 0, s);
+    a.mode = 1;
+    a.work_list = (const int *)(ws + L.esclist);
+    a.work_cnt = &dctl->esc_a;
+    launch_colsolve(a, 1, s);
+    if (rj == 0) return;
+    KktArgs<T> k{};
+    k.S = a.S;
+    k.p = p;
+    k.kkt_tol = a.kkt_tol;
+    k.band = a.band;
+    k.lam_used = a.lam_used;
+    k.col_status = a.col_status;
+    k.w_cnt = a.w_cnt;
+    k.w_idx = a.w_idx;
+    k.supp_cnt = a.supp_cnt;
+    k.supp_idx = a.supp_idx;
+    k.supp_val = a.supp_val;
+    k.pend_cnt = a.pend_cnt;
+    k.pend_idx = a.pend_idx;
+    k.dirty_cnt = &dctl->dirty;
+    k.dirty_list = (int *)(ws + L.dirtylist);
+    k.band_cnt = a.band_cnt;
+    k.band_idx = a.band_idx;
+    k.flags = &dctl->flags;
+    launch_kkt_rows(k, rj, s);
+    // re-solve the flagged columns
+    a.work_list = (const int *)(ws + L.dirtylist);
+    a.work_cnt = &dctl->dirty;
+    a.esc_cnt = &dctl->esc_c;
+    a.esc_list = (int *)(ws + L.esclist2);
+    launch_colsolve(a, 0, s);
+    a.work_list = (const int *)(ws + L.esclist2);
+    a.work_cnt = &dctl->esc_c;
+    launch_colsolve(a, 1, s);
+}
+
 // Enqueue one full solve.  ws: workspace base laid out by `L`; dctl: this
 // problem's control block.  Records the phase events when `ev` is non-null.
 static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
@@ -243,62 +336,12 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                            p, (float *)(ws + L.S), s);
     if (ev) HIPTRY(ctx, hipEventRecord(ev[2], s));
 
-    if (L.prec == SPMESL_FP64) {
-        ColArgs<double> a{};
-        a.S = (const double *)(ws + L.S);
-        a.p = p;
-        a.lambda0 = opt->lambda0;
-        a.tol = opt->tol;
-        a.kkt_tol = opt->tol;
-        a.band = 0.0;
-        a.max_outer = max_outer;
-        a.max_sweeps = max_sweeps;
-        a.max_rounds = max_rounds;
-        a.w_cnt = (int *)(ws + L.wcnt);
-        a.w_idx = (int *)(ws + L.widx);
-        a.w_beta = (double *)(ws + L.wbeta);
-        a.sigma = (double *)(ws + L.sigma);
-        a.lam_used = (double *)(ws + L.lam);
-        a.col_status = (int *)(ws + L.cstat);
-        a.esc_cnt = &dctl->esc1;
-        a.esc_list = (int *)(ws + L.esclist);
-        a.counters = dctl->counters;
-        a.status_bits = &dctl->status1;
-        a.flags = &dctl->flags;
-        a.resume = 0;
-        launch_colsolve(a, s);
-        a.resume = 1;
-        launch_colsolve(a, s);
-    } else {
-        const double tol32 = std::max(opt->tol, (double)SPMESL_FP32_TOL_FLOOR);
-        ColArgs<float> a{};
-        a.S = (const float *)(ws + L.S);
-        a.p = p;
-        a.lambda0 = (float)opt->lambda0;
-        a.tol = (float)tol32;
-        a.kkt_tol = (float)tol32;
-        a.band = L.prec == SPMESL_MIXED ? (float)kMixedBand : 0.0f;
-        a.max_outer = max_outer;
-        a.max_sweeps = max_sweeps;
-        a.max_rounds = max_rounds;
-        a.w_cnt = (int *)(ws + L.wcnt);
-        a.w_idx = (int *)(ws + L.widx);
-        a.w_beta = (float *)(ws + L.wbeta);
-        a.sigma = (double *)(ws + L.sigma);
-        a.lam_used = (double *)(ws + L.lam);
-        a.col_status = (int *)(ws + L.cstat);
-        a.band_cnt = L.prec == SPMESL_MIXED ? (int *)(ws + L.bandcnt) : nullptr;
-        a.band_idx = L.prec == SPMESL_MIXED ? (int *)(ws + L.bandidx) : nullptr;
-        a.esc_cnt = &dctl->esc1;
-        a.esc_list = (int *)(ws + L.esclist);
-        a.counters = dctl->counters;
-        a.status_bits = L.prec == SPMESL_MIXED ? &dctl->status2 : &dctl->status1;
-        a.flags = &dctl->flags;
-        a.resume = 0;
-        launch_colsolve(a, s);
-        a.resume = 1;
-        launch_colsolve(a, s);
-    }
+    if (L.prec == SPMESL_FP64)
+        enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s);
+    else
+        enqueue_columns<float>(L, ws, dctl, opt, std::max(opt->tol, (double)SPMESL_FP32_TOL_FLOOR),
+                               L.prec == SPMESL_MIXED ? kMixedBand : 0.0, max_outer, max_sweeps,
+                               max_rounds, s);
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
 
     if (L.prec == SPMESL_MIXED) {
@@ -324,7 +367,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         // |S32 - S64| per entry: bfloat16 split (3 * 2^-16) plus float
         // accumulation over n terms; plus float rounding of the gradient
         q.eps = 3.0 * std::ldexp(1.0, -16) + (double)(n + 2) * std::ldexp(1.0, -24) + 1e-6;
-        q.esc_cnt = &dctl->esc2;
+        q.esc_cnt = &dctl->esc_polish;
         q.esc_list = (int *)(ws + L.esclist64);
         q.w_cnt = (int *)(ws + L.wcnt64);
         q.w_idx = (int *)(ws + L.widx64);
@@ -332,10 +375,17 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         q.sigma = (double *)(ws + L.sigma64);
         q.lam_used = (double *)(ws + L.lam64);
         q.col_status = (int *)(ws + L.cstat64);
-        q.counters = dctl->counters;
-        q.status_bits = &dctl->status1;
+        q.polinfo = (int *)(ws + L.polinfo);
         q.flags = &dctl->flags;
         launch_polish(q, s);
+    }
+    {
+        const bool mixed = L.prec == SPMESL_MIXED;
+        launch_reduce_stats(p, (const int *)(ws + L.colinfo),
+                            mixed ? (const int *)(ws + L.polinfo) : nullptr,
+                            (const int *)(ws + (mixed ? L.wcnt64 : L.wcnt)),
+                            (const int *)(ws + (mixed ? L.cstat64 : L.cstat)), dctl->counters,
+                            &dctl->status1, s);
     }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[4], s));
 

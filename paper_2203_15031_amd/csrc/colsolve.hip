@@ -11,8 +11,7 @@
 //
 // How (design for gfx950, not the paper's GPU design):
 //   * Working set.  Coordinates outside a working set W stay at zero; a
-//     KKT pass over all p coordinates (a streamed read of row k of S and of
-//     the rows of the current support) finds every j outside W with
+//     KKT pass over all p coordinates finds every j outside W with
 //     |g_j| > lambda + tol and adds it; the column is done when a pass finds
 //     none.  Coordinates outside W would not move in a cyclic sweep anyway,
 //     so the fixed point is Algorithm 1's.
@@ -25,39 +24,83 @@
 //   * The outer loop is Algorithm 1's: lambda = sigma lambda0, sweeps until
 //     the largest change is < tol, then sigma; stop when |d sigma| < tol.
 //
-// Two tiers: a 32-coordinate working set with four columns per workgroup,
-// and a 128-coordinate one (one column per workgroup) that resumes columns
-// the first tier hands over.  Beyond 128 the column reports SPMESL_EWORKSET.
+// Phases of one solve:
+//   fresh  : screen (the KKT pass at beta = 0 reads row k of S only), first
+//            working-set solve; with defer_kkt the column stops there and the
+//            row-tiled pass of kkt.hip checks every column reading S once;
+//   resume : columns that pass flagged (or that outgrew 32 coordinates) take
+//            their violators from the pending list, re-solve, and finish with
+//            in-wave KKT passes (rows of S streamed per column).
+// Two tiers: 32-coordinate working sets (four columns per workgroup) and
+// 128-coordinate ones (one per workgroup).  Beyond 128 the column reports
+// SPMESL_EWORKSET.
 #include "colsolve_dev.hpp"
 
 namespace spmesl {
 
 template <typename T, int LW>
-__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k);
+__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier);
 
 template <typename T, int LW, int NW>
-__global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A)
+__global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A, int tier)
 {
     __shared__ WaveSm<T, LW> smem[NW];
     const int wv = threadIdx.x / kWave;
     WaveSm<T, LW> &sm = smem[wv];
     const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
-    // tier 2 walks the escalation queue with a small grid
-    const int64_t nwork = A.resume ? (int64_t)*A.esc_cnt : A.p;
+    const int64_t nwork = A.mode ? (int64_t)*A.work_cnt : A.p;
     for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
-        const int64_t k = A.resume ? (int64_t)A.esc_list[gw] : gw;
-        solve_column<T, LW>(A, sm, k);
+        const int64_t k = A.mode ? (int64_t)A.work_list[gw] : gw;
+        solve_column<T, LW>(A, sm, k, tier);
+    }
+}
+
+// per-column counters: set by the first solve, accumulated by later phases
+template <typename T>
+__device__ void record_info(const ColArgs<T> &A, int64_t k, const SolveCounts &cnt, int rounds)
+{
+    int *ci = A.colinfo + k * 4;
+    if (A.mode == 0) {
+        ci[0] = cnt.outer;
+        ci[1] = cnt.sweeps;
+        ci[2] = cnt.updates;
+        ci[3] = rounds;
+    } else {
+        ci[0] += cnt.outer;
+        ci[1] += cnt.sweeps;
+        ci[2] += cnt.updates;
+        ci[3] += rounds;
     }
 }
 
 template <typename T, int LW>
-__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k)
+__device__ void escalate(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm,
+                         const ColState<T, LW> &st, int np, const SolveCounts &cnt, int rounds)
+{
+    const int lane = lane_id();
+    store_column(A, k, sm, st, kColOk, false);
+    if (lane == 0) record_info(A, k, cnt, rounds);
+    for (int i = lane; i < np; i += kWave) A.pend_idx[k * kPendMax + i] = sm.pend[i];
+    if (lane == 0) {
+        A.pend_cnt[k] = np;
+        int pos = atomicAdd(A.esc_cnt, 1);
+        A.esc_list[pos] = (int)k;
+        atomicAdd(&A.counters[kCntEscalated], 1ull);
+    }
+}
+
+template <typename T, int LW>
+__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier)
 {
     const int lane = lane_id();
     if (*A.flags) {
-        // bad input: leave an empty, well-formed list for every consumer
+        // bad input: leave an empty, well-formed column for every consumer
         if (lane == 0) {
             A.w_cnt[k] = 0;
+            A.supp_cnt[k] = 0;
+            A.pend_cnt[k] = 0;
+            A.colinfo[k * 4 + 0] = A.colinfo[k * 4 + 1] = 0;
+            A.colinfo[k * 4 + 2] = A.colinfo[k * 4 + 3] = 0;
             A.sigma[k] = 1.0;
             A.lam_used[k] = (double)A.lambda0;
             A.col_status[k] = kColOk;
@@ -66,28 +109,61 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k)
         return;
     }
     const int64_t p = A.p;
+    const bool band = A.band > T(0);
     ColState<T, LW> st;
     SolveCounts cnt = {0, 0, 0};
-    int rounds = 0, status = kColOk, maxw = 0;
-    if (A.resume) {
-        st.w = A.w_cnt[k];
-        for (int q = lane; q < st.w; q += kWave) {
-            sm.widx[q] = A.w_idx[k * kWMax + q];
-            sm.wbeta[q] = A.w_beta[k * kWMax + q];
-        }
-        st.sigma = (T)A.sigma[k];
-        st.lam_used = (T)A.lam_used[k];
-        wave_sync();
-        load_working_set(A.S, p, k, sm, st);
-    } else {
+    int rounds = 0, status = kColOk;
+    bool deferred = false;
+
+    if (A.mode == 0) {
         st.w = 0;
         st.sigma = T(1);
         st.lam_used = A.lambda0;
 #pragma unroll
         for (int s = 0; s < ColState<T, LW>::NS; ++s) st.g[s] = st.b[s] = st.sv[s] = T(0);
+    } else {
+        st.w = A.w_cnt[k];
+        st.w = st.w < 0 ? 0 : (st.w > LW ? LW : st.w);
+        for (int q = lane; q < st.w; q += kWave) {
+            sm.widx[q] = A.w_idx[k * kWMax + q];
+            sm.wbeta[q] = A.w_beta[k * kWMax + q];
+        }
+#pragma unroll
+        for (int s = 0; s < ColState<T, LW>::NS; ++s) {
+            int q = s * kWave + lane;
+            st.b[s] = q < st.w ? A.w_beta[k * kWMax + q] : T(0);
+            st.g[s] = st.sv[s] = T(0);
+        }
+        st.sigma = (T)A.sigma[k];
+        st.lam_used = (T)A.lam_used[k];
+        int np = A.pend_cnt[k];
+        np = np < 0 ? 0 : (np > kPendMax ? kPendMax : np);
+        for (int i = lane; i < np; i += kWave) sm.pend[i] = A.pend_idx[k * kPendMax + i];
+        wave_sync();
+        if (lane == 0) A.pend_cnt[k] = 0;
+        if (np > 0) {
+            np = sort_unique_small(sm.pend, np);
+            if (st.w + np > LW) {
+                if (tier == 0) {
+                    escalate(A, k, sm, st, np, cnt, rounds);
+                    return;
+                }
+                np = LW - st.w;
+            }
+            if (np > 0) {
+                ++rounds;
+                merge_pending(sm, st, np);
+                load_working_set(A.S, p, k, sm, st);
+                status = scaled_lasso_W(sm, st, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+            } else {
+                status = kColWorkset;
+            }
+        } else {
+            load_working_set(A.S, p, k, sm, st);
+        }
     }
-    const bool band = A.band > T(0);
-    for (;;) {
+
+    while (status == kColOk) {
         int ns = build_support(sm, st);
         int npend = kkt_pass(A.S, p, k, sm, st.w, ns, st.lam_used + A.kkt_tol, band,
                              st.lam_used - A.band, A.band_cnt, A.band_idx);
@@ -96,17 +172,10 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k)
             status = kColNoconv;
             break;
         }
-        ++rounds;
         int np = npend < kPendMax ? npend : kPendMax;
         if (st.w + np > LW) {
-            if (LW < kWMax && !A.resume) {
-                // hand the column to the wider tier from its current state
-                store_column(A, k, sm, st, kColOk);
-                if (lane == 0) {
-                    int pos = atomicAdd(A.esc_cnt, 1);
-                    A.esc_list[pos] = (int)k;
-                    atomicAdd(&A.counters[kCntEscalated], 1ull);
-                }
+            if (tier == 0) {
+                escalate(A, k, sm, st, np, cnt, rounds);
                 return;
             }
             np = LW - st.w;
@@ -115,42 +184,44 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k)
                 break;
             }
         }
+        ++rounds;
         merge_pending(sm, st, np);
-        maxw = st.w > maxw ? st.w : maxw;
         load_working_set(A.S, p, k, sm, st);
         status = scaled_lasso_W(sm, st, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
-        if (status != kColOk) break;
-    }
-    store_column(A, k, sm, st, status);
-    if (lane == 0) {
-        atomicAdd(&A.counters[kCntOuter], (unsigned long long)cnt.outer);
-        atomicAdd(&A.counters[kCntSweeps], (unsigned long long)cnt.sweeps);
-        atomicAdd(&A.counters[kCntUpdates], (unsigned long long)cnt.updates);
-        atomicAdd(&A.counters[kCntRounds], (unsigned long long)rounds);
-        atomicMax(&A.counters[kCntMaxW], (unsigned long long)maxw);
-        atomicMax(&A.counters[kCntMaxOuter], (unsigned long long)cnt.outer);
-        if (status != kColOk) {
-            atomicAdd(&A.counters[kCntNoconv], 1ull);
-            atomicOr(A.status_bits, status == kColWorkset ? 4 : (status == kColDegenerate ? 2 : 1));
+        if (A.mode == 0 && A.defer_kkt && status == kColOk) {
+            deferred = true;
+            break;
         }
+    }
+    store_column(A, k, sm, st, deferred ? (int)kColDeferred : status, true);
+    if (lane == 0) {
+        // deferred: the row-tiled pass appends to these lists; error: the
+        // band list may predate the final support, so drop it
+        if (deferred || status != kColOk) {
+            A.pend_cnt[k] = 0;
+            if (A.band_cnt) A.band_cnt[k] = 0;
+        }
+        record_info(A, k, cnt, rounds);
     }
 }
 
 template <typename T>
-void launch_colsolve(const ColArgs<T> &a, hipStream_t s)
+void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
 {
-    if (!a.resume) {
+    if (tier == 0) {
         constexpr int NW = 4;
-        unsigned blocks = (unsigned)((a.p + NW - 1) / NW);
-        hipLaunchKernelGGL((k_colsolve<T, 32, NW>), dim3(blocks), dim3(kWave * NW), 0, s, a);
+        int64_t blocks = (a.p + NW - 1) / NW;
+        if (a.mode && blocks > 2048) blocks = 2048;  // resume walks a work list
+        hipLaunchKernelGGL((k_colsolve<T, 32, NW>), dim3((unsigned)blocks), dim3(kWave * NW), 0, s, a,
+                           0);
     } else {
         // one wave per block walking the (short) escalation queue
         unsigned blocks = (unsigned)(a.p < 256 ? a.p : 256);
-        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1>), dim3(blocks), dim3(kWave), 0, s, a);
+        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1>), dim3(blocks), dim3(kWave), 0, s, a, 1);
     }
 }
 
-template void launch_colsolve<double>(const ColArgs<double> &, hipStream_t);
-template void launch_colsolve<float>(const ColArgs<float> &, hipStream_t);
+template void launch_colsolve<double>(const ColArgs<double> &, int, hipStream_t);
+template void launch_colsolve<float>(const ColArgs<float> &, int, hipStream_t);
 
 } // namespace spmesl

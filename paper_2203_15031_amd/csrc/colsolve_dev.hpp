@@ -77,9 +77,10 @@ __device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 bool ok = t + u < ns;
-                int l = ok ? sm.sidx[t + u] : (int)k;
+                int64_t l = ok ? (int64_t)sm.sidx[t + u] : k;
+                l = l < 0 ? 0 : (l >= p ? p - 1 : l);
                 v[u] = ok ? sm.sval[t + u] : T(0);
-                rows[u] = S + (int64_t)l * p;
+                rows[u] = S + l * p;
             }
             T x[4][CH];
 #pragma unroll
@@ -152,27 +153,40 @@ __device__ int build_support(WaveSm<T, LW> &sm, const ColState<T, LW> &st)
     return ns;
 }
 
-// Merge the np (ascending) pending violators into W (ascending), with
-// coefficient 0 for the new ones.  Requires w + np <= LW.
+// Merge the np ascending, distinct pending candidates into W (ascending),
+// with coefficient 0 for the new ones; candidates already in W are dropped.
+// Requires w + np <= LW.  Returns the number added.
 template <typename T, int LW>
-__device__ void merge_pending(WaveSm<T, LW> &sm, ColState<T, LW> &st, int np)
+__device__ int merge_pending(WaveSm<T, LW> &sm, ColState<T, LW> &st, int np)
 {
     const int lane = lane_id();
     const int w = st.w;
+    // drop members of W (np <= kPendMax = 64: one lane per candidate)
+    int v = lane < np ? sm.pend[lane] : 0;
+    bool keep = false;
+    if (lane < np) {
+        int pos = lds_lower_bound(sm.widx, w, v);
+        keep = !(pos < w && sm.widx[pos] == v);
+    }
+    unsigned long long m = __ballot(keep);
+    wave_sync();
+    if (keep) sm.pend[lanes_below(m)] = v;
+    wave_sync();
+    np = __popcll(m);
 #pragma unroll
     for (int s = 0; s < ColState<T, LW>::NS; ++s) {
         int q = s * kWave + lane;
         if (q < w) {
-            int v = sm.widx[q];
-            int pos = q + lds_lower_bound(sm.pend, np, v);
-            sm.tidx[pos] = v;
+            int vv = sm.widx[q];
+            int pos = q + lds_lower_bound(sm.pend, np, vv);
+            sm.tidx[pos] = vv;
             sm.tbeta[pos] = st.b[s];
         }
     }
     for (int i = lane; i < np; i += kWave) {
-        int v = sm.pend[i];
-        int pos = i + lds_lower_bound(sm.widx, w, v);
-        sm.tidx[pos] = v;
+        int vv = sm.pend[i];
+        int pos = i + lds_lower_bound(sm.widx, w, vv);
+        sm.tidx[pos] = vv;
         sm.tbeta[pos] = T(0);
     }
     wave_sync();
@@ -182,6 +196,7 @@ __device__ void merge_pending(WaveSm<T, LW> &sm, ColState<T, LW> &st, int np)
         sm.wbeta[q] = sm.tbeta[q];
     }
     wave_sync();
+    return np;
 }
 
 // Load s_W, beta (from sm.wbeta) and S_WW (LDS) for the current W from S.
@@ -195,7 +210,8 @@ __device__ void load_working_set(const T *__restrict__ S, int64_t p, int64_t k,
     for (int s = 0; s < ColState<T, LW>::NS; ++s) {
         int q = s * kWave + lane;
         if (q < w) {
-            int j = sm.widx[q];
+            int64_t j = sm.widx[q];
+            j = j < 0 ? 0 : (j >= p ? p - 1 : j);
             st.sv[s] = S[k * p + j];
             st.b[s] = sm.wbeta[q];
         } else {
@@ -207,7 +223,10 @@ __device__ void load_working_set(const T *__restrict__ S, int64_t p, int64_t k,
     const int tot = w * w;
     for (int e = lane; e < tot; e += kWave) {
         int qj = e / w, qi = e - qj * w;
-        sm.sww[qj * LW + qi] = S[(int64_t)sm.widx[qj] * p + sm.widx[qi]];
+        int64_t a = sm.widx[qj], b = sm.widx[qi];
+        a = a < 0 ? 0 : (a >= p ? p - 1 : a);
+        b = b < 0 ? 0 : (b >= p ? p - 1 : b);
+        sm.sww[qj * LW + qi] = S[a * p + b];
     }
     wave_sync();
 }
@@ -315,17 +334,55 @@ __device__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st, T lambda0,
     }
 }
 
-template <typename T, int LW>
-__device__ void store_column(const ColArgs<T> &A, int64_t k, WaveSm<T, LW> &sm,
-                             const ColState<T, LW> &st, int status)
+// In-wave sort of n <= 64 ints in LDS with duplicates removed (stable rank
+// sort, then compaction).  Returns the number of distinct values.
+__device__ __forceinline__ int sort_unique_small(int *a, int n)
 {
     const int lane = lane_id();
+    int v = lane < n ? a[lane] : 0;
+    int rank = 0;
+    for (int i = 0; i < n; ++i) {
+        int ai = a[i];
+        rank += (ai < v || (ai == v && i < lane)) ? 1 : 0;
+    }
+    wave_sync();
+    if (lane < n) a[rank] = v;
+    wave_sync();
+    int u = lane < n ? a[lane] : 0;
+    bool keep = lane < n && (lane == 0 || a[lane - 1] != u);
+    unsigned long long m = __ballot(keep);
+    wave_sync();
+    if (keep) a[lanes_below(m)] = u;
+    wave_sync();
+    return __popcll(m);
+}
+
+// Store a column's state: working set and coefficients (k-major), sigma,
+// lambda, status, and (with_support) the slot-major support list.
+template <typename T, int LW>
+__device__ void store_column(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm,
+                             const ColState<T, LW> &st, int status, bool with_support)
+{
+    const int lane = lane_id();
+    const int64_t p = A.p;
+    int ns = 0;
 #pragma unroll
     for (int s = 0; s < ColState<T, LW>::NS; ++s) {
         int q = s * kWave + lane;
-        if (q < st.w) {
+        bool in = q < st.w;
+        if (in) {
             A.w_idx[k * kWMax + q] = sm.widx[q];
             A.w_beta[k * kWMax + q] = st.b[s];
+        }
+        if (with_support) {
+            bool nz = in && st.b[s] != T(0);
+            unsigned long long m = __ballot(nz);
+            if (nz) {
+                int pos = ns + lanes_below(m);
+                A.supp_idx[(int64_t)pos * p + k] = sm.widx[q];
+                A.supp_val[(int64_t)pos * p + k] = st.b[s];
+            }
+            ns += __popcll(m);
         }
     }
     if (lane == 0) {
@@ -333,6 +390,7 @@ __device__ void store_column(const ColArgs<T> &A, int64_t k, WaveSm<T, LW> &sm,
         A.sigma[k] = (double)st.sigma;
         A.lam_used[k] = (double)st.lam_used;
         A.col_status[k] = status;
+        if (with_support) A.supp_cnt[k] = ns;
     }
 }
 

@@ -34,6 +34,7 @@ enum Counter : int {
 
 // Column status codes written by the kernels (mirror the public codes).
 enum ColStatus : int {
+    kColDeferred = 1,   // first solve done, KKT check left to the row-tiled pass
     kColOk = 0,
     kColDegenerate = -4,
     kColNoconv = -5,
@@ -134,25 +135,56 @@ struct ColArgs {
     T lambda0;
     T tol;               // delta: inner stop on max |change|, outer on |d sigma|
     T kkt_tol;           // a variable outside the working set violates when |g| > lambda + kkt_tol
-    T band;              // record j outside W with |g| > lambda - band (0: off)
+    T band;              // record j off the support with |g| > lambda - band (0: off)
     int max_outer, max_sweeps, max_rounds;
+    int mode;            // 0: fresh (screen + solve); 1: resume from the stored state
+    int defer_kkt;       // fresh mode: stop after the first solve (the row-tiled pass checks)
+    const int *work_list;// resume mode: columns work_list[0 .. *work_cnt)
+    const int *work_cnt;
     int *w_cnt;          // [p]
-    int *w_idx;          // [p * kWMax], sorted
+    int *w_idx;          // [p * kWMax], ascending
     T *w_beta;           // [p * kWMax]
     double *sigma;       // [p]
     double *lam_used;    // [p] lambda the stored coefficients solve
     int *col_status;     // [p]
+    int *supp_cnt;       // [p] support of the stored coefficients, slot-major:
+    int *supp_idx;       // supp_idx[q * p + k], q < supp_cnt[k]
+    T *supp_val;
+    int *pend_cnt;       // [p] violators handed between phases
+    int *pend_idx;       // [p * kPendMax]
     int *band_cnt;       // [p] or null
     int *band_idx;       // [p * kBandMax] or null
-    int *esc_cnt;        // escalation queue (tier 1 -> tier 2)
+    int *esc_cnt;        // escalation queue (32 -> 128 working set)
     int *esc_list;       // [p]
-    int resume;          // tier 2: process esc_list[0 .. *esc_cnt) from stored state
+    int *colinfo;        // [p * 4] per column: sigma updates, sweeps, updates, rounds
     unsigned long long *counters;
-    int *status_bits;    // |= 1 no convergence, 2 degenerate, 4 working set overflow
     const int *flags;    // nonzero: bad input, every wave exits at once
 };
+// tier: 0 = 32-wide working sets (escalating), 1 = 128-wide
 template <typename T>
-void launch_colsolve(const ColArgs<T> &a, hipStream_t s);
+void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s);
+
+// Row-tiled KKT pass over every column: stage rows of S in LDS once, check
+// g_jk = s_jk - sum_l S_jl beta_lk for all (j, k) (see kkt.hip).
+template <typename T>
+struct KktArgs {
+    const T *S;
+    int64_t p;
+    T kkt_tol, band;
+    const double *lam_used;
+    const int *col_status;
+    const int *w_cnt, *w_idx;
+    const int *supp_cnt, *supp_idx;
+    const T *supp_val;
+    int *pend_cnt, *pend_idx;
+    int *dirty_cnt, *dirty_list;
+    int *band_cnt, *band_idx;
+    const int *flags;
+};
+// rows per block that fit `lds_budget` bytes, 0 if one row does not fit
+int kkt_rows_per_block(int64_t p, size_t elem, size_t lds_budget);
+template <typename T>
+void launch_kkt_rows(const KktArgs<T> &a, int rj, hipStream_t s);
 
 // Double-precision polish of the float solution (mixed form).
 struct PolishArgs {
@@ -179,11 +211,17 @@ struct PolishArgs {
     double *sigma;
     double *lam_used;
     int *col_status;
-    unsigned long long *counters;
-    int *status_bits;
+    int *polinfo;           // [p * 8] per column: sigma updates, sweeps, updates, checks, added
     const int *flags;
 };
 void launch_polish(const PolishArgs &a, hipStream_t s);
+
+// Reduce the per-column counters and final statuses of one solve into the
+// control block: counters[kNumCounters] and status bits (1 no convergence,
+// 2 degenerate, 4 working set overflow).
+void launch_reduce_stats(int64_t p, const int *colinfo, const int *polinfo, const int *w_cnt,
+                         const int *col_status, unsigned long long *counters, int *status_bits,
+                         hipStream_t s);
 
 // Zero n 32-bit words (a kernel, so it is safe inside captured graphs).
 void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s);

@@ -29,6 +29,81 @@ void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s)
     hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, s, a, n);
 }
 
+// One block: sums and maxima of the per-column counters, status bits from
+// the final per-column statuses.
+__global__ __launch_bounds__(1024) void k_reduce_stats(int64_t p, const int *__restrict__ colinfo,
+                                                       const int *__restrict__ polinfo,
+                                                       const int *__restrict__ w_cnt,
+                                                       const int *__restrict__ col_status,
+                                                       unsigned long long *__restrict__ counters,
+                                                       int *__restrict__ status_bits)
+{
+    // outer, sweeps, updates, rounds, polish checks, polish added, noconv
+    unsigned long long sum[7] = {0, 0, 0, 0, 0, 0, 0};
+    int maxw = 0, maxo = 0, bits = 0;
+    for (int64_t k = threadIdx.x; k < p; k += blockDim.x) {
+        const int *ci = colinfo + k * 4;
+        int o = ci[0];
+        sum[0] += (unsigned)o;
+        sum[1] += (unsigned)ci[1];
+        sum[2] += (unsigned)ci[2];
+        sum[3] += (unsigned)ci[3];
+        if (polinfo) {
+            const int *pi = polinfo + k * 8;
+            o += pi[0];
+            sum[0] += (unsigned)pi[0];
+            sum[1] += (unsigned)pi[1];
+            sum[2] += (unsigned)pi[2];
+            sum[4] += (unsigned)pi[3];
+            sum[5] += (unsigned)pi[4];
+        }
+        maxo = o > maxo ? o : maxo;
+        maxw = w_cnt[k] > maxw ? w_cnt[k] : maxw;
+        int st = col_status[k];
+        if (st < 0) {
+            ++sum[6];
+            bits |= st == kColWorkset ? 4 : (st == kColDegenerate ? 2 : 1);
+        }
+    }
+    __shared__ unsigned long long red[7][1024];
+    __shared__ int redi[3][1024];
+    for (int i = 0; i < 7; ++i) red[i][threadIdx.x] = sum[i];
+    redi[0][threadIdx.x] = maxw;
+    redi[1][threadIdx.x] = maxo;
+    redi[2][threadIdx.x] = bits;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            for (int i = 0; i < 7; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + off];
+            int a = redi[0][threadIdx.x + off], b = redi[1][threadIdx.x + off];
+            redi[0][threadIdx.x] = redi[0][threadIdx.x] > a ? redi[0][threadIdx.x] : a;
+            redi[1][threadIdx.x] = redi[1][threadIdx.x] > b ? redi[1][threadIdx.x] : b;
+            redi[2][threadIdx.x] |= redi[2][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counters[kCntOuter] = red[0][0];
+        counters[kCntSweeps] = red[1][0];
+        counters[kCntUpdates] = red[2][0];
+        counters[kCntRounds] = red[3][0];
+        counters[kCntPolishChecks] = red[4][0];
+        counters[kCntPolishAdded] = red[5][0];
+        counters[kCntNoconv] = red[6][0];
+        counters[kCntMaxW] = (unsigned long long)redi[0][0];
+        counters[kCntMaxOuter] = (unsigned long long)redi[1][0];
+        *status_bits = redi[2][0];
+    }
+}
+
+void launch_reduce_stats(int64_t p, const int *colinfo, const int *polinfo, const int *w_cnt,
+                         const int *col_status, unsigned long long *counters, int *status_bits,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(1024), 0, s, p, colinfo, polinfo, w_cnt,
+                       col_status, counters, status_bits);
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ A, int64_t count)
 {
     typedef double dv2 __attribute__((ext_vector_type(2)));

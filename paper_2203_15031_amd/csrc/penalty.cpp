@@ -11,7 +11,7 @@
 // accurate to about 1e-16 relative.
 #include <math.h>
 
-#include "../../include/spmesl.h"
+#include "spmesl.h"
 
 namespace {
 

@@ -20,9 +20,14 @@
 namespace spmesl {
 
 // S_W'W' (LDS) and s_W' (registers) in double from Xt (p x n, standardised).
+__device__ __forceinline__ int64_t clamp_index(int v, int64_t p)
+{
+    return v < 0 ? 0 : (v >= p ? p - 1 : (int64_t)v);
+}
+
 template <int LW>
-__device__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t k,
-                                    WaveSm<double, LW> &sm, ColState<double, LW> &st)
+__device__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t p,
+                                    int64_t k, WaveSm<double, LW> &sm, ColState<double, LW> &st)
 {
     constexpr int NS = ColState<double, LW>::NS;
     const int lane = lane_id();
@@ -49,11 +54,11 @@ __device__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, in
                 int qi = t - qj * (qj - 1) / 2;
                 qa[u] = qi;
                 qb[u] = qj;
-                ra[u] = Xt + (int64_t)sm.widx[qi] * n;
-                rb[u] = Xt + (int64_t)sm.widx[qj] * n;
+                ra[u] = Xt + clamp_index(sm.widx[qi], p) * n;
+                rb[u] = Xt + clamp_index(sm.widx[qj], p) * n;
             } else if (t < P) {
                 qa[u] = t - ntri;
-                ra[u] = Xt + (int64_t)sm.widx[t - ntri] * n;
+                ra[u] = Xt + clamp_index(sm.widx[t - ntri], p) * n;
             }
         }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -129,6 +134,7 @@ __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64
             A.sigma[k] = 1.0;
             A.lam_used[k] = A.lambda0;
             A.col_status[k] = kColOk;
+            for (int i = 0; i < 8; ++i) A.polinfo[k * 8 + i] = 0;
         }
         return;
     }
@@ -142,7 +148,8 @@ __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64
     w32 = w32 < 0 ? 0 : (w32 > kWMax ? kWMax : w32);
     int nb = A.band_cnt[k];
     nb = nb < 0 ? 0 : nb;
-    bool full = nb > kBandMax || A.col_status32[k] != kColOk;
+    const int st32 = A.col_status32[k];
+    bool full = nb > kBandMax || (st32 != kColOk && st32 != kColDeferred);
     nb = nb < kBandMax ? nb : kBandMax;
     double norm32 = 0.0;
     int ns = 0;
@@ -162,6 +169,7 @@ __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64
     norm32 = wave_sum(norm32);
     for (int i = lane; i < nb; i += kWave) sm.pend[i] = A.band_idx[k * kBandMax + i];
     wave_sync();
+    nb = sort_unique_small(sm.pend, nb);  // the row-tiled pass appends in any order
     if (ns + nb > LW) {
         if (!tier2) {
             if (lane == 0) {
@@ -192,7 +200,7 @@ __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64
     const double lam32 = A.lam32[k];
 
     while (status == kColOk) {
-        load_working_set_xt(A.Xt, A.n, k, sm, st);
+        load_working_set_xt(A.Xt, A.n, A.p, k, sm, st);
         status = scaled_lasso_W(sm, st, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         if (status != kColOk) break;
         // bound on the change of any gradient outside W'
@@ -264,16 +272,12 @@ __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64
         A.sigma[k] = st.sigma;
         A.lam_used[k] = st.lam_used;
         A.col_status[k] = status;
-        atomicAdd(&A.counters[kCntPolishChecks], (unsigned long long)checks);
-        atomicAdd(&A.counters[kCntPolishAdded], (unsigned long long)added);
-        atomicAdd(&A.counters[kCntOuter], (unsigned long long)cnt.outer);
-        atomicAdd(&A.counters[kCntSweeps], (unsigned long long)cnt.sweeps);
-        atomicAdd(&A.counters[kCntUpdates], (unsigned long long)cnt.updates);
-        atomicMax(&A.counters[kCntMaxW], (unsigned long long)st.w);
-        if (status != kColOk) {
-            atomicAdd(&A.counters[kCntNoconv], 1ull);
-            atomicOr(A.status_bits, status == kColWorkset ? 4 : (status == kColDegenerate ? 2 : 1));
-        }
+        int *pi = A.polinfo + k * 8;
+        pi[0] = cnt.outer;
+        pi[1] = cnt.sweeps;
+        pi[2] = cnt.updates;
+        pi[3] = checks;
+        pi[4] = added;
     }
 }
 
