@@ -385,6 +385,11 @@ __device__ void store_column(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW>
             ns += __popcll(m);
         }
     }
+    if (with_support && lane >= ns && lane < kSuppPad) {
+        // pad the first slots so readers may load them without the count
+        A.supp_idx[(int64_t)lane * p + k] = (int)k;
+        A.supp_val[(int64_t)lane * p + k] = T(0);
+    }
     if (lane == 0) {
         A.w_cnt[k] = st.w;
         A.sigma[k] = (double)st.sigma;

@@ -15,6 +15,9 @@ constexpr int kWMax = 128;
 constexpr int kPendMax = 64;
 // Near-threshold candidates a float solve records for the double polish.
 constexpr int kBandMax = 32;
+// Support slots always written (padded with (k, 0)) so the row-tiled KKT pass
+// can load them without waiting for the count.
+constexpr int kSuppPad = 4;
 
 // Per-solve counters, accumulated with 64-bit atomics.
 enum Counter : int {

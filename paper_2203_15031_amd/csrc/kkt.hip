@@ -24,13 +24,25 @@ int kkt_rows_per_block(int64_t p, size_t elem, size_t lds_budget)
     return 0;
 }
 
-constexpr int kKktThreads = 1024;
-constexpr int kKktQ = 4;      // support entries preloaded per column
+constexpr int kKktThreads = 512;
+constexpr int kKktQ = kSuppPad;  // support entries preloaded per column
 
-template <typename T, int RJ>
-__device__ void kkt_check(const KktArgs<T> &A, int64_t k, int64_t j, T g, T lam, int cnt)
+// Rare path for one flagged pair (j, k): recompute g_jk from the staged row
+// and the column's support, then record a violation / band entry.
+template <typename T>
+__device__ __forceinline__ void kkt_flagged(const KktArgs<T> &A, int64_t k, int64_t j,
+                                         const T *__restrict__ row)
 {
     const int64_t p = A.p;
+    int cnt = A.supp_cnt[k];
+    cnt = cnt < 0 ? 0 : (cnt > kWMax ? kWMax : cnt);
+    const T lam = (T)A.lam_used[k];
+    T g = row[k];
+    for (int q = 0; q < cnt; ++q) {
+        int64_t l = A.supp_idx[(int64_t)q * p + k];
+        l = l < 0 ? 0 : (l >= p ? p - 1 : l);
+        g -= A.supp_val[(int64_t)q * p + k] * row[l];
+    }
     const T a = g < T(0) ? -g : g;
     const bool over = a > lam + A.kkt_tol;
     const bool near = A.band > T(0) && a > lam - A.band;
@@ -64,87 +76,168 @@ __device__ void kkt_check(const KktArgs<T> &A, int64_t k, int64_t j, T g, T lam,
     }
 }
 
-template <typename T, int RJ>
-__global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A)
+// Persistent blocks: block b owns rows [b * rpb, (b + 1) * rpb) of S.  For
+// each chunk of kKktThreads * CPT columns the block loads every thread's
+// CPT columns (support, lambda) into registers once, then streams its row
+// tiles of RJ rows through LDS, so S is read once per column chunk (once when
+// p <= kKktThreads * CPT) and the support lists once per block and chunk.
+template <typename T, int RJ, int CPT>
+__global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t rpb)
 {
     extern __shared__ __align__(16) unsigned char kkt_lds[];
     T *rows = reinterpret_cast<T *>(kkt_lds);
-    constexpr int kKktCols = sizeof(T) == 8 ? 2 : 4;  // columns a thread handles at once
     if (*A.flags) return;
     const int64_t p = A.p;
-    const int64_t j0 = (int64_t)blockIdx.x * RJ;
-    const int64_t nr = (p - j0) < RJ ? (p - j0) : RJ;
-    // rows j0 .. j0+nr-1 of S are contiguous
-    const T *src = A.S + j0 * p;
-    const int64_t tot = nr * p;
-    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) rows[e] = src[e];
-    __syncthreads();
-    for (int64_t kb = threadIdx.x; kb < p; kb += (int64_t)kKktCols * blockDim.x) {
-        int64_t kk[kKktCols];
-        int cnt[kKktCols];
-        T lam[kKktCols];
-        bool act[kKktCols];
-        // all metadata loads of the group first, then all support loads
+    const int64_t rb = (int64_t)blockIdx.x * rpb;
+    const int64_t re = rb + rpb < p ? rb + rpb : p;
+    if (rb >= p) return;
+    const int tid = threadIdx.x;
+    for (int64_t cbase = 0; cbase < p; cbase += (int64_t)CPT * kKktThreads) {
+        int64_t kk[CPT];
+        int cnt[CPT];
+        T lam[CPT];
+        bool act[CPT];
 #pragma unroll
-        for (int u = 0; u < kKktCols; ++u) {
-            kk[u] = kb + (int64_t)u * blockDim.x;
+        for (int u = 0; u < CPT; ++u) {
+            kk[u] = cbase + (int64_t)u * kKktThreads + tid;
             act[u] = kk[u] < p && A.col_status[kk[u]] == kColDeferred;
             cnt[u] = act[u] ? A.supp_cnt[kk[u]] : 0;
             cnt[u] = cnt[u] < 0 ? 0 : (cnt[u] > kWMax ? kWMax : cnt[u]);
             lam[u] = act[u] ? (T)A.lam_used[kk[u]] : T(0);
         }
-        int li[kKktCols][kKktQ];
-        T lv[kKktCols][kKktQ];
+        // the first kKktQ slots are always written (padding (k, 0) past the
+        // support), so these loads do not wait for the counts
+        int li[CPT][kKktQ];
+        T lv[CPT][kKktQ];
 #pragma unroll
-        for (int u = 0; u < kKktCols; ++u)
-#pragma unroll
-            for (int q = 0; q < kKktQ; ++q) {
-                bool ok = q < cnt[u];
-                li[u][q] = ok ? A.supp_idx[(int64_t)q * p + kk[u]] : 0;
-                lv[u][q] = ok ? A.supp_val[(int64_t)q * p + kk[u]] : T(0);
-            }
-#pragma unroll
-        for (int u = 0; u < kKktCols; ++u) {
-            if (!act[u]) continue;
-            const int64_t k = kk[u];
-            T acc[RJ];
-#pragma unroll
-            for (int r = 0; r < RJ; ++r) acc[r] = r < nr ? rows[r * p + k] : T(0);
+        for (int u = 0; u < CPT; ++u)
 #pragma unroll
             for (int q = 0; q < kKktQ; ++q) {
-                const int64_t l = li[u][q] < 0 ? 0 : (li[u][q] >= p ? p - 1 : li[u][q]);
-#pragma unroll
-                for (int r = 0; r < RJ; ++r)
-                    if (r < nr) acc[r] -= lv[u][q] * rows[r * p + l];
+                const int64_t kq = kk[u] < p ? kk[u] : 0;
+                int v = A.supp_idx[(int64_t)q * p + kq];
+                li[u][q] = v < 0 ? 0 : (v >= p ? (int)(p - 1) : v);
+                lv[u][q] = A.supp_val[(int64_t)q * p + kq];
             }
-            for (int q = kKktQ; q < cnt[u]; ++q) {
-                int64_t l = A.supp_idx[(int64_t)q * p + k];
-                l = l < 0 ? 0 : (l >= p ? p - 1 : l);
-                const T v = A.supp_val[(int64_t)q * p + k];
+        for (int64_t j0 = rb; j0 < re; j0 += RJ) {
+            const int64_t nr = (re - j0) < RJ ? (re - j0) : RJ;
+            __syncthreads();  // previous tile consumed
+            {
+                // rows j0 .. j0+nr-1 of S are contiguous: 16-byte loads, four in
+                // flight per thread before any is stored
+                const T *src = A.S + j0 * p;
+                const int64_t tot = nr * p;
+                constexpr int V = 16 / sizeof(T);
+                const bool aligned = ((uintptr_t)src & 15u) == 0;
+                const int64_t nvec = aligned ? tot / V : 0;
+                typedef __attribute__((ext_vector_type(4))) unsigned int u4;
+                const u4 *s4 = reinterpret_cast<const u4 *>(src);
+                u4 *d4 = reinterpret_cast<u4 *>(rows);
+                for (int64_t e0 = tid; e0 < nvec; e0 += 4 * (int64_t)kKktThreads) {
+                    u4 t[4];
 #pragma unroll
-                for (int r = 0; r < RJ; ++r)
-                    if (r < nr) acc[r] -= v * rows[r * p + l];
+                    for (int u = 0; u < 4; ++u) {
+                        int64_t e = e0 + (int64_t)u * kKktThreads;
+                        if (e < nvec) t[u] = s4[e];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        int64_t e = e0 + (int64_t)u * kKktThreads;
+                        if (e < nvec) d4[e] = t[u];
+                    }
+                }
+                for (int64_t e = nvec * V + tid; e < tot; e += kKktThreads) rows[e] = src[e];
             }
+            __syncthreads();
+            // gradients of every (row, column) pair; only a flag leaves the
+            // unrolled body
+            unsigned long long flagged = 0ull;
 #pragma unroll
-            for (int r = 0; r < RJ; ++r) {
-                const int64_t j = j0 + r;
-                if (r < nr && j != k) kkt_check<T, RJ>(A, k, j, acc[r], lam[u], cnt[u]);
+            for (int u = 0; u < CPT; ++u) {
+                if (!act[u]) continue;
+                const int64_t k = kk[u];
+                T acc[RJ];
+#pragma unroll
+                for (int r = 0; r < RJ; ++r) acc[r] = r < nr ? rows[r * p + k] : T(0);
+#pragma unroll
+                for (int q = 0; q < kKktQ; ++q)
+#pragma unroll
+                    for (int r = 0; r < RJ; ++r)
+                        if (r < nr) acc[r] -= lv[u][q] * rows[r * p + li[u][q]];
+                for (int q = kKktQ; q < cnt[u]; ++q) {
+                    int64_t l = A.supp_idx[(int64_t)q * p + k];
+                    l = l < 0 ? 0 : (l >= p ? p - 1 : l);
+                    const T v = A.supp_val[(int64_t)q * p + k];
+#pragma unroll
+                    for (int r = 0; r < RJ; ++r)
+                        if (r < nr) acc[r] -= v * rows[r * p + l];
+                }
+                const T lo_thr = A.band > T(0) ? lam[u] - A.band : lam[u] + A.kkt_tol;
+#pragma unroll
+                for (int r = 0; r < RJ; ++r) {
+                    const T a = acc[r] < T(0) ? -acc[r] : acc[r];
+                    if (r < nr && j0 + r != k && a > lo_thr) flagged |= 1ull << (u * RJ + r);
+                }
+            }
+            while (flagged) {
+                const int bit = __builtin_ctzll(flagged);
+                flagged &= flagged - 1;
+                const int u = bit / RJ, r = bit % RJ;
+                const int64_t k = cbase + (int64_t)u * kKktThreads + tid;
+                kkt_flagged<T>(A, k, j0 + r, rows + (int64_t)r * p);
             }
         }
     }
 }
 
+template <typename T, int RJ, int CPT>
+static void launch_kkt_rows_c(const KktArgs<T> &a, hipStream_t s)
+{
+    // one block per CU, each owning a contiguous range of rows
+    int64_t nblk = 256;
+    int64_t rpb = (a.p + nblk - 1) / nblk;
+    rpb = (rpb + RJ - 1) / RJ * RJ;
+    nblk = (a.p + rpb - 1) / rpb;
+    const size_t lds = (size_t)RJ * (size_t)a.p * sizeof(T);
+    hipLaunchKernelGGL((k_kkt_rows<T, RJ, CPT>), dim3((unsigned)nblk), dim3(kKktThreads), lds, s, a,
+                       rpb);
+}
+
+// rj: rows that fit in LDS.  Columns per thread: enough to cover p in one
+// chunk (S read once) within the register budget; rows per tile are then
+// capped so the unrolled gathers stay in registers.
 template <typename T>
 void launch_kkt_rows(const KktArgs<T> &a, int rj, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)((a.p + rj - 1) / rj);
-    const size_t lds = (size_t)rj * (size_t)a.p * sizeof(T);
-    const dim3 b(kKktThreads);
-    switch (rj) {
-    case 8: hipLaunchKernelGGL((k_kkt_rows<T, 8>), dim3(blocks), b, lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_kkt_rows<T, 4>), dim3(blocks), b, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_kkt_rows<T, 2>), dim3(blocks), b, lds, s, a); break;
-    default: hipLaunchKernelGGL((k_kkt_rows<T, 1>), dim3(blocks), b, lds, s, a); break;
+    const int64_t need = (a.p + kKktThreads - 1) / kKktThreads;
+    if constexpr (sizeof(T) == 4) {
+        if (need <= 4) {
+            if (rj >= 4) launch_kkt_rows_c<T, 4, 4>(a, s);
+            else if (rj == 2) launch_kkt_rows_c<T, 2, 4>(a, s);
+            else launch_kkt_rows_c<T, 1, 4>(a, s);
+        } else if (need <= 6) {
+            if (rj >= 4) launch_kkt_rows_c<T, 4, 6>(a, s);
+            else if (rj == 2) launch_kkt_rows_c<T, 2, 6>(a, s);
+            else launch_kkt_rows_c<T, 1, 6>(a, s);
+        } else {
+            if (rj >= 2) launch_kkt_rows_c<T, 2, 10>(a, s);
+            else launch_kkt_rows_c<T, 1, 10>(a, s);
+        }
+    } else {
+        if (need <= 2) {
+            if (rj >= 8) launch_kkt_rows_c<T, 8, 2>(a, s);
+            else if (rj == 4) launch_kkt_rows_c<T, 4, 2>(a, s);
+            else if (rj == 2) launch_kkt_rows_c<T, 2, 2>(a, s);
+            else launch_kkt_rows_c<T, 1, 2>(a, s);
+        } else if (need <= 4) {
+            if (rj >= 4) launch_kkt_rows_c<T, 4, 4>(a, s);
+            else if (rj == 2) launch_kkt_rows_c<T, 2, 4>(a, s);
+            else launch_kkt_rows_c<T, 1, 4>(a, s);
+        } else if (need <= 6) {
+            if (rj >= 2) launch_kkt_rows_c<T, 2, 6>(a, s);
+            else launch_kkt_rows_c<T, 1, 6>(a, s);
+        } else {
+            launch_kkt_rows_c<T, 1, 8>(a, s);
+        }
     }
 }
 

@@ -24,7 +24,21 @@ __global__ __launch_bounds__(256) void k_colstats_partial(const double *__restri
     int64_t i0 = (int64_t)r * rows_per;
     int64_t i1 = i0 + rows_per < n ? i0 + rows_per : n;
     double s1 = 0.0, s2 = 0.0;
-    for (int64_t i = i0; i < i1; ++i) {
+    int64_t i = i0;
+    for (; i + 4 <= i1; i += 4) {
+        double x0 = X[i * ldx + j], x1 = X[(i + 1) * ldx + j];
+        double x2 = X[(i + 2) * ldx + j], x3 = X[(i + 3) * ldx + j];
+        double d0 = x0 - K, d1 = x1 - K, d2 = x2 - K, d3 = x3 - K;
+        s1 += d0;
+        s2 += d0 * d0;
+        s1 += d1;
+        s2 += d1 * d1;
+        s1 += d2;
+        s2 += d2 * d2;
+        s1 += d3;
+        s2 += d3 * d3;
+    }
+    for (; i < i1; ++i) {
         double d = X[i * ldx + j] - K;
         s1 += d;
         s2 += d * d;
@@ -45,9 +59,20 @@ __global__ __launch_bounds__(256) void k_colstats_final(const double *__restrict
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= p) return;
     double s1 = 0.0, s2 = 0.0;
-    for (int r = 0; r < rchunks; ++r) {
-        s1 += partial[(2 * (int64_t)r) * p + j];
-        s2 += partial[(2 * (int64_t)r + 1) * p + j];
+    // fixed summation order; loads issued eight chunks at a time
+    for (int r0 = 0; r0 < rchunks; r0 += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int r = r0 + u;
+            a[u] = r < rchunks ? partial[(2 * (int64_t)r) * p + j] : 0.0;
+            b[u] = r < rchunks ? partial[(2 * (int64_t)r + 1) * p + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s1 += a[u];
+            s2 += b[u];
+        }
     }
     double K = X[j];
     double nn = (double)n;

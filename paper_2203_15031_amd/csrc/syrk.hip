@@ -61,7 +61,7 @@ __device__ __forceinline__ void tile_of_block(int T, int *bj, int *bk)
     *bk = row + t;
 }
 
-constexpr int kSyrkKC = 16;
+constexpr int kSyrkKC = 32;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int64_t n, int64_t p,
@@ -86,17 +86,33 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
 
-    // loader mapping: 16 rows x 64 columns, 4 consecutive columns per thread
+    // loader mapping: rows lr and lr + 16 of the chunk, 4 consecutive columns
     const int lr = tid >> 4, lc = (tid & 15) * 4;
-    for (int64_t i0 = 0; i0 < n; i0 += kSyrkKC) {
-        int64_t i = i0 + lr;
+    constexpr int NL = kSyrkKC / 16;
+    T ra[NL][4], rb[NL][4];
+    auto fetch = [&](int64_t i0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int64_t ja = j0 + lc + e, kb = k0 + lc + e;
-            sm.in.a[lr][lc + e] = (i < n && ja < p) ? Xs[i * p + ja] : T(0);
-            sm.in.b[lr][lc + e] = (i < n && kb < p) ? Xs[i * p + kb] : T(0);
+        for (int h = 0; h < NL; ++h) {
+            int64_t i = i0 + lr + 16 * h;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int64_t ja = j0 + lc + e, kb = k0 + lc + e;
+                ra[h][e] = (i < n && ja < p) ? Xs[i * p + ja] : T(0);
+                rb[h][e] = (i < n && kb < p) ? Xs[i * p + kb] : T(0);
+            }
         }
+    };
+    fetch(0);
+    for (int64_t i0 = 0; i0 < n; i0 += kSyrkKC) {
+#pragma unroll
+        for (int h = 0; h < NL; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sm.in.a[lr + 16 * h][lc + e] = ra[h][e];
+                sm.in.b[lr + 16 * h][lc + e] = rb[h][e];
+            }
         __syncthreads();
+        if (i0 + kSyrkKC < n) fetch(i0 + kSyrkKC);  // in flight during the MFMAs below
 #pragma unroll
         for (int kk = 0; kk < kSyrkKC; kk += 4) {
             T av[2], bv[2];
@@ -185,26 +201,32 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
 
     // loader: 128 vars x 64 samples per panel; thread -> (var = tid/2, half)
     const int lv = tid >> 1, lh = (tid & 1) * 32;
-    for (int64_t i0 = 0; i0 < npad; i0 += kBfKC) {
+    uint4 pre[4][4];
+    auto fetch = [&](int64_t i0) {
 #pragma unroll
         for (int pnl = 0; pnl < 4; ++pnl) {
             const uint16_t *src = (pnl & 1) ? lo : hi;
             int64_t v = ((pnl < 2) ? j0 : k0) + lv;
-            uint4 q0 = {0, 0, 0, 0}, q1 = q0, q2 = q0, q3 = q0;
             if (v < p) {
                 const uint4 *g = reinterpret_cast<const uint4 *>(src + v * npad + i0 + lh);
-                q0 = g[0];
-                q1 = g[1];
-                q2 = g[2];
-                q3 = g[3];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pre[pnl][q] = g[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pre[pnl][q] = uint4{0, 0, 0, 0};
             }
+        }
+    };
+    fetch(0);
+    for (int64_t i0 = 0; i0 < npad; i0 += kBfKC) {
+#pragma unroll
+        for (int pnl = 0; pnl < 4; ++pnl) {
             uint4 *d = reinterpret_cast<uint4 *>(&sm.in[pnl][lv * kBfLd + lh]);
-            d[0] = q0;
-            d[1] = q1;
-            d[2] = q2;
-            d[3] = q3;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d[q] = pre[pnl][q];
         }
         __syncthreads();
+        if (i0 + kBfKC < npad) fetch(i0 + kBfKC);  // in flight during the MFMAs below
 #pragma unroll
         for (int kk = 0; kk < kBfKC; kk += 32) {
             bf8 ha[4], la[4], hb[4], lb[4];
