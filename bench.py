@@ -121,6 +121,36 @@ def cpu_baseline(X_np, lam0, tol, target_s=20.0):
                       f"Omega assembly excluded"}
 
 
+def bench_batch(args, torch, spmesl, workloads):
+    """The batched hub workload: 64 data sets of uneven shape, one library call per step."""
+    Xs_np = workloads.generate_batch()
+    Xs = [torch.from_numpy(X).to("cuda:0") for X in Xs_np]
+    lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs_np]
+    ctx = spmesl.Context(0)
+    line = {"metric": "batched SPMESL data sets/s (64 hub data sets, p~U{256..4096}, n=ceil(p/2))",
+            "unit": "datasets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+            "config": {"workload": "hub_batch64", "count": len(Xs), "sum_p": int(sum(X.shape[1] for X in Xs_np)),
+                       "tol": 1e-8}}
+    for prec in args.forms.split(","):
+        for _ in range(args.warmup):
+            ctx.solve_batch(Xs, lams, 1e-8, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.solve_batch(Xs, lams, 1e-8, prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / args.steps
+        line.setdefault("forms", {})[prec] = {"ms_per_step": round(ms, 3),
+                                              "datasets_per_s": round(len(Xs) * 1000 / ms, 2)}
+        print(f"[bench] batch {prec}: {ms:.3f} ms per 64 data sets", file=sys.stderr, flush=True)
+    head = args.forms.split(",")[0]
+    line["value"] = line["forms"][head]["datasets_per_s"]
+    line["ms_per_step"] = line["forms"][head]["ms_per_step"]
+    line["dtype"] = {"mixed": "bf16x3-f32+f64", "fp64": "f64", "fp32": "f32"}[head]
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +158,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="blockar_n400_p5000 (headline), sf_n1000_p20000, or hub_batch64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -138,8 +170,10 @@ def main():
     import torch
     from paper_2203_15031_amd import spmesl, workloads
 
-    w = workloads.workload(WORKLOAD)
-    X_np = workloads.generate(WORKLOAD)
+    if args.workload == "hub_batch64":
+        return bench_batch(args, torch, spmesl, workloads)
+    w = workloads.workload(args.workload)
+    X_np = workloads.generate(args.workload)
     X = torch.from_numpy(X_np).to("cuda:0")
     lam0, tol = w.lambda0, w.tol
     ctx = spmesl.Context(0)
@@ -169,7 +203,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"mixed": "bf16x3-f32+f64", "fp64": "f64", "fp32": "f32"}[head],
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": w.n, "p": w.p, "lambda0": round(lam0, 6),
+        "config": {"workload": args.workload, "n": w.n, "p": w.p, "lambda0": round(lam0, 6),
                    "tol": tol, "precision": head},
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
         "roofline": roof,

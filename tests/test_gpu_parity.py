@@ -236,3 +236,43 @@ def test_blockar_p5000_sampled_columns(ctx, prec, bar):
     rO = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision=prec, want=("Omega",))
     Om = host(rO.Omega)
     assert np.array_equal(Om, Om.T)
+
+
+# ---------------------------------------------------------------------------
+# batched data sets and the p = 20000 workload
+# ---------------------------------------------------------------------------
+
+def test_solve_batch_matches_single_solves(ctx):
+    from paper_2203_15031_amd import workloads as Wk
+    Xs = Wk.generate_batch(count=6, seed=3, pmin=64, pmax=300)
+    lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs]
+    Xg = [gpu(X) for X in Xs]
+    for prec in ("fp64", "mixed"):
+        res = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec)
+        for X, Xd, lam, r in zip(Xs, Xg, lams, res):
+            assert r.status == 0
+            one = ctx.solve(Xd, lam, tol=1e-8, precision=prec)
+            assert torch.equal(r.Omega, one.Omega) and torch.equal(r.B, one.B)
+    # and against the oracle on two of them
+    for i in (0, 3):
+        ref = oracle.spmesl(Xs[i], lams[i], tol=1e-12)
+        r = ctx.solve(Xg[i], lams[i], tol=1e-8, precision="mixed")
+        assert rel_err(host(r.Omega), ref["Omega"]) <= 1e-4
+
+
+@pytest.mark.parametrize("prec,bar", [("mixed", 1e-4), ("fp64", 1e-6)])
+def test_scale_free_p20000_sampled_columns(ctx, prec, bar):
+    w = W.workload("sf_n1000_p20000")
+    X = W.generate(w.name)
+    r = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision=prec, output_scale="standardized",
+                  want=("B", "sigma"))
+    assert r.status == 0
+    rng = np.random.default_rng(1)
+    cols = np.sort(rng.choice(w.p, size=12, replace=False))
+    ref = oracle.spmesl_columns(X, w.lambda0, cols, tol=1e-12, nthreads=0)
+    assert ref["status"] == 0
+    B = r.B[:, torch.from_numpy(cols).to(DEV)].cpu().numpy()
+    sig = host(r.sigma)[cols]
+    for i in range(len(cols)):
+        assert rel_err(B[:, i], ref["B"][:, i]) <= bar
+        assert abs(sig[i] - ref["sigma"][i]) <= bar * ref["sigma"][i]
