@@ -38,7 +38,11 @@ struct Ctl {
 static_assert(sizeof(Ctl) % 4 == 0, "Ctl is zeroed as 32-bit words");
 static_assert(kNumCounters <= 16, "counter slots");
 
+// Mixed form: the float solve stops at kMixedFloatTol and records the
+// near-threshold band of width kMixedBand for the double polish, which then
+// meets the caller's tolerance.
 constexpr double kMixedBand = 4e-3;
+constexpr double kMixedFloatTol = 1e-5;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -339,7 +343,9 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     if (L.prec == SPMESL_FP64)
         enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s);
     else
-        enqueue_columns<float>(L, ws, dctl, opt, std::max(opt->tol, (double)SPMESL_FP32_TOL_FLOOR),
+        enqueue_columns<float>(L, ws, dctl, opt,
+                               std::max(opt->tol, L.prec == SPMESL_MIXED ? kMixedFloatTol
+                                                                         : (double)SPMESL_FP32_TOL_FLOOR),
                                L.prec == SPMESL_MIXED ? kMixedBand : 0.0, max_outer, max_sweeps,
                                max_rounds, s);
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));

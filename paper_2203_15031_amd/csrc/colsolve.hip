@@ -74,7 +74,7 @@ __device__ void record_info(const ColArgs<T> &A, int64_t k, const SolveCounts &c
 }
 
 template <typename T, int LW>
-__device__ void escalate(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm,
+__device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm,
                          const ColState<T, LW> &st, int np, const SolveCounts &cnt, int rounds)
 {
     const int lane = lane_id();
@@ -90,7 +90,7 @@ __device__ void escalate(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm
 }
 
 template <typename T, int LW>
-__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier)
+__device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier)
 {
     const int lane = lane_id();
     if (*A.flags) {
@@ -111,6 +111,7 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, 
     const int64_t p = A.p;
     const bool band = A.band > T(0);
     ColState<T, LW> st;
+    unsigned rlo[ColState<T, LW>::kRows], rhi[ColState<T, LW>::kRowsHi];
     SolveCounts cnt = {0, 0, 0};
     int rounds = 0, status = kColOk;
     bool deferred = false;
@@ -153,13 +154,13 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, 
             if (np > 0) {
                 ++rounds;
                 merge_pending(sm, st, np);
-                load_working_set(A.S, p, k, sm, st);
-                status = scaled_lasso_W(sm, st, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+                load_working_set(A.S, p, k, sm, st, rlo, rhi);
+                status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
             } else {
                 status = kColWorkset;
             }
         } else {
-            load_working_set(A.S, p, k, sm, st);
+            load_working_set(A.S, p, k, sm, st, rlo, rhi);
         }
     }
 
@@ -186,8 +187,8 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, 
         }
         ++rounds;
         merge_pending(sm, st, np);
-        load_working_set(A.S, p, k, sm, st);
-        status = scaled_lasso_W(sm, st, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+        load_working_set(A.S, p, k, sm, st, rlo, rhi);
+        status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         if (A.mode == 0 && A.defer_kkt && status == kColOk) {
             deferred = true;
             break;

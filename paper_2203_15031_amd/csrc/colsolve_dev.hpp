@@ -31,10 +31,61 @@ struct WaveSm {
 template <typename T, int LW>
 struct ColState {
     static constexpr int NS = (LW + kWave - 1) / kWave;  // slots per lane
+    // working sets of up to 32 keep lane i's row of S_WW in registers,
+    // indexed by the (wave-uniform) coordinate being updated
+    static constexpr bool kRegRows = LW <= 32;
+    static constexpr int kRows = kRegRows ? LW : 1;
+    static constexpr int kRowsHi = (kRegRows && sizeof(T) == 8) ? LW : 1;
     T g[NS], b[NS], sv[NS];
     int w;
     T sigma, lam_used;
 };
+
+// Copy lane i's row of S_WW from LDS into registers (zero beyond w).
+// Register rows: lane i's row of S_WW, indexed by a wave-uniform coordinate.
+// The row is held as raw 32-bit words (two arrays for doubles: low and high
+// halves) declared directly in the caller; the compiler keeps such arrays in
+// registers and indexes them with s_set_gpr_idx, where an array inside a
+// struct, or an array of 64-bit elements, goes to scratch.
+template <typename T> __device__ __forceinline__ T row_get(const unsigned *lo, const unsigned *hi, int q);
+template <> __device__ __forceinline__ float row_get<float>(const unsigned *lo, const unsigned *, int q)
+{
+    return __uint_as_float(lo[q]);
+}
+template <> __device__ __forceinline__ double row_get<double>(const unsigned *lo, const unsigned *hi, int q)
+{
+    return __longlong_as_double(((long long)hi[q] << 32) | (unsigned long long)lo[q]);
+}
+__device__ __forceinline__ void row_set(unsigned *lo, unsigned *, int q, float x) { lo[q] = __float_as_uint(x); }
+__device__ __forceinline__ void row_set(unsigned *lo, unsigned *hi, int q, double x)
+{
+    long long b = __double_as_longlong(x);
+    lo[q] = (unsigned)(b & 0xffffffffll);
+    hi[q] = (unsigned)((unsigned long long)b >> 32);
+}
+
+template <typename T, int LW>
+__device__ __forceinline__ void rows_to_registers(const WaveSm<T, LW> &sm, const ColState<T, LW> &st,
+                                                  unsigned *rlo, unsigned *rhi)
+{
+    if constexpr (ColState<T, LW>::kRegRows) {
+        const int lane = lane_id();
+        const bool in = lane < st.w;
+#pragma unroll
+        for (int q = 0; q < LW; ++q) row_set(rlo, rhi, q, (in && q < st.w) ? sm.sww[q * LW + lane] : T(0));
+    }
+}
+
+// Soft_lambda(a) as a - clamp(a, -lambda, lambda): the same value as the
+// branch form (a - lambda, a + lambda or exactly 0).
+__device__ __forceinline__ float soft_clamp(float a, float lam)
+{
+    return a - __builtin_amdgcn_fmed3f(a, -lam, lam);
+}
+__device__ __forceinline__ double soft_clamp(double a, double lam)
+{
+    return a - fmax(fmin(a, lam), -lam);
+}
 
 // lower_bound over an ascending int array in LDS
 __device__ __forceinline__ int lds_lower_bound(const int *a, int n, int v)
@@ -133,7 +184,7 @@ __device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T
 
 // Support list (nonzero coefficients, ascending) from the slot registers.
 template <typename T, int LW>
-__device__ int build_support(WaveSm<T, LW> &sm, const ColState<T, LW> &st)
+__device__ __forceinline__ int build_support(WaveSm<T, LW> &sm, const ColState<T, LW> &st)
 {
     const int lane = lane_id();
     int ns = 0;
@@ -157,7 +208,7 @@ __device__ int build_support(WaveSm<T, LW> &sm, const ColState<T, LW> &st)
 // with coefficient 0 for the new ones; candidates already in W are dropped.
 // Requires w + np <= LW.  Returns the number added.
 template <typename T, int LW>
-__device__ int merge_pending(WaveSm<T, LW> &sm, ColState<T, LW> &st, int np)
+__device__ __forceinline__ int merge_pending(WaveSm<T, LW> &sm, ColState<T, LW> &st, int np)
 {
     const int lane = lane_id();
     const int w = st.w;
@@ -201,8 +252,9 @@ __device__ int merge_pending(WaveSm<T, LW> &sm, ColState<T, LW> &st, int np)
 
 // Load s_W, beta (from sm.wbeta) and S_WW (LDS) for the current W from S.
 template <typename T, int LW>
-__device__ void load_working_set(const T *__restrict__ S, int64_t p, int64_t k,
-                                 WaveSm<T, LW> &sm, ColState<T, LW> &st)
+__device__ __forceinline__ void load_working_set(const T *__restrict__ S, int64_t p, int64_t k,
+                                 WaveSm<T, LW> &sm, ColState<T, LW> &st,
+                                 unsigned *rlo, unsigned *rhi)
 {
     const int lane = lane_id();
     const int w = st.w;
@@ -229,11 +281,13 @@ __device__ void load_working_set(const T *__restrict__ S, int64_t p, int64_t k,
         sm.sww[qj * LW + qi] = S[a * p + b];
     }
     wave_sync();
+    rows_to_registers(sm, st, rlo, rhi);
 }
 
 // g = s_W - S_WW beta, from scratch.
 template <typename T, int LW>
-__device__ void fresh_gradient(WaveSm<T, LW> &sm, ColState<T, LW> &st)
+__device__ __forceinline__ void fresh_gradient(WaveSm<T, LW> &sm, ColState<T, LW> &st,
+                                               const unsigned *rlo, const unsigned *rhi)
 {
     constexpr int NS = ColState<T, LW>::NS;
     const int lane = lane_id();
@@ -247,10 +301,14 @@ __device__ void fresh_gradient(WaveSm<T, LW> &sm, ColState<T, LW> &st)
             m &= m - 1;
             int qq = s2 * kWave + l;
             T bq = bcast(st.b[s2], l);
+            if constexpr (ColState<T, LW>::kRegRows) {
+                st.g[0] -= row_get<T>(rlo, rhi, qq) * bq;
+            } else {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                int q = s * kWave + lane;
-                if (q < LW) st.g[s] -= sm.sww[qq * LW + q] * bq;
+                for (int s = 0; s < NS; ++s) {
+                    int q = s * kWave + lane;
+                    if (q < LW) st.g[s] -= sm.sww[qq * LW + q] * bq;
+                }
             }
         }
     }
@@ -263,8 +321,10 @@ struct SolveCounts {
 // Algorithm 1 on the working set: outer sigma loop around cyclic sweeps.
 // Returns kColOk, kColNoconv or kColDegenerate.
 template <typename T, int LW>
-__device__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st, T lambda0, T tol,
-                              int max_outer, int max_sweeps, SolveCounts &cnt)
+__device__ __forceinline__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st,
+                                              const unsigned *rlo, const unsigned *rhi,
+                                              T lambda0, T tol, int max_outer, int max_sweeps,
+                                              SolveCounts &cnt)
 {
     constexpr int NS = ColState<T, LW>::NS;
     const int lane = lane_id();
@@ -272,8 +332,35 @@ __device__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st, T lambda0,
         if (cnt.outer >= max_outer) return kColNoconv;
         ++cnt.outer;
         const T lam = st.sigma * lambda0;
-        fresh_gradient(sm, st);
+        fresh_gradient(sm, st, rlo, rhi);
         bool inner_ok = false;
+        if constexpr (ColState<T, LW>::kRegRows) {
+            // lanes at or beyond w hold b = g = 0 and a zero row, so their
+            // change is always 0 and needs no mask
+            for (int m = 0; m < max_sweeps; ++m) {
+                ++cnt.sweeps;
+                T maxd = T(0);
+                unsigned long long live = ~0ull;   // coordinates after the last update
+                for (;;) {
+                    const T nb = soft_clamp(st.g[0] + st.b[0], lam);
+                    const T d = nb - st.b[0];
+                    const unsigned long long mk = __ballot(d != T(0)) & live;
+                    if (!mk) break;
+                    const int qs = __builtin_ffsll((long long)mk) - 1;
+                    const T dd = bcast(d, qs);
+                    if (lane == qs) st.b[0] = nb;
+                    st.g[0] -= row_get<T>(rlo, rhi, qs) * dd;
+                    const T ad = dd < T(0) ? -dd : dd;
+                    maxd = ad > maxd ? ad : maxd;
+                    live = qs >= 63 ? 0ull : (~0ull << (qs + 1));
+                    ++cnt.updates;
+                }
+                if (maxd < tol) {
+                    inner_ok = true;
+                    break;
+                }
+            }
+        } else
         for (int m = 0; m < max_sweeps; ++m) {
             ++cnt.sweeps;
             T maxd = T(0);
@@ -284,7 +371,7 @@ __device__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st, T lambda0,
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     int q = s * kWave + lane;
-                    nb[s] = soft_threshold(st.g[s] + st.b[s], lam);
+                    nb[s] = soft_clamp(st.g[s] + st.b[s], lam);
                     d[s] = nb[s] - st.b[s];
                     bool nz = q < st.w && q > cur && d[s] != T(0);
                     unsigned long long mk = __ballot(nz);
@@ -360,7 +447,7 @@ __device__ __forceinline__ int sort_unique_small(int *a, int n)
 // Store a column's state: working set and coefficients (k-major), sigma,
 // lambda, status, and (with_support) the slot-major support list.
 template <typename T, int LW>
-__device__ void store_column(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm,
+__device__ __forceinline__ void store_column(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm,
                              const ColState<T, LW> &st, int status, bool with_support)
 {
     const int lane = lane_id();

@@ -26,8 +26,9 @@ __device__ __forceinline__ int64_t clamp_index(int v, int64_t p)
 }
 
 template <int LW>
-__device__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t p,
-                                    int64_t k, WaveSm<double, LW> &sm, ColState<double, LW> &st)
+__device__ __forceinline__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t p,
+                                    int64_t k, WaveSm<double, LW> &sm, ColState<double, LW> &st,
+                                    unsigned *rlo, unsigned *rhi)
 {
     constexpr int NS = ColState<double, LW>::NS;
     const int lane = lane_id();
@@ -81,6 +82,7 @@ __device__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, in
     }
     for (int q = lane; q < w; q += kWave) sm.sww[q * LW + q] = 1.0;
     wave_sync();
+    rows_to_registers(sm, st, rlo, rhi);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int q = s * kWave + lane;
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kWave *NW) void k_polish(PolishArgs A, int tier2)
 }
 
 template <int LW>
-__device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64_t k, int tier2)
+__device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64_t k, int tier2)
 {
     constexpr int NS = ColState<double, LW>::NS;
     const int lane = lane_id();
@@ -140,6 +142,7 @@ __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64
     }
     const int64_t p = A.p;
     ColState<double, LW> st;
+    unsigned rlo[ColState<double, LW>::kRows], rhi[ColState<double, LW>::kRowsHi];
     SolveCounts cnt = {0, 0, 0};
     int status = kColOk, rounds = 0, checks = 0, added = 0;
 
@@ -200,8 +203,8 @@ __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64
     const double lam32 = A.lam32[k];
 
     while (status == kColOk) {
-        load_working_set_xt(A.Xt, A.n, A.p, k, sm, st);
-        status = scaled_lasso_W(sm, st, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+        load_working_set_xt(A.Xt, A.n, A.p, k, sm, st, rlo, rhi);
+        status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         if (status != kColOk) break;
         // bound on the change of any gradient outside W'
         double part = 0.0, nrm = 0.0;
