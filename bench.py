@@ -5,7 +5,10 @@ Omega, B and sigma written to HBM) of the block-AR(1) workload
 (n = 400, p = 5000, 50 blocks of 100 with AR(1) covariance rho = 0.6,
 lambda0 = sqrt(2 log p / n), tol 1e-8), with X already resident in HBM.
 The headline is the mixed-precision form; the plain double form is timed
-beside it.  Prints one JSON line.
+beside it.  `value` is the throughput of K solves enqueued back to back
+(each the replay of the solve's HIP graph) and synchronised once; the rate
+of one call at a time (each waiting for its result) is reported beside it.
+Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -27,45 +30,45 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 WORKLOAD = "blockar_n400_p5000"
 
 
-def phase_costs(n, p, prec, stats):
-    """Algorithmic work per phase: (bytes, flops, flop dtype)."""
-    npad = (n + 63) // 64 * 64
+def kernel_costs(n, p, prec):
+    """Algorithmic work of one launch of each kernel step: (bytes, flops, flop dtype).
+
+    S = Xs^T Xs / n needs n p (p + 1) flops (the upper triangle, one
+    multiply-add per sample and pair); the mixed form issues three bf16
+    products per term.  The screen of the first solves reads row k of S for
+    every column (p rows), and the row-tiled KKT pass reads S once; the zero
+    fill writes one dense p x p double output.
+    """
     tsz = 8 if prec == "fp64" else 4
-    ws = stats["total_updates"]
-    out = {}
-    # standardise: read X, write the form the covariance reads
-    wrote = {"fp64": 8 * n * p, "fp32": 4 * n * p, "mixed": 8 * n * p + 4 * npad * p}[prec]
-    out["standardize"] = (8 * n * p * 2 + wrote, 0.0, None)
-    # covariance: n p (p + 1) multiply-adds counted as 2 flops per symmetric
-    # entry pair; the mixed form issues three bf16 products per term
     fl = float(n) * p * (p + 1)
-    if prec == "mixed":
-        out["covariance"] = (2 * n * p * 2 + tsz * p * p, 3 * fl, "bf16")
-    else:
-        out["covariance"] = (tsz * n * p * 2 + tsz * p * p, fl, prec)
-    # solve: one read of row k of S per column (the screening pass) plus the
-    # support rows of each further KKT pass are the algorithmic floor
-    out["solve"] = (tsz * p * p, 0.0, None)
-    out["polish"] = (0.0, 0.0, None)
-    # outputs: dense B and Omega (p x p double) and sigma
-    out["output"] = (16 * p * p + 8 * p, 0.0, None)
-    return out
+    syrk = {"fp64": ("syrk_f64", (8.0 * p * p, fl, "fp64")),
+            "fp32": ("syrk_f32", (4.0 * p * p, fl, "fp32")),
+            "mixed": ("syrk_bf16x3", (4.0 * p * p, 3 * fl, "bf16"))}[prec]
+    return {
+        syrk[0]: syrk[1],
+        "colsolve_first": (float(tsz) * p * p, 0.0, None),
+        "kkt_rows": (float(tsz) * p * p, 0.0, None),
+        "fill_B": (8.0 * p * p, 0.0, None),
+        "fill_Omega": (8.0 * p * p, 0.0, None),
+    }
 
 
-def roofline_of(phase, ms, costs):
-    nbytes, flops, fdt = costs[phase]
+def roofline_of(name, ms, cost):
+    """Roofline of one kernel launch: algorithmic bytes or flops / its time."""
+    nbytes, flops, fdt = cost
     t = ms * 1e-3
     t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
     t_mfma = flops / (PEAK_TFLOPS[fdt] * 1e12) if fdt else 0.0
     if t_mfma > t_hbm:
         ach = flops / t / 1e12
         peak = PEAK_TFLOPS[fdt]
-        return {"kernel": phase, "bound": "mfma", "achieved": round(ach, 2), "peak": peak,
+        return {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
-                "dtype": fdt}
+                "dtype": fdt, "ms_per_launch": round(ms, 5)}
     ach = nbytes / t / 1e9
-    return {"kernel": phase, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None}
+    return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+            "ms_per_launch": round(ms, 5)}
 
 
 def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
@@ -73,26 +76,49 @@ def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
     out = dict(B=torch.empty((p, p), dtype=torch.float64, device=X.device),
                sigma=torch.empty((p,), dtype=torch.float64, device=X.device),
                Omega=torch.empty((p, p), dtype=torch.float64, device=X.device))
+    status = torch.full((1,), 99, dtype=torch.int32, device=X.device)
     for _ in range(warmup):
         ctx.solve(X, lam0, tol, prec, out=out)
+        ctx.solve_async(X, lam0, status, tol, prec, out=out)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    # the job: K full solves enqueued back to back (each one replay of the
+    # solve's HIP graph), then one synchronisation
+    status.fill_(99)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.solve_async(X, lam0, status, tol, prec, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if int(status.item()) != 0:
+        raise RuntimeError(f"{prec} solve returned status {int(status.item())}")
+    # one call at a time: each call waits for its solve and reads its status
     e0.record(stream)
     for _ in range(steps):
         r = ctx.solve(X, lam0, tol, prec, out=out)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    # a separate pass with the library's per-phase HIP events (same stream)
+    ms_sync = e0.elapsed_time(e1) / steps
+    # the same solves with the library's HIP events: per phase, and per
+    # kernel launch on the stream each kernel runs on
     ph = {k: 0.0 for k in ("standardize", "covariance", "solve", "polish", "output", "total")}
+    kern = {}
     reps = max(1, min(steps, 10))
     for _ in range(reps):
         r = ctx.solve(X, lam0, tol, prec, out=out, timing=True)
         for k in ph:
             ph[k] += r.stats["ms_" + k] / reps
-    return ms, ph, r
+        for name, kms in ctx.kernel_times():
+            d = kern.setdefault(name, [0.0, 0])
+            d[0] += kms
+            d[1] += 1
+    kern = {k: {"ms_per_solve": v[0] / reps, "launches": v[1] / reps, "ms_per_launch": v[0] / v[1]}
+            for k, v in kern.items()}
+    return ms, ms_sync, ph, kern, r
 
 
 def cpu_baseline(X_np, lam0, tol, target_s=20.0):
@@ -132,13 +158,17 @@ def bench_batch(args, torch, spmesl, workloads):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
             "config": {"workload": "hub_batch64", "count": len(Xs), "sum_p": int(sum(X.shape[1] for X in Xs_np)),
                        "tol": 1e-8}}
+    outs = [dict(B=torch.empty((X.shape[1], X.shape[1]), dtype=torch.float64, device="cuda:0"),
+                 sigma=torch.empty((X.shape[1],), dtype=torch.float64, device="cuda:0"),
+                 Omega=torch.empty((X.shape[1], X.shape[1]), dtype=torch.float64, device="cuda:0"))
+            for X in Xs]
     for prec in args.forms.split(","):
         for _ in range(args.warmup):
-            ctx.solve_batch(Xs, lams, 1e-8, prec)
+            ctx.solve_batch(Xs, lams, 1e-8, prec, outs=outs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ctx.solve_batch(Xs, lams, 1e-8, prec)
+            ctx.solve_batch(Xs, lams, 1e-8, prec, outs=outs)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000 / args.steps
         line.setdefault("forms", {})[prec] = {"ms_per_step": round(ms, 3),
@@ -180,16 +210,26 @@ def main():
     forms = args.forms.split(",")
     res = {}
     for prec in forms:
-        ms, ph, r = time_form(ctx, X, lam0, tol, prec, args.steps, args.warmup, torch)
-        res[prec] = (ms, ph, r)
-        print(f"[bench] {prec}: {ms:.3f} ms/solve phases " +
+        ms, ms_sync, ph, kern, r = time_form(ctx, X, lam0, tol, prec, args.steps, args.warmup, torch)
+        res[prec] = (ms, ms_sync, ph, kern, r)
+        print(f"[bench] {prec}: {ms:.3f} ms/solve pipelined, {ms_sync:.3f} one call at a time; phases " +
               " ".join(f"{k}={v:.4f}" for k, v in ph.items()), file=sys.stderr, flush=True)
+        print(f"[bench] {prec} kernels: " +
+              " ".join(f"{k}={v['ms_per_solve']:.4f}" for k, v in kern.items()), file=sys.stderr, flush=True)
 
     head = forms[0]
-    ms, ph, r = res[head]
-    costs = phase_costs(w.n, w.p, head, r.stats)
-    dom = max(("standardize", "covariance", "solve", "polish", "output"), key=lambda k: ph[k])
-    roof = roofline_of(dom, ph[dom], costs)
+    ms, ms_sync, ph, kern, r = res[head]
+    costs = kernel_costs(w.n, w.p, head)
+    # the kernel step that takes longest per solve, among those on the
+    # solver's stream (the output fill overlaps them on the second stream)
+    main = {k: v for k, v in kern.items() if not k.startswith(("fill_", "wait_"))}
+    dom = max(main, key=lambda k: main[k]["ms_per_solve"])
+    roof = roofline_of(dom, main[dom]["ms_per_launch"], costs.get(dom, (0.0, 0.0, None)))
+    if dom not in costs:
+        roof["note"] = "latency-bound step with no algorithmic byte count; achieved is 0"
+    kernels = {k: dict(ms_per_solve=round(v["ms_per_solve"], 5), launches=v["launches"],
+                       **({"roofline": roofline_of(k, v["ms_per_launch"], costs[k])} if k in costs else {}))
+               for k, v in kern.items()}
     line = {
         "metric": "full SPMESL solves/s at p=5000 (mixed vs FP64), % MFMA/HBM roofline",
         "value": round(1000.0 / ms, 3),
@@ -198,6 +238,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_per_solve_one_call_at_a_time": round(ms_sync, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -207,14 +248,17 @@ def main():
                    "tol": tol, "precision": head},
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
         "roofline": roof,
+        "kernels": kernels,
         "stats": {k: r.stats[k] for k in ("total_outer", "max_outer", "total_sweeps",
                                           "total_updates", "total_rounds", "max_working_set",
                                           "columns_noconv", "polish_kkt_checks", "polish_added")},
     }
     for prec in forms[1:]:
-        ms2, ph2, r2 = res[prec]
+        ms2, ms2_sync, ph2, kern2, r2 = res[prec]
         line[prec] = {"value": round(1000.0 / ms2, 3), "ms_per_step": round(ms2, 4),
-                      "phases_ms": {k: round(v, 4) for k, v in ph2.items()}}
+                      "ms_per_solve_one_call_at_a_time": round(ms2_sync, 4),
+                      "phases_ms": {k: round(v, 4) for k, v in ph2.items()},
+                      "kernels_ms": {k: round(v["ms_per_solve"], 5) for k, v in kern2.items()}}
         line["speedup_vs_" + prec] = round(ms2 / ms, 3)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(X_np, lam0, tol)

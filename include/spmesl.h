@@ -108,10 +108,14 @@ typedef struct {
     int32_t max_rounds;  /* cap on working-set growth rounds (<= 0: 64) */
     int32_t precision;   /* SPMESL_FP64 | SPMESL_FP32 | SPMESL_MIXED */
     int32_t output_scale;/* SPMESL_SCALE_ORIGINAL | SPMESL_SCALE_STANDARDIZED */
-    int32_t flags;       /* bit 0: record per-phase times in stats */
+    int32_t flags;       /* SPMESL_FLAG_TIMING | SPMESL_FLAG_EAGER */
 } spmesl_options;
 
 #define SPMESL_FLAG_TIMING 1
+/* Enqueue the kernels one by one instead of replaying the context's cached
+ * HIP graph of the call (the default for calls that repeat the pointers,
+ * sizes and options of the previous call; timed calls are always eager). */
+#define SPMESL_FLAG_EAGER 2
 
 typedef struct {
     /* host-side counters filled by a solve */
@@ -164,11 +168,36 @@ int spmesl_set_workspace(spmesl_ctx *ctx, void *device_ptr, size_t bytes);
 int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob,
                  const spmesl_options *opt, spmesl_result *res);
 
-/* Solve `count` independent problems (uneven n, p) with the same options.
- * status[i] (host) receives each problem's code; the return value is the
- * first non-OK code, or SPMESL_OK. */
+/* As spmesl_solve, but returns once the work is enqueued on the context's
+ * stream (host-side argument errors are still returned at once).  When the
+ * solve completes on the stream, its status code (SPMESL_OK, SPMESL_ENOCONV
+ * or an error code, as spmesl_solve would return) is written to the int at
+ * `status_dev` (device memory, caller-owned).  No stats are reported.  The
+ * outputs and *status_dev are valid once the stream has reached that point
+ * (synchronise the stream or an event recorded after the call); the
+ * context's workspace is reused by the next call on the same stream, which
+ * stream order makes safe. */
+int spmesl_solve_async(spmesl_ctx *ctx, const spmesl_problem *prob,
+                       const spmesl_options *opt, spmesl_result *res, int *status_dev);
+
+/* Solve `count` independent problems (uneven n, p) with the same options,
+ * except that problem i uses lambda0s[i] when lambda0s (HOST array of count
+ * doubles) is not NULL.  status[i] (host) receives each problem's code; the
+ * return value is the first non-OK code, or SPMESL_OK.  The problems run one
+ * after another on the context's stream, as one graph launch when the call
+ * repeats the previous call's pointers, sizes and options. */
 int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
-                       const spmesl_options *opt, spmesl_result *res, int *status);
+                       const spmesl_options *opt, const double *lambda0s,
+                       spmesl_result *res, int *status);
+
+/* Kernel times of the last spmesl_solve run with SPMESL_FLAG_TIMING: one
+ * entry per launch step in enqueue order, `names[i]` a static string naming
+ * the kernel(s) and `ms[i]` its duration in milliseconds, from HIP events
+ * recorded on the stream the step ran on (the zero fill of the dense outputs
+ * runs on the context's second stream).  Fills at most `cap` entries (names
+ * and ms may be NULL when cap is 0) and returns the number of steps
+ * recorded, or SPMESL_EINVAL / SPMESL_EHIP. */
+int spmesl_kernel_times(const spmesl_ctx *ctx, int cap, const char **names, double *ms);
 
 /* ---- single steps (each is also a step of spmesl_solve) ---------------- */
 

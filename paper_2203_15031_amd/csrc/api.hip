@@ -149,6 +149,28 @@ struct spmesl_ctx {
     size_t pinned_count = 0;
     hipEvent_t ev[6] = {};
     bool have_events = false;
+    // second stream (default priority) for the zero fill of the dense
+    // outputs, which overlaps the latency-bound column solves
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    // per-launch timing (SPMESL_FLAG_TIMING): events in enqueue order, each
+    // with the index of the previous event on its stream
+    static constexpr int kMaxMarks = 48;
+    hipEvent_t kev[kMaxMarks] = {};
+    const char *kname[kMaxMarks] = {};
+    int kprev[kMaxMarks] = {};
+    int nmarks = 0;
+    bool kev_ok = false;
+    float kms[kMaxMarks] = {};
+    // replay of the last call's whole enqueue sequence as one HIP graph,
+    // captured on `cap` (a capturable stream) and launched on `stream`
+    hipStream_t cap = nullptr;
+    struct CachedGraph {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    static constexpr size_t kMaxGraphs = 4;
+    std::vector<CachedGraph> graphs;  // most recently used first
     std::string err;
 };
 
@@ -165,6 +187,88 @@ static int fail(spmesl_ctx *ctx, int code, const std::string &msg)
 {
     if (ctx) ctx->err = msg;
     return code;
+}
+
+// The status code of one finished solve from its control block, on the
+// device (the asynchronous entry point's status; the host-side decode()
+// below is the same mapping).
+__global__ void k_decode_status(const Ctl *c, int *status)
+{
+    int st = SPMESL_OK;
+    const int bits = c->status1;
+    if (c->flags & 1) st = SPMESL_ENONFINITE;
+    else if (c->flags & 2) st = SPMESL_EZEROVAR;
+    else if (bits & 4) st = SPMESL_EWORKSET;
+    else if (bits & 2) st = SPMESL_EDEGENERATE;
+    else if (bits & 1) st = SPMESL_ENOCONV;
+    *status = st;
+}
+
+// Bytes that identify a call for graph replay: every pointer, size and
+// option the enqueued kernels take, plus the streams.
+struct KeyBuf {
+    std::vector<unsigned char> b;
+    template <typename V> void add(const V &v)
+    {
+        const unsigned char *q = reinterpret_cast<const unsigned char *>(&v);
+        b.insert(b.end(), q, q + sizeof(V));
+    }
+};
+
+static void key_problem(KeyBuf &k, const spmesl_problem &pr, const spmesl_result &r)
+{
+    k.add(pr.X);
+    k.add(pr.n);
+    k.add(pr.p);
+    k.add(pr.ldx);
+    k.add(r.B);
+    k.add(r.sigma);
+    k.add(r.Omega);
+}
+
+static void key_options(KeyBuf &k, const spmesl_options &o)
+{
+    k.add(o.lambda0);
+    k.add(o.tol);
+    k.add(o.max_outer);
+    k.add(o.max_sweeps);
+    k.add(o.max_rounds);
+    k.add(o.precision);
+    k.add(o.output_scale);
+}
+
+// Records the per-launch events of a timed solve; a null Marker records
+// nothing.  mark(s, name) closes the step that ran on s since the previous
+// mark on s; a null name opens the stream's first step.
+struct Marker {
+    spmesl_ctx *ctx;
+    hipStream_t streams[2] = {};
+    int last[2] = {-1, -1};
+    explicit Marker(spmesl_ctx *c) : ctx(c) { ctx->nmarks = 0; }
+    void mark(hipStream_t s, const char *name)
+    {
+        int si = -1;
+        for (int i = 0; i < 2 && si < 0; ++i)
+            if (streams[i] == s && last[i] >= 0) si = i;
+        if (si < 0)
+            for (int i = 0; i < 2 && si < 0; ++i)
+                if (last[i] < 0) {
+                    si = i;
+                    streams[i] = s;
+                }
+        const int e = ctx->nmarks;
+        if (si < 0 || e >= spmesl_ctx::kMaxMarks) return;
+        if (hipEventRecord(ctx->kev[e], s) != hipSuccess) return;
+        ctx->kname[e] = last[si] < 0 ? nullptr : name;
+        ctx->kprev[e] = last[si];
+        last[si] = e;
+        ctx->nmarks = e + 1;
+    }
+};
+
+static inline void mark(Marker *m, hipStream_t s, const char *name)
+{
+    if (m) m->mark(s, name);
 }
 
 static int ensure_pinned(spmesl_ctx *ctx, size_t count)
@@ -229,12 +333,10 @@ static int validate(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
 template <typename T>
 static void enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt,
                             double tol, double band, int max_outer, int max_sweeps, int max_rounds,
-                            hipStream_t s)
+                            hipStream_t s, Marker *mk)
 {
     const int64_t p = L.p;
-    const int rj = kkt_rows_per_block(p, sizeof(T), (size_t)80 * 1024) > 0
-                       ? kkt_rows_per_block(p, sizeof(T), (size_t)80 * 1024)
-                       : kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
+    const int rj = kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
     ColArgs<T> a{};
     a.S = (const T *)(ws + L.S);
     a.p = p;
@@ -267,10 +369,12 @@ static void enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opt
     a.esc_cnt = &dctl->esc_a;
     a.esc_list = (int *)(ws + L.esclist);
     launch_colsolve(a, 0, s);
+    mark(mk, s, "colsolve_first");
     a.mode = 1;
     a.work_list = (const int *)(ws + L.esclist);
     a.work_cnt = &dctl->esc_a;
     launch_colsolve(a, 1, s);
+    mark(mk, s, "colsolve_first_wide");
     if (rj == 0) return;
     KktArgs<T> k{};
     k.S = a.S;
@@ -292,15 +396,18 @@ static void enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opt
     k.band_idx = a.band_idx;
     k.flags = &dctl->flags;
     launch_kkt_rows(k, rj, s);
+    mark(mk, s, "kkt_rows");
     // re-solve the flagged columns
     a.work_list = (const int *)(ws + L.dirtylist);
     a.work_cnt = &dctl->dirty;
     a.esc_cnt = &dctl->esc_c;
     a.esc_list = (int *)(ws + L.esclist2);
     launch_colsolve(a, 0, s);
+    mark(mk, s, "colsolve_resume");
     a.work_list = (const int *)(ws + L.esclist2);
     a.work_cnt = &dctl->esc_c;
     launch_colsolve(a, 1, s);
+    mark(mk, s, "colsolve_resume_wide");
 }
 
 // Enqueue one full solve.  ws: workspace base laid out by `L`; dctl: this
@@ -319,9 +426,14 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     const int original = opt->output_scale == SPMESL_SCALE_ORIGINAL;
 
     if (ev) HIPTRY(ctx, hipEventRecord(ev[0], s));
+    Marker marker(ctx);
+    Marker *mk = ev ? &marker : nullptr;
+    mark(mk, s, nullptr);
     launch_zero_words((uint32_t *)dctl, sizeof(Ctl) / 4, s);
+    mark(mk, s, "zero_control");
     launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
                     &dctl->flags, s);
+    mark(mk, s, "colstats");
     if (L.prec == SPMESL_FP64)
         launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
     else if (L.prec == SPMESL_FP32)
@@ -329,6 +441,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     else
         launch_standardize_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
                                  (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
+    mark(mk, s, "standardize");
     if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
 
     if (L.prec == SPMESL_FP64)
@@ -338,16 +451,36 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     else
         launch_syrk_bf16x3((const uint16_t *)(ws + L.hi), (const uint16_t *)(ws + L.lo), n, L.npad,
                            p, (float *)(ws + L.S), s);
+    mark(mk, s, L.prec == SPMESL_FP64 ? "syrk_f64" : (L.prec == SPMESL_FP32 ? "syrk_f32" : "syrk_bf16x3"));
     if (ev) HIPTRY(ctx, hipEventRecord(ev[2], s));
 
+    // The zero fill of B and Omega needs nothing of the solve: it runs on the
+    // side stream from here on, and the scatter waits for it.
+    const bool fill = res->B || res->Omega;
+    if (fill) {
+        HIPTRY(ctx, hipEventRecord(ctx->fork, s));
+        HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+        mark(mk, ctx->side, nullptr);
+        if (res->B) {
+            launch_fill_zero(res->B, p * p, ctx->side);
+            mark(mk, ctx->side, "fill_B");
+        }
+        if (res->Omega) {
+            launch_fill_zero(res->Omega, p * p, ctx->side);
+            mark(mk, ctx->side, "fill_Omega");
+        }
+        HIPTRY(ctx, hipEventRecord(ctx->join, ctx->side));
+    }
+
     if (L.prec == SPMESL_FP64)
-        enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s);
+        enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s,
+                                mk);
     else
         enqueue_columns<float>(L, ws, dctl, opt,
                                std::max(opt->tol, L.prec == SPMESL_MIXED ? kMixedFloatTol
                                                                          : (double)SPMESL_FP32_TOL_FLOOR),
                                L.prec == SPMESL_MIXED ? kMixedBand : 0.0, max_outer, max_sweeps,
-                               max_rounds, s);
+                               max_rounds, s, mk);
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
 
     if (L.prec == SPMESL_MIXED) {
@@ -384,6 +517,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         q.polinfo = (int *)(ws + L.polinfo);
         q.flags = &dctl->flags;
         launch_polish(q, s);
+        mark(mk, s, "polish");
     }
     {
         const bool mixed = L.prec == SPMESL_MIXED;
@@ -392,11 +526,12 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                             (const int *)(ws + (mixed ? L.wcnt64 : L.wcnt)),
                             (const int *)(ws + (mixed ? L.cstat64 : L.cstat)), dctl->counters,
                             &dctl->status1, s);
+        mark(mk, s, "reduce_stats");
     }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[4], s));
 
-    if (res->B) launch_fill_zero(res->B, p * p, s);
-    if (res->Omega) launch_fill_zero(res->Omega, p * p, s);
+    if (fill) HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join, 0));
+    mark(mk, s, "wait_fill");
     if (L.prec == SPMESL_FP64)
         launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
                                        (const double *)(ws + L.wbeta), (const double *)(ws + L.sigma),
@@ -412,8 +547,55 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                                        (const double *)(ws + L.wbeta64),
                                        (const double *)(ws + L.sigma64), scale, original, res->B,
                                        res->sigma, res->Omega, &dctl->flags, s);
+    mark(mk, s, "scatter");
     if (ev) HIPTRY(ctx, hipEventRecord(ev[5], s));
     HIPTRY(ctx, hipGetLastError());
+    return SPMESL_OK;
+}
+
+// Enqueue `body` (which enqueues on ctx->stream) as one HIP graph launch on
+// the caller's stream.  A call whose key matches the cached graph's replays
+// it; otherwise `body` runs under capture on the context's own capturable
+// stream (the caller's may be the null stream), and the instantiated graph
+// replaces the cached one.  Kernel launches, event records and waits are the
+// only stream work `body` does (no memset or copy nodes).
+template <typename F>
+static int run_graph(spmesl_ctx *ctx, std::vector<unsigned char> &&key, F &&body)
+{
+    hipStream_t user = ctx->stream;
+    auto &gs = ctx->graphs;
+    for (size_t i = 0; i < gs.size(); ++i) {
+        if (gs[i].key != key) continue;
+        std::rotate(gs.begin(), gs.begin() + (std::ptrdiff_t)i, gs.begin() + (std::ptrdiff_t)i + 1);
+        HIPTRY(ctx, hipGraphLaunch(gs[0].exec, user));
+        return SPMESL_OK;
+    }
+    if (!ctx->cap) HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    HIPTRY(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    ctx->stream = ctx->cap;
+    const int v = body();
+    ctx->stream = user;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+    if (v != SPMESL_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        if (v != SPMESL_OK) return v;
+        return fail(ctx, SPMESL_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess)
+        return fail(ctx, SPMESL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    if (gs.size() >= spmesl_ctx::kMaxGraphs) {
+        // the least recently used graph may still be executing on the stream
+        HIPTRY(ctx, hipStreamSynchronize(user));
+        HIPTRY(ctx, hipGraphExecDestroy(gs.back().exec));
+        gs.pop_back();
+    }
+    gs.insert(gs.begin(), spmesl_ctx::CachedGraph{std::move(key), ex});
+    HIPTRY(ctx, hipGraphLaunch(ex, user));
     return SPMESL_OK;
 }
 
@@ -463,6 +645,12 @@ int spmesl_create(spmesl_ctx **out, int device, void *hip_stream)
     bool ok = true;
     for (int i = 0; i < 6 && ok; ++i) ok = hipEventCreate(&ctx->ev[i]) == hipSuccess;
     ctx->have_events = ok;
+    ok = ok && hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) == hipSuccess;
+    bool kok = ok;
+    for (int i = 0; i < spmesl_ctx::kMaxMarks && kok; ++i) kok = hipEventCreate(&ctx->kev[i]) == hipSuccess;
+    ctx->kev_ok = kok;
     if (!ok || ensure_pinned(ctx, 1) != SPMESL_OK) {
         spmesl_destroy(ctx);
         return SPMESL_EHIP;
@@ -477,6 +665,19 @@ void spmesl_destroy(spmesl_ctx *ctx)
     {
         DevGuard g(ctx->device);
         if (ctx->stream || ctx->ws) (void)hipStreamSynchronize(ctx->stream);
+        if (ctx->side) {
+            (void)hipStreamSynchronize(ctx->side);
+            (void)hipStreamDestroy(ctx->side);
+        }
+        for (auto &cg : ctx->graphs) (void)hipGraphExecDestroy(cg.exec);
+        if (ctx->cap) {
+            (void)hipStreamSynchronize(ctx->cap);
+            (void)hipStreamDestroy(ctx->cap);
+        }
+        for (int i = 0; i < spmesl_ctx::kMaxMarks; ++i)
+            if (ctx->kev[i]) (void)hipEventDestroy(ctx->kev[i]);
+        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+        if (ctx->join) (void)hipEventDestroy(ctx->join);
         if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         for (int i = 0; i < 6; ++i)
@@ -539,8 +740,18 @@ int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_optio
     v = ensure_pinned(ctx, 1);
     if (v != SPMESL_OK) return v;
     Ctl *dctl = (Ctl *)(ctx->ws + ctl_off);
-    const bool timing = (opt->flags & SPMESL_FLAG_TIMING) && ctx->have_events;
-    v = enqueue_solve(ctx, prob, opt, res, L, ctx->ws, dctl, timing ? ctx->ev : nullptr);
+    const bool timing = (opt->flags & SPMESL_FLAG_TIMING) && ctx->have_events && ctx->kev_ok;
+    if (timing || (opt->flags & SPMESL_FLAG_EAGER)) {
+        v = enqueue_solve(ctx, prob, opt, res, L, ctx->ws, dctl, timing ? ctx->ev : nullptr);
+    } else {
+        KeyBuf k;
+        k.add('s');
+        k.add(ctx->ws);
+        key_problem(k, *prob, *res);
+        key_options(k, *opt);
+        v = run_graph(ctx, std::move(k.b),
+                      [&] { return enqueue_solve(ctx, prob, opt, res, L, ctx->ws, dctl, nullptr); });
+    }
     if (v != SPMESL_OK) return v;
     HIPTRY(ctx, hipMemcpyAsync(ctx->pinned, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
     HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -560,6 +771,15 @@ int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_optio
             res->stats->ms_total = tot;
         }
     }
+    if (timing) {
+        for (int i = 0; i < ctx->nmarks; ++i) {
+            ctx->kms[i] = 0.f;
+            if (ctx->kname[i] && ctx->kprev[i] >= 0)
+                HIPTRY(ctx, hipEventElapsedTime(&ctx->kms[i], ctx->kev[ctx->kprev[i]], ctx->kev[i]));
+        }
+    } else {
+        ctx->nmarks = 0;
+    }
     if (st == SPMESL_ENONFINITE) ctx->err = "X holds a NaN or Inf";
     else if (st == SPMESL_EZEROVAR) ctx->err = "a column of X has zero variance";
     else if (st == SPMESL_EWORKSET) ctx->err = "a working set exceeded SPMESL_MAX_WORKING_SET";
@@ -568,16 +788,49 @@ int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_optio
     return st;
 }
 
-int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
-                       const spmesl_options *opt, spmesl_result *res, int *status)
+int spmesl_solve_async(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
+                       spmesl_result *res, int *status_dev)
 {
-    if (!ctx || count < 0 || (count > 0 && (!probs || !res || !status))) return SPMESL_EINVAL;
+    if (!ctx || !res || !status_dev) return SPMESL_EINVAL;
+    int v = validate(ctx, prob, opt);
+    if (v != SPMESL_OK) return v;
+    DevGuard g(ctx->device);
+    Plan L = make_plan(prob->n, prob->p, opt->precision);
+    size_t ctl_off = align_up(L.total, 256);
+    v = ensure_workspace(ctx, ctl_off + sizeof(Ctl));
+    if (v != SPMESL_OK) return v;
+    Ctl *dctl = (Ctl *)(ctx->ws + ctl_off);
+    ctx->nmarks = 0;
+    auto body = [&] {
+        int vi = enqueue_solve(ctx, prob, opt, res, L, ctx->ws, dctl, nullptr);
+        if (vi != SPMESL_OK) return vi;
+        hipLaunchKernelGGL(k_decode_status, dim3(1), dim3(1), 0, ctx->stream, dctl, status_dev);
+        HIPTRY(ctx, hipGetLastError());
+        return (int)SPMESL_OK;
+    };
+    if (opt->flags & SPMESL_FLAG_EAGER) return body();
+    KeyBuf k;
+    k.add('a');
+    k.add(ctx->ws);
+    k.add(status_dev);
+    key_problem(k, *prob, *res);
+    key_options(k, *opt);
+    return run_graph(ctx, std::move(k.b), body);
+}
+
+int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
+                       const spmesl_options *opt, const double *lambda0s, spmesl_result *res,
+                       int *status)
+{
+    if (!ctx || !opt || count < 0 || (count > 0 && (!probs || !res || !status))) return SPMESL_EINVAL;
     if (count == 0) return SPMESL_OK;
     DevGuard g(ctx->device);
     size_t need = 0;
     std::vector<Plan> plans((size_t)count);
+    std::vector<spmesl_options> opts((size_t)count, *opt);
     for (int i = 0; i < count; ++i) {
-        int v = validate(ctx, &probs[i], opt);
+        if (lambda0s) opts[(size_t)i].lambda0 = lambda0s[i];
+        int v = validate(ctx, &probs[i], &opts[(size_t)i]);
         if (v != SPMESL_OK) {
             ctx->err = "problem " + std::to_string(i) + ": " + ctx->err;
             return v;
@@ -591,10 +844,29 @@ int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
     v = ensure_pinned(ctx, (size_t)count);
     if (v != SPMESL_OK) return v;
     Ctl *dctl = (Ctl *)(ctx->ws + ctl_off);
-    for (int i = 0; i < count; ++i) {
-        v = enqueue_solve(ctx, &probs[i], opt, &res[i], plans[(size_t)i], ctx->ws, dctl + i, nullptr);
-        if (v != SPMESL_OK) return v;
+    ctx->nmarks = 0;
+    auto body = [&] {
+        for (int i = 0; i < count; ++i) {
+            int vi = enqueue_solve(ctx, &probs[i], &opts[(size_t)i], &res[i], plans[(size_t)i], ctx->ws,
+                                   dctl + i, nullptr);
+            if (vi != SPMESL_OK) return vi;
+        }
+        return (int)SPMESL_OK;
+    };
+    if (opt->flags & SPMESL_FLAG_EAGER) {
+        v = body();
+    } else {
+        KeyBuf k;
+        k.add('b');
+        k.add(ctx->ws);
+        k.add(count);
+        for (int i = 0; i < count; ++i) {
+            key_problem(k, probs[i], res[i]);
+            key_options(k, opts[(size_t)i]);
+        }
+        v = run_graph(ctx, std::move(k.b), body);
     }
+    if (v != SPMESL_OK) return v;
     HIPTRY(ctx, hipMemcpyAsync(ctx->pinned, dctl, (size_t)count * sizeof(Ctl),
                                hipMemcpyDeviceToHost, ctx->stream));
     HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -604,6 +876,21 @@ int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
         if (first == SPMESL_OK && status[i] != SPMESL_OK) first = status[i];
     }
     return first;
+}
+
+int spmesl_kernel_times(const spmesl_ctx *ctx, int cap, const char **names, double *ms)
+{
+    if (!ctx || cap < 0 || (cap > 0 && (!names || !ms))) return SPMESL_EINVAL;
+    int n = 0;
+    for (int i = 0; i < ctx->nmarks; ++i) {
+        if (!ctx->kname[i]) continue;
+        if (n < cap) {
+            names[n] = ctx->kname[i];
+            ms[n] = (double)ctx->kms[i];
+        }
+        ++n;
+    }
+    return n;
 }
 
 int spmesl_covariance(spmesl_ctx *ctx, const spmesl_problem *prob, int precision, void *S_out,

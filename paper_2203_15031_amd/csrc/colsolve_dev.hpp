@@ -106,80 +106,165 @@ __device__ __forceinline__ int lds_lower_bound(const int *a, int n, int v)
 //   band     : j != k, beta_j == 0, |g_j| > bthr -> band_idx (when recording)
 // Returns the number of violators (may exceed kPendMax; only the first
 // kPendMax are stored).
+//
+// Each lane reads V consecutive entries of a row at once (one 16-byte load
+// when every row of S is 16-byte aligned, i.e. p a multiple of V), CH such
+// groups per trip, and U support rows at a time.
 // ---------------------------------------------------------------------------
-template <typename TS, typename T, int LW>
-__device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
-                        int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
+template <typename TS, int V>
+__device__ __forceinline__ void load_group(const TS *__restrict__ src, TS (&x)[V])
 {
-    constexpr int CH = 8;
+    if constexpr (V == 1) {
+        x[0] = *src;
+    } else {
+        typedef TS vt __attribute__((ext_vector_type(V)));
+        const vt y = *reinterpret_cast<const vt *>(src);
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[e] = y[e];
+    }
+}
+
+// Rank of this lane's first element among the flagged elements of a chunk
+// taken lane by lane (c: this lane's count, 0..7), and the chunk's total.
+__device__ __forceinline__ int lane_prefix(int c, int *total)
+{
+    int r = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const unsigned long long m = __ballot((c >> b) & 1);
+        r += lanes_below(m) << b;
+        tot += __popcll(m) << b;
+    }
+    *total = tot;
+    return r;
+}
+
+template <typename TS, typename T, int LW, int V>
+__device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
+                          int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
+{
+    constexpr int CH = V == 1 ? 8 : 4;
+    constexpr int U = V == 1 ? 4 : 2;
+    constexpr int STEP = kWave * V * CH;
     const int lane = lane_id();
     const TS *Sk = S + k * p;
     int npend = 0, nband = 0;
-    for (int64_t base = 0; base < p; base += (int64_t)kWave * CH) {
-        T acc[CH];
+    for (int64_t base = 0; base < p; base += STEP) {
+        T acc[CH][V];
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
-            int64_t j = base + c * kWave + lane;
-            acc[c] = j < p ? (T)Sk[j] : T(0);
-        }
-        for (int t = 0; t < ns; t += 4) {
-            const TS *rows[4];
-            T v[4];
+            const int64_t j = base + (int64_t)(c * kWave + lane) * V;
+            TS x[V];
+            if (j < p) {
+                load_group<TS, V>(Sk + j, x);
+            } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+                for (int e = 0; e < V; ++e) x[e] = TS(0);
+            }
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc[c][e] = (T)x[e];
+        }
+        for (int t = 0; t < ns; t += U) {
+            const TS *rows[U];
+            T v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 bool ok = t + u < ns;
                 int64_t l = ok ? (int64_t)sm.sidx[t + u] : k;
                 l = l < 0 ? 0 : (l >= p ? p - 1 : l);
                 v[u] = ok ? sm.sval[t + u] : T(0);
                 rows[u] = S + l * p;
             }
-            T x[4][CH];
+            TS x[U][CH][V];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
-                    int64_t j = base + c * kWave + lane;
-                    x[u][c] = j < p ? (T)rows[u][j] : T(0);
+                    const int64_t j = base + (int64_t)(c * kWave + lane) * V;
+                    if (j < p) {
+                        load_group<TS, V>(rows[u] + j, x[u][c]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < V; ++e) x[u][c][e] = TS(0);
+                    }
                 }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int c = 0; c < CH; ++c) acc[c] -= v[u] * x[u][c];
+                for (int c = 0; c < CH; ++c)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) acc[c][e] -= v[u] * (T)x[u][c][e];
         }
+        // chunk by chunk, in ascending j: lane by lane, then element
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
-            int64_t j = base + c * kWave + lane;
-            T aa = acc[c] < T(0) ? -acc[c] : acc[c];
-            bool live = j < p && j != k;
-            bool viol = live && aa > thr;
-            bool bnd = record_band && live && aa > bthr;
-            if (viol) {
-                int pos = lds_lower_bound(sm.widx, w, (int)j);
-                viol = !(pos < w && sm.widx[pos] == (int)j);
+            const int64_t j0 = base + (int64_t)(c * kWave + lane) * V;
+            unsigned vm = 0u, bm = 0u;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t j = j0 + e;
+                const T aa = acc[c][e] < T(0) ? -acc[c][e] : acc[c][e];
+                const bool live = j < p && j != k;
+                if (live && aa > thr) vm |= 1u << e;
+                if (record_band && live && aa > bthr) bm |= 1u << e;
             }
-            if (bnd) {
-                int pos = lds_lower_bound(sm.sidx, ns, (int)j);
-                bnd = !(pos < ns && sm.sidx[pos] == (int)j);
+            if (vm) {
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if ((vm >> e) & 1u) {
+                        const int j = (int)(j0 + e);
+                        const int pos = lds_lower_bound(sm.widx, w, j);
+                        if (pos < w && sm.widx[pos] == j) vm &= ~(1u << e);
+                    }
             }
-            unsigned long long m = __ballot(viol);
-            if (m) {
-                int pos = npend + lanes_below(m);
-                if (viol && pos < kPendMax) sm.pend[pos] = (int)j;
-                npend += __popcll(m);
+            if (bm) {
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if ((bm >> e) & 1u) {
+                        const int j = (int)(j0 + e);
+                        const int pos = lds_lower_bound(sm.sidx, ns, j);
+                        if (pos < ns && sm.sidx[pos] == j) bm &= ~(1u << e);
+                    }
             }
-            if (record_band) {
-                unsigned long long mb = __ballot(bnd);
-                if (mb) {
-                    int pos = nband + lanes_below(mb);
-                    if (bnd && pos < kBandMax) band_idx[k * kBandMax + pos] = (int)j;
-                    nband += __popcll(mb);
-                }
+            if (__ballot(vm != 0u)) {
+                int tot;
+                int pos = npend + lane_prefix(__popc(vm), &tot);
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if ((vm >> e) & 1u) {
+                        if (pos < kPendMax) sm.pend[pos] = (int)(j0 + e);
+                        ++pos;
+                    }
+                npend += tot;
+            }
+            if (record_band && __ballot(bm != 0u)) {
+                int tot;
+                int pos = nband + lane_prefix(__popc(bm), &tot);
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if ((bm >> e) & 1u) {
+                        if (pos < kBandMax) band_idx[k * kBandMax + pos] = (int)(j0 + e);
+                        ++pos;
+                    }
+                nband += tot;
             }
         }
     }
     if (record_band && lane == 0) band_cnt[k] = nband;
     wave_sync();
     return npend;
+}
+
+template <typename TS, typename T, int LW>
+__device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
+                        int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
+{
+    constexpr int V = 16 / sizeof(TS);
+    // rows of S start 16-byte aligned when p is a multiple of V (S itself
+    // is 256-byte aligned)
+    if (p % V == 0)
+        return kkt_pass_v<TS, T, LW, V>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx);
+    return kkt_pass_v<TS, T, LW, 1>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx);
 }
 
 // Support list (nonzero coefficients, ascending) from the slot registers.

@@ -13,19 +13,29 @@
 // the near-threshold band (j off the support with |g_jk| > lambda_k - band)
 // is recorded for the double polish.  Only columns left deferred by their
 // first solve are examined.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace spmesl {
 
+// Two tile buffers of rj rows each (plus a 16-byte group of slack at either
+// end) must fit the LDS budget.
+static int64_t kkt_buffer_elems(int64_t p, int rj, size_t elem)
+{
+    const int64_t v = (int64_t)(16 / elem);
+    return ((int64_t)rj * p + 2 * v + v - 1) / v * v;
+}
+
 int kkt_rows_per_block(int64_t p, size_t elem, size_t lds_budget)
 {
-    for (int rj = 8; rj >= 1; rj >>= 1)
-        if ((size_t)rj * (size_t)p * elem <= lds_budget) return rj;
+    for (int rj = 4; rj >= 1; rj >>= 1)
+        if (2 * (size_t)kkt_buffer_elems(p, rj, elem) * elem <= lds_budget) return rj;
     return 0;
 }
 
-constexpr int kKktThreads = 512;
-constexpr int kKktQ = kSuppPad;  // support entries preloaded per column
+constexpr int kKktThreads = 1024;
+constexpr int kKktQ = 8;  // support entries held in registers per column
 
 // Rare path for one flagged pair (j, k): recompute g_jk from the staged row
 // and the column's support, then record a violation / band entry.
@@ -76,106 +86,166 @@ __device__ __forceinline__ void kkt_flagged(const KktArgs<T> &A, int64_t k, int6
     }
 }
 
+// Start the copy of elements [src, src + tot) of S into LDS with the direct
+// global-to-LDS path (16 bytes per lane; a wave fills 1 KB of consecutive
+// LDS).  Whole 16-byte groups are moved, so the tile starts at
+// buf + (src's element offset within its group); the partial groups at
+// either end bring a few neighbouring elements of S, all inside S's
+// 256-byte-aligned workspace region.  Completion is awaited by the caller
+// (vmcnt, then a barrier).
+template <typename T>
+__device__ __forceinline__ const T *kkt_issue_tile(const T *src, int64_t tot, T *buf)
+{
+    constexpr int V = 16 / sizeof(T);
+    constexpr int NWV = kKktThreads / kWave;
+    const uintptr_t a = (uintptr_t)src;
+    const int lofs = (int)((a & 15u) / sizeof(T));
+    const char *g0 = reinterpret_cast<const char *>(a & ~(uintptr_t)15u);
+    const int64_t ng = (lofs + tot + V - 1) / V;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (int64_t e0 = (int64_t)wv * kWave; e0 < ng; e0 += (int64_t)NWV * kWave) {
+        const int64_t e = e0 + lane;
+        if (e < ng)
+            __builtin_amdgcn_global_load_lds(
+                g0 + e * 16, (__attribute__((address_space(3))) void *)(buf + e0 * V), 16, 0, 0);
+    }
+    return buf + lofs;
+}
+
 // Persistent blocks: block b owns rows [b * rpb, (b + 1) * rpb) of S.  For
-// each chunk of kKktThreads * CPT columns the block loads every thread's
-// CPT columns (support, lambda) into registers once, then streams its row
-// tiles of RJ rows through LDS, so S is read once per column chunk (once when
-// p <= kKktThreads * CPT) and the support lists once per block and chunk.
-template <typename T, int RJ, int CPT>
-__global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t rpb)
+// each chunk of kKktThreads * CPT columns every thread loads its CPT
+// columns' first kKktQ support entries and thresholds into registers once;
+// the block's row tiles of RJ rows then stream through two LDS buffers, the
+// copy of tile t + 1 in flight while tile t is examined.  S is read once per
+// column chunk (once when p <= kKktThreads * CPT).
+//
+// The register copy of a support holds its indices as 16-bit halves when
+// PK (p <= 65535) and its coefficients as floats.  For double S that makes
+// the examination a filter: the float coefficients move each gradient by at
+// most 2^-24 ||beta||_1 (|S_jl| <= 1), so pairs are flagged against the
+// threshold lowered by twice that, and every flagged pair is recomputed
+// exactly from the double coefficients before anything is recorded.
+template <typename T, int RJ, int CPT, bool PK>
+__global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t rpb, int64_t bstride)
 {
     extern __shared__ __align__(16) unsigned char kkt_lds[];
-    T *rows = reinterpret_cast<T *>(kkt_lds);
+    T *const buf0 = reinterpret_cast<T *>(kkt_lds);
     if (*A.flags) return;
     const int64_t p = A.p;
     const int64_t rb = (int64_t)blockIdx.x * rpb;
     const int64_t re = rb + rpb < p ? rb + rpb : p;
     if (rb >= p) return;
     const int tid = threadIdx.x;
+    const int ntile = (int)((re - rb + RJ - 1) / RJ);
+    constexpr int NI = PK ? kKktQ / 2 : kKktQ;
     for (int64_t cbase = 0; cbase < p; cbase += (int64_t)CPT * kKktThreads) {
-        int64_t kk[CPT];
-        int cnt[CPT];
-        T lam[CPT];
-        bool act[CPT];
+        __syncthreads();  // the previous chunk's last tile has been read
+        const T *tile = kkt_issue_tile<T>(A.S + rb * p, (re - rb < RJ ? re - rb : RJ) * p, buf0);
+        int cnt[CPT];  // support size; -1 for a column not examined
+        T thr[CPT];
+        unsigned li[CPT][NI];
+        float lv[CPT][kKktQ];
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
-            kk[u] = cbase + (int64_t)u * kKktThreads + tid;
-            act[u] = kk[u] < p && A.col_status[kk[u]] == kColDeferred;
-            cnt[u] = act[u] ? A.supp_cnt[kk[u]] : 0;
-            cnt[u] = cnt[u] < 0 ? 0 : (cnt[u] > kWMax ? kWMax : cnt[u]);
-            lam[u] = act[u] ? (T)A.lam_used[kk[u]] : T(0);
-        }
-        // the first kKktQ slots are always written (padding (k, 0) past the
-        // support), so these loads do not wait for the counts
-        int li[CPT][kKktQ];
-        T lv[CPT][kKktQ];
-#pragma unroll
-        for (int u = 0; u < CPT; ++u)
+            const int64_t k = cbase + (int64_t)u * kKktThreads + tid;
+            const int64_t kq = k < p ? k : 0;
+            // with PK every offset fits 32 bits: one offset register per
+            // column against a scalar base per slot
+            const unsigned ko = (unsigned)kq;
+            auto at = [&](const auto *base, int64_t q) {
+                typedef typename std::remove_const<typename std::remove_pointer<decltype(base)>::type>::type E;
+                if constexpr (PK)
+                    return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base + q * p) +
+                                                        ko * (unsigned)sizeof(E));
+                else
+                    return base[q * p + kq];
+            };
+            const bool act = k < p && at(A.col_status, 0) == kColDeferred;
+            int c = act ? at(A.supp_cnt, 0) : -1;
+            cnt[u] = c < -1 ? 0 : (c > kWMax ? kWMax : c);
+            T l1 = T(0);
 #pragma unroll
             for (int q = 0; q < kKktQ; ++q) {
-                const int64_t kq = kk[u] < p ? kk[u] : 0;
-                int v = A.supp_idx[(int64_t)q * p + kq];
-                li[u][q] = v < 0 ? 0 : (v >= p ? (int)(p - 1) : v);
-                lv[u][q] = A.supp_val[(int64_t)q * p + kq];
-            }
-        for (int64_t j0 = rb; j0 < re; j0 += RJ) {
-            const int64_t nr = (re - j0) < RJ ? (re - j0) : RJ;
-            __syncthreads();  // previous tile consumed
-            {
-                // rows j0 .. j0+nr-1 of S are contiguous: 16-byte loads, four in
-                // flight per thread before any is stored
-                const T *src = A.S + j0 * p;
-                const int64_t tot = nr * p;
-                constexpr int V = 16 / sizeof(T);
-                const bool aligned = ((uintptr_t)src & 15u) == 0;
-                const int64_t nvec = aligned ? tot / V : 0;
-                typedef __attribute__((ext_vector_type(4))) unsigned int u4;
-                const u4 *s4 = reinterpret_cast<const u4 *>(src);
-                u4 *d4 = reinterpret_cast<u4 *>(rows);
-                for (int64_t e0 = tid; e0 < nvec; e0 += 4 * (int64_t)kKktThreads) {
-                    u4 t[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        int64_t e = e0 + (int64_t)u * kKktThreads;
-                        if (e < nvec) t[u] = s4[e];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        int64_t e = e0 + (int64_t)u * kKktThreads;
-                        if (e < nvec) d4[e] = t[u];
-                    }
+                // slots past the count hold stale values: replaced by (0, 0),
+                // which adds nothing
+                int v = at(A.supp_idx, q);
+                v = v < 0 ? 0 : (v >= (int)p - 1 ? (int)p - 1 : v);
+                const T b = at(A.supp_val, q);
+                const bool in = q < cnt[u];
+                v = in ? v : 0;
+                lv[u][q] = in ? (float)b : 0.0f;
+                if (in) l1 += b < T(0) ? -b : b;
+                if (PK) {
+                    if (q & 1) li[u][q / 2] |= (unsigned)v << 16;
+                    else li[u][q / 2] = (unsigned)v;
+                } else {
+                    li[u][q] = (unsigned)v;
                 }
-                for (int64_t e = nvec * V + tid; e < tot; e += kKktThreads) rows[e] = src[e];
             }
-            __syncthreads();
+            const T lam = act ? (T)at(A.lam_used, 0) : T(0);
+            T t = A.band > T(0) ? lam - A.band : lam + A.kkt_tol;
+            if (sizeof(T) == 8) t -= l1 * (T)(1.0 / 8388608.0);
+            thr[u] = t;
+        }
+        for (int t = 0; t < ntile; ++t) {
+            const int64_t j0 = rb + (int64_t)t * RJ;
+            const int64_t nr = (re - j0) < RJ ? (re - j0) : RJ;
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of tile t have landed
+            __syncthreads();                // ... and every wave's; tile t - 1 is no longer read
+            const T *cur = tile;
+            if (t + 1 < ntile) {
+                const int64_t j1 = j0 + RJ;
+                const int64_t n1 = (re - j1) < RJ ? (re - j1) : RJ;
+                tile = kkt_issue_tile<T>(A.S + j1 * p, n1 * p, buf0 + ((t + 1) & 1) * bstride);
+            }
             // gradients of every (row, column) pair; only a flag leaves the
             // unrolled body
             unsigned long long flagged = 0ull;
 #pragma unroll
             for (int u = 0; u < CPT; ++u) {
-                if (!act[u]) continue;
-                const int64_t k = kk[u];
+                // opaque per tile: the slot masks and row offsets derived
+                // from these are recomputed rather than held across tiles
+                int cu = cnt[u];
+                int kl = (int)(cbase + (int64_t)u * kKktThreads) + tid;
+                asm volatile("" : "+v"(cu), "+v"(kl));
+                if (cu < 0) continue;
+                const int64_t k = kl;
+                // rows past the tile's end (last tile of a range) read stale
+                // LDS; their results are discarded by the flag test
                 T acc[RJ];
 #pragma unroll
-                for (int r = 0; r < RJ; ++r) acc[r] = r < nr ? rows[r * p + k] : T(0);
+                for (int r = 0; r < RJ; ++r) acc[r] = cur[r * p + k];
+                // slots in two groups of four, each without per-slot
+                // branches (padding adds zero), so their gathers issue
+                // together
 #pragma unroll
-                for (int q = 0; q < kKktQ; ++q)
+                for (int g = 0; g < kKktQ; g += 4) {
+                    if (g > 0 && cu <= g) break;
 #pragma unroll
-                    for (int r = 0; r < RJ; ++r)
-                        if (r < nr) acc[r] -= lv[u][q] * rows[r * p + li[u][q]];
-                for (int q = kKktQ; q < cnt[u]; ++q) {
+                    for (int q = g; q < g + 4; ++q) {
+                        // the empty asm keeps the packed forms live across
+                        // tiles instead of every unpacked index, row offset
+                        // and converted coefficient
+                        unsigned w = PK ? li[u][q / 2] : li[u][q];
+                        float v32 = lv[u][q];
+                        asm volatile("" : "+v"(w), "+v"(v32));
+                        const int l = PK ? (int)((w >> ((q & 1) * 16)) & 0xffffu) : (int)w;
+                        const T v = (T)v32;
+#pragma unroll
+                        for (int r = 0; r < RJ; ++r) acc[r] -= v * cur[r * p + l];
+                    }
+                }
+                for (int q = kKktQ; q < cu; ++q) {
                     int64_t l = A.supp_idx[(int64_t)q * p + k];
                     l = l < 0 ? 0 : (l >= p ? p - 1 : l);
                     const T v = A.supp_val[(int64_t)q * p + k];
 #pragma unroll
-                    for (int r = 0; r < RJ; ++r)
-                        if (r < nr) acc[r] -= v * rows[r * p + l];
+                    for (int r = 0; r < RJ; ++r) acc[r] -= v * cur[r * p + l];
                 }
-                const T lo_thr = A.band > T(0) ? lam[u] - A.band : lam[u] + A.kkt_tol;
 #pragma unroll
                 for (int r = 0; r < RJ; ++r) {
                     const T a = acc[r] < T(0) ? -acc[r] : acc[r];
-                    if (r < nr && j0 + r != k && a > lo_thr) flagged |= 1ull << (u * RJ + r);
+                    if (r < nr && j0 + r != k && a > thr[u]) flagged |= 1ull << (u * RJ + r);
                 }
             }
             while (flagged) {
@@ -183,7 +253,7 @@ __global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t 
                 flagged &= flagged - 1;
                 const int u = bit / RJ, r = bit % RJ;
                 const int64_t k = cbase + (int64_t)u * kKktThreads + tid;
-                kkt_flagged<T>(A, k, j0 + r, rows + (int64_t)r * p);
+                kkt_flagged<T>(A, k, j0 + r, cur + (int64_t)r * p);
             }
         }
     }
@@ -197,48 +267,36 @@ static void launch_kkt_rows_c(const KktArgs<T> &a, hipStream_t s)
     int64_t rpb = (a.p + nblk - 1) / nblk;
     rpb = (rpb + RJ - 1) / RJ * RJ;
     nblk = (a.p + rpb - 1) / rpb;
-    const size_t lds = (size_t)RJ * (size_t)a.p * sizeof(T);
-    hipLaunchKernelGGL((k_kkt_rows<T, RJ, CPT>), dim3((unsigned)nblk), dim3(kKktThreads), lds, s, a,
-                       rpb);
+    const int64_t bstride = kkt_buffer_elems(a.p, RJ, sizeof(T));
+    const size_t lds = 2 * (size_t)bstride * sizeof(T);
+    if (a.p <= 65535)
+        hipLaunchKernelGGL((k_kkt_rows<T, RJ, CPT, true>), dim3((unsigned)nblk), dim3(kKktThreads), lds,
+                           s, a, rpb, bstride);
+    else
+        hipLaunchKernelGGL((k_kkt_rows<T, RJ, CPT, false>), dim3((unsigned)nblk), dim3(kKktThreads), lds,
+                           s, a, rpb, bstride);
 }
 
-// rj: rows that fit in LDS.  Columns per thread: enough to cover p in one
-// chunk (S read once) within the register budget; rows per tile are then
-// capped so the unrolled gathers stay in registers.
+// rj: rows per tile that fit LDS twice.  Columns per thread: enough to cover
+// p in one chunk (S read once), up to five for float and three for double
+// (the register budget of 16 waves per CU); larger p takes several chunks.
+template <typename T, int RJ>
+static void launch_kkt_rows_r(const KktArgs<T> &a, hipStream_t s)
+{
+    const int64_t need = (a.p + kKktThreads - 1) / kKktThreads;
+    if (need <= 1) launch_kkt_rows_c<T, RJ, 1>(a, s);
+    else if (need <= 2) launch_kkt_rows_c<T, RJ, 2>(a, s);
+    else if constexpr (sizeof(T) == 8) launch_kkt_rows_c<T, RJ, 3>(a, s);  // 5 would spill
+    else if (need <= 3) launch_kkt_rows_c<T, RJ, 3>(a, s);
+    else launch_kkt_rows_c<T, RJ, 5>(a, s);
+}
+
 template <typename T>
 void launch_kkt_rows(const KktArgs<T> &a, int rj, hipStream_t s)
 {
-    const int64_t need = (a.p + kKktThreads - 1) / kKktThreads;
-    if constexpr (sizeof(T) == 4) {
-        if (need <= 4) {
-            if (rj >= 4) launch_kkt_rows_c<T, 4, 4>(a, s);
-            else if (rj == 2) launch_kkt_rows_c<T, 2, 4>(a, s);
-            else launch_kkt_rows_c<T, 1, 4>(a, s);
-        } else if (need <= 6) {
-            if (rj >= 4) launch_kkt_rows_c<T, 4, 6>(a, s);
-            else if (rj == 2) launch_kkt_rows_c<T, 2, 6>(a, s);
-            else launch_kkt_rows_c<T, 1, 6>(a, s);
-        } else {
-            if (rj >= 2) launch_kkt_rows_c<T, 2, 10>(a, s);
-            else launch_kkt_rows_c<T, 1, 10>(a, s);
-        }
-    } else {
-        if (need <= 2) {
-            if (rj >= 8) launch_kkt_rows_c<T, 8, 2>(a, s);
-            else if (rj == 4) launch_kkt_rows_c<T, 4, 2>(a, s);
-            else if (rj == 2) launch_kkt_rows_c<T, 2, 2>(a, s);
-            else launch_kkt_rows_c<T, 1, 2>(a, s);
-        } else if (need <= 4) {
-            if (rj >= 4) launch_kkt_rows_c<T, 4, 4>(a, s);
-            else if (rj == 2) launch_kkt_rows_c<T, 2, 4>(a, s);
-            else launch_kkt_rows_c<T, 1, 4>(a, s);
-        } else if (need <= 6) {
-            if (rj >= 2) launch_kkt_rows_c<T, 2, 6>(a, s);
-            else launch_kkt_rows_c<T, 1, 6>(a, s);
-        } else {
-            launch_kkt_rows_c<T, 1, 8>(a, s);
-        }
-    }
+    if (rj >= 4) launch_kkt_rows_r<T, 4>(a, s);
+    else if (rj == 2) launch_kkt_rows_r<T, 2>(a, s);
+    else launch_kkt_rows_r<T, 1>(a, s);
 }
 
 template void launch_kkt_rows<double>(const KktArgs<double> &, int, hipStream_t);

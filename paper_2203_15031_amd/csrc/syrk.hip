@@ -175,106 +175,149 @@ void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, hipStream_
 
 // ---------------------------------------------------------------------------
 // mixed form: bf16 split, 128 x 128 tiles, 64 samples per stage
+//
+// Persistent blocks walk the upper-triangle tile list (tiles of one row
+// panel kept on one XCD).  A stage (the hi and lo panels of the tile's row
+// and column blocks, 128 variables x 64 samples each, 64 KB) is copied to LDS
+// by the direct global-to-LDS path; the output tile of the epilogue reuses
+// the same LDS.  At 66 KB of LDS two blocks share a CU, so one block's copy
+// overlaps the other's matrix-core work (measured faster than one block per
+// CU with two stage buffers).
+//
+// LDS layout of a panel: row m (a variable) holds its 64 samples as eight
+// 16-byte chunks, chunk c stored in slot c ^ f(m), f(m) = (m & 7) ^ ((m >> 3)
+// & 1).  The operand reads (16 lanes on 16 consecutive rows, one chunk each)
+// then touch distinct banks with either 32 or 64 LDS banks.
 // ---------------------------------------------------------------------------
-constexpr int kBfKC = 64;            // samples per LDS stage
-constexpr int kBfLd = kBfKC + 8;     // padded row (bf16 elements)
+constexpr int kBfKC = 64;                   // samples per stage
+constexpr int kBfPanel = 128 * kBfKC * 2;   // bytes of one panel (16 KB)
+constexpr int kBfStage = 4 * kBfPanel;      // hi_J, lo_J, hi_K, lo_K
+constexpr int kBfOutLd = 129;               // padded row of the staged output tile
+constexpr int kBfLds = 128 * kBfOutLd * 4;  // output tile; the stage fits inside
+static_assert(kBfLds >= kBfStage, "stage and output tile share the LDS");
+
+__device__ __forceinline__ int bf_swz(int m) { return (m & 7) ^ ((m >> 3) & 1); }
+
+// Upper-triangle tile number -> (row block, column block), row-major order.
+__device__ __forceinline__ void bf_tile(int t, int T, int *bj, int *bk)
+{
+    int row = 0;
+    while (t >= T - row) {
+        t -= T - row;
+        ++row;
+    }
+    *bj = row;
+    *bk = row + t;
+}
+
+// Issue the copies of one stage: samples [i0, i0 + 64) of variables j0.. and
+// k0.. (hi and lo).  A diagonal tile copies its one panel pair only.  Rows
+// past p load row p - 1 (valid memory; those results are never stored).
+__device__ __forceinline__ void bf_issue(const uint16_t *__restrict__ hi, const uint16_t *__restrict__ lo,
+                                         int64_t npad, int64_t p, int64_t j0, int64_t k0, int64_t i0,
+                                         bool diag, unsigned char *stage)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int npan = diag ? 2 : 4;
+    // 16 groups of 8 rows per panel; one 1 KB wave instruction per group
+    for (int blk = wv; blk < npan * 16; blk += 4) {
+        const int pnl = blk >> 4, grp = blk & 15;
+        const int m = grp * 8 + (lane >> 3);
+        const int c = (lane & 7) ^ bf_swz(m);
+        int64_t v = ((pnl < 2) ? j0 : k0) + m;
+        v = v < p ? v : p - 1;
+        const uint16_t *src = ((pnl & 1) ? lo : hi) + v * npad + i0 + c * 8;
+        __builtin_amdgcn_global_load_lds(
+            src, (__attribute__((address_space(3))) void *)(stage + pnl * kBfPanel + grp * 1024), 16, 0, 0);
+    }
+}
 
 __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict__ hi,
                                                      const uint16_t *__restrict__ lo,
                                                      int64_t npad, int64_t p,
                                                      float *__restrict__ S, int Tt, float invn)
 {
-    __shared__ union {
-        uint16_t in[4][128 * kBfLd];  // hi_J, lo_J, hi_K, lo_K ; [var][sample]
-        float out[128][129];
-    } sm;
-    int bj, bk;
-    tile_of_block(Tt, &bj, &bk);
-    const int64_t j0 = (int64_t)bj * 128, k0 = (int64_t)bk * 128;
+    extern __shared__ __align__(16) unsigned char bf_lds[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
-    f4 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    const int ntiles = Tt * (Tt + 1) / 2;
+    // tiles of XCD x = blockIdx % 8 form one contiguous range of the list
+    const int nb = gridDim.x, x = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int nbx = (nb >> 3) + ((nb & 7) > x ? 1 : 0);
+    const int q = ntiles >> 3, r = ntiles & 7;
+    const int tbeg = x * q + (x < r ? x : r), tend = tbeg + q + (x < r ? 1 : 0);
+    const int nst = (int)(npad / kBfKC);
 
-    // loader: 128 vars x 64 samples per panel; thread -> (var = tid/2, half)
-    const int lv = tid >> 1, lh = (tid & 1) * 32;
-    uint4 pre[4][4];
-    auto fetch = [&](int64_t i0) {
+    int t = tbeg + slot;
+    for (; t < tend; t += nbx) {
+        int bj, bk;
+        bf_tile(t, Tt, &bj, &bk);
+        const int64_t j0 = (int64_t)bj * 128, k0 = (int64_t)bk * 128;
+        const bool diag = bj == bk;
+        const int pk = diag ? 0 : 2;
+        f4 acc[4][4];
 #pragma unroll
-        for (int pnl = 0; pnl < 4; ++pnl) {
-            const uint16_t *src = (pnl & 1) ? lo : hi;
-            int64_t v = ((pnl < 2) ? j0 : k0) + lv;
-            if (v < p) {
-                const uint4 *g = reinterpret_cast<const uint4 *>(src + v * npad + i0 + lh);
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) pre[pnl][q] = g[q];
-            } else {
+            for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+        for (int st = 0; st < nst; ++st) {
+            __syncthreads();
+            bf_issue(hi, lo, npad, p, j0, k0, (int64_t)st * kBfKC, diag, bf_lds);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            const unsigned char *sb = bf_lds;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) pre[pnl][q] = uint4{0, 0, 0, 0};
-            }
-        }
-    };
-    fetch(0);
-    for (int64_t i0 = 0; i0 < npad; i0 += kBfKC) {
+            for (int kk = 0; kk < kBfKC; kk += 32) {
+                const int c = kk / 8 + (lane >> 4);
+                bf8 ha[4], la[4], hb[4], lb[4];
 #pragma unroll
-        for (int pnl = 0; pnl < 4; ++pnl) {
-            uint4 *d = reinterpret_cast<uint4 *>(&sm.in[pnl][lv * kBfLd + lh]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) d[q] = pre[pnl][q];
-        }
-        __syncthreads();
-        if (i0 + kBfKC < npad) fetch(i0 + kBfKC);  // in flight during the MFMAs below
-#pragma unroll
-        for (int kk = 0; kk < kBfKC; kk += 32) {
-            bf8 ha[4], la[4], hb[4], lb[4];
-            const int ko = kk + 8 * (lane >> 4);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                int r = 64 * wm + 16 * a + (lane & 15);
-                ha[a] = *reinterpret_cast<const bf8 *>(&sm.in[0][r * kBfLd + ko]);
-                la[a] = *reinterpret_cast<const bf8 *>(&sm.in[1][r * kBfLd + ko]);
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                int c = 64 * wn + 16 * b + (lane & 15);
-                hb[b] = *reinterpret_cast<const bf8 *>(&sm.in[2][c * kBfLd + ko]);
-                lb[b] = *reinterpret_cast<const bf8 *>(&sm.in[3][c * kBfLd + ko]);
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 4; ++a) {
+                    const int m = 64 * wm + 16 * a + (lane & 15);
+                    const int off = m * 128 + ((c ^ bf_swz(m)) << 4);
+                    ha[a] = *reinterpret_cast<const bf8 *>(sb + off);
+                    la[a] = *reinterpret_cast<const bf8 *>(sb + kBfPanel + off);
+                }
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
+                    const int m = 64 * wn + 16 * b + (lane & 15);
+                    const int off = m * 128 + ((c ^ bf_swz(m)) << 4);
+                    hb[b] = *reinterpret_cast<const bf8 *>(sb + pk * kBfPanel + off);
+                    lb[b] = *reinterpret_cast<const bf8 *>(sb + (pk + 1) * kBfPanel + off);
                 }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
+                    }
+            }
         }
         __syncthreads();
-    }
+        float *outc = reinterpret_cast<float *>(bf_lds);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                sm.out[64 * wm + 16 * a + 4 * (lane >> 4) + r][64 * wn + 16 * b + (lane & 15)] =
-                    acc[a][b][r] * invn;
-    __syncthreads();
-    const bool diag = bj == bk;
-    for (int e = tid; e < 128 * 128; e += 256) {
-        int rr = e >> 7, cc = e & 127;
-        int64_t j = j0 + rr, k = k0 + cc;
-        if (j < p && k < p)
-            S[j * p + k] = (j == k) ? 1.0f : ((diag && rr > cc) ? sm.out[cc][rr] : sm.out[rr][cc]);
-    }
-    if (bj != bk) {
+                for (int rr = 0; rr < 4; ++rr)
+                    outc[(64 * wm + 16 * a + 4 * (lane >> 4) + rr) * kBfOutLd + 64 * wn + 16 * b + (lane & 15)] =
+                        acc[a][b][rr] * invn;
+        __syncthreads();
         for (int e = tid; e < 128 * 128; e += 256) {
-            int rr = e >> 7, cc = e & 127;
-            int64_t k = k0 + rr, j = j0 + cc;
-            if (j < p && k < p) S[k * p + j] = sm.out[cc][rr];
+            const int rr = e >> 7, cc = e & 127;
+            const int64_t j = j0 + rr, k = k0 + cc;
+            if (j < p && k < p)
+                S[j * p + k] = (j == k) ? 1.0f
+                                        : ((diag && rr > cc) ? outc[cc * kBfOutLd + rr] : outc[rr * kBfOutLd + cc]);
+        }
+        if (!diag) {
+            for (int e = tid; e < 128 * 128; e += 256) {
+                const int rr = e >> 7, cc = e & 127;
+                const int64_t k = k0 + rr, j = j0 + cc;
+                if (j < p && k < p) S[k * p + j] = outc[cc * kBfOutLd + rr];
+            }
         }
     }
 }
@@ -282,9 +325,12 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
 void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
                         int64_t p, float *S, hipStream_t s)
 {
+    (void)n;
     int Tt = (int)((p + 127) / 128);
     int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
-    hipLaunchKernelGGL(k_syrk_bf16x3, dim3((unsigned)ntiles), dim3(256), 0, s, hi, lo, npad, p, S,
+    // two blocks per CU (the LDS of a block), at most one per tile
+    int64_t grid = ntiles < 512 ? ntiles : 512;
+    hipLaunchKernelGGL(k_syrk_bf16x3, dim3((unsigned)grid), dim3(256), kBfLds, s, hi, lo, npad, p, S,
                        Tt, (float)(1.0 / (double)n));
 }
 

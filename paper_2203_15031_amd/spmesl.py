@@ -29,6 +29,7 @@ EWORKSET = -8
 FP64, FP32, MIXED = 0, 1, 2
 SCALE_ORIGINAL, SCALE_STANDARDIZED = 0, 1
 FLAG_TIMING = 1
+FLAG_EAGER = 2
 MAX_WORKING_SET = 128
 
 _PRECISION = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
@@ -99,12 +100,16 @@ def load():
     lib.spmesl_solve.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result)]
     lib.spmesl_solve.restype = C.c_int
     lib.spmesl_solve_batch.argtypes = [vp, C.c_int, C.POINTER(Problem), C.POINTER(Options),
-                                       C.POINTER(Result), C.POINTER(C.c_int)]
+                                       C.POINTER(C.c_double), C.POINTER(Result), C.POINTER(C.c_int)]
+    lib.spmesl_solve_async.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result), vp]
+    lib.spmesl_solve_async.restype = C.c_int
     lib.spmesl_solve_batch.restype = C.c_int
     lib.spmesl_covariance.argtypes = [vp, C.POINTER(Problem), C.c_int, vp, vp, vp]
     lib.spmesl_covariance.restype = C.c_int
     lib.spmesl_symmetrize.argtypes = [vp, i64, vp, vp]
     lib.spmesl_symmetrize.restype = C.c_int
+    lib.spmesl_kernel_times.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double)]
+    lib.spmesl_kernel_times.restype = C.c_int
     for f in ("spmesl_lambda_univ", "spmesl_lambda_ub"):
         getattr(lib, f).argtypes = [C.c_double, C.c_double]
         getattr(lib, f).restype = C.c_double
@@ -212,11 +217,11 @@ class Context:
 
     @staticmethod
     def options(lambda0, tol=1e-8, precision="fp64", output_scale="original", max_outer=0,
-                max_sweeps=0, max_rounds=0, timing=False):
+                max_sweeps=0, max_rounds=0, timing=False, eager=False):
         return Options(float(lambda0), float(tol), int(max_outer), int(max_sweeps),
                        int(max_rounds), _PRECISION[precision] if isinstance(precision, str) else int(precision),
                        _SCALE[output_scale] if isinstance(output_scale, str) else int(output_scale),
-                       FLAG_TIMING if timing else 0)
+                       (FLAG_TIMING if timing else 0) | (FLAG_EAGER if eager else 0))
 
     @staticmethod
     def problem(X):
@@ -235,15 +240,41 @@ class Context:
     # -- entry points -------------------------------------------------------
     def solve(self, X, lambda0, tol=1e-8, precision="fp64", output_scale="original",
               want=("B", "sigma", "Omega"), out=None, max_outer=0, max_sweeps=0, max_rounds=0,
-              timing=False, check=True) -> SolveResult:
+              timing=False, check=True, eager=False) -> SolveResult:
         """Full SPMESL of X (n x p float64 CUDA tensor).
 
         Returns B (p x p, column k = beta of response k), sigma (p) and the
         symmetrised Omega (p x p).  `out` may hold preallocated output
         tensors.  Raises SpmeslError on any code other than OK and (when
-        check is False) ENOCONV."""
+        check is False) ENOCONV.  eager=True enqueues kernel by kernel
+        instead of replaying the context's graph of a repeated call."""
         opt = self.options(lambda0, tol, precision, output_scale, max_outer, max_sweeps,
-                           max_rounds, timing)
+                           max_rounds, timing, eager)
+        prob, res, out, stats = self._prepare(X, opt, want, out)
+        st = load().spmesl_solve(self._h, C.byref(prob), C.byref(opt), C.byref(res))
+        if st != OK and (check or st != ENOCONV):
+            raise SpmeslError(st, self._err())
+        return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), st, stats.as_dict())
+
+    def solve_async(self, X, lambda0, status, tol=1e-8, precision="fp64", output_scale="original",
+                    want=("B", "sigma", "Omega"), out=None, eager=False) -> SolveResult:
+        """Enqueue a full solve on torch's current stream without waiting.
+
+        `status` is a one-element int32 CUDA tensor that receives the status
+        code when the solve completes on the stream.  Returns the output
+        tensors (valid once the stream has reached that point); stats are
+        not reported."""
+        if status.dtype != torch.int32 or status.device != X.device or status.numel() < 1:
+            raise ValueError("status must be an int32 tensor on the device of X")
+        opt = self.options(lambda0, tol, precision, output_scale, eager=eager)
+        prob, res, out, _ = self._prepare(X, opt, want, out)
+        st = load().spmesl_solve_async(self._h, C.byref(prob), C.byref(opt), C.byref(res),
+                                       C.c_void_p(status.data_ptr()))
+        if st != OK:
+            raise SpmeslError(st, self._err())
+        return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), OK, {})
+
+    def _prepare(self, X, opt, want, out):
         prob = self.problem(X)
         p = prob.p
         dev = X.device
@@ -261,47 +292,43 @@ class Context:
                      _ptr(out.get("Omega")).value, C.pointer(stats))
         self._workspace(self.workspace_size(X, opt) + 4096)
         self._bind_stream()
-        st = load().spmesl_solve(self._h, C.byref(prob), C.byref(opt), C.byref(res))
-        if st != OK and (check or st != ENOCONV):
-            raise SpmeslError(st, self._err())
-        return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), st, stats.as_dict())
+        return prob, res, out, stats
 
     def solve_batch(self, Xs, lambda0s, tol=1e-8, precision="fp64", output_scale="original",
-                    check=True):
-        """Solve several datasets (uneven n, p); lambda0s is one value or one
-        per dataset.  Datasets that share lambda0 go in one library call."""
+                    check=True, outs=None, eager=False):
+        """Solve several datasets (uneven n, p) in one library call; lambda0s
+        is one value or one per dataset.  `outs` may hold one dict of
+        preallocated B / sigma / Omega tensors per dataset (a repeated call
+        with the same tensors replays the context's graph of the batch)."""
+        m = len(Xs)
         if not isinstance(lambda0s, (list, tuple)):
-            lambda0s = [lambda0s] * len(Xs)
-        results = [None] * len(Xs)
-        groups = {}
-        for i, lam in enumerate(lambda0s):
-            groups.setdefault(float(lam), []).append(i)
-        for lam, idx in groups.items():
-            opt = self.options(lam, tol, precision, output_scale)
-            probs = (Problem * len(idx))(*[self.problem(Xs[i]) for i in idx])
-            stats = [Stats() for _ in idx]
-            outs = []
-            ress = (Result * len(idx))()
-            need = 0
-            for j, i in enumerate(idx):
-                p = Xs[i].shape[1]
-                o = dict(B=torch.empty((p, p), dtype=torch.float64, device=Xs[i].device),
-                         sigma=torch.empty((p,), dtype=torch.float64, device=Xs[i].device),
-                         Omega=torch.empty((p, p), dtype=torch.float64, device=Xs[i].device))
-                outs.append(o)
-                ress[j] = Result(o["B"].data_ptr(), o["sigma"].data_ptr(), o["Omega"].data_ptr(),
-                                 C.pointer(stats[j]))
-                need = max(need, self.workspace_size(Xs[i], opt))
-            self._workspace(need + 4096 * (len(idx) + 1))
-            self._bind_stream()
-            status = (C.c_int * len(idx))()
-            st = load().spmesl_solve_batch(self._h, len(idx), probs, C.byref(opt), ress, status)
-            if st != OK and (check or st != ENOCONV):
-                raise SpmeslError(st, self._err())
-            for j, i in enumerate(idx):
-                o = outs[j]
-                results[i] = SolveResult(o["B"], o["sigma"], o["Omega"], status[j], stats[j].as_dict())
-        return results
+            lambda0s = [lambda0s] * m
+        opt = self.options(lambda0s[0] if m else 1.0, tol, precision, output_scale, eager=eager)
+        probs = (Problem * m)(*[self.problem(X) for X in Xs])
+        lams = (C.c_double * m)(*[float(v) for v in lambda0s])
+        stats = [Stats() for _ in range(m)]
+        ress = (Result * m)()
+        outs = list(outs) if outs is not None else [None] * m
+        need = 0
+        for i, X in enumerate(Xs):
+            p = X.shape[1]
+            o = outs[i]
+            if o is None:
+                o = dict(B=torch.empty((p, p), dtype=torch.float64, device=X.device),
+                         sigma=torch.empty((p,), dtype=torch.float64, device=X.device),
+                         Omega=torch.empty((p, p), dtype=torch.float64, device=X.device))
+                outs[i] = o
+            ress[i] = Result(_ptr(o.get("B")).value, _ptr(o.get("sigma")).value,
+                             _ptr(o.get("Omega")).value, C.pointer(stats[i]))
+            need = max(need, self.workspace_size(X, self.options(lams[i], tol, precision, output_scale)))
+        self._workspace(need + 4096 * (m + 1))
+        self._bind_stream()
+        status = (C.c_int * max(m, 1))()
+        st = load().spmesl_solve_batch(self._h, m, probs, C.byref(opt), lams, ress, status)
+        if st != OK and (check or st != ENOCONV):
+            raise SpmeslError(st, self._err())
+        return [SolveResult(outs[i].get("B"), outs[i].get("sigma"), outs[i].get("Omega"), status[i],
+                            stats[i].as_dict()) for i in range(m)]
 
     def covariance(self, X, precision="fp64"):
         """Standardise X and form S; returns (S, mean, scale)."""
@@ -319,6 +346,17 @@ class Context:
         if st != OK:
             raise SpmeslError(st, self._err())
         return S, mean, scale
+
+    def kernel_times(self):
+        """[(name, ms)] of each launch step of the last solve run with timing=True."""
+        lib = load()
+        n = lib.spmesl_kernel_times(self._h, 0, None, None)
+        if n < 0:
+            raise SpmeslError(n, self._err())
+        names = (C.c_char_p * max(n, 1))()
+        ms = (C.c_double * max(n, 1))()
+        n = lib.spmesl_kernel_times(self._h, n, names, ms)
+        return [(names[i].decode(), float(ms[i])) for i in range(n)]
 
     def symmetrize(self, Omega1):
         if Omega1.dtype != torch.float64 or not Omega1.is_cuda or not Omega1.is_contiguous():

@@ -249,10 +249,20 @@ def test_solve_batch_matches_single_solves(ctx):
     Xg = [gpu(X) for X in Xs]
     for prec in ("fp64", "mixed"):
         res = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec)
+        outs = [dict(B=r.B, sigma=r.sigma, Omega=r.Omega) for r in res]
         for X, Xd, lam, r in zip(Xs, Xg, lams, res):
             assert r.status == 0
-            one = ctx.solve(Xd, lam, tol=1e-8, precision=prec)
+            one = ctx.solve(Xd, lam, tol=1e-8, precision=prec, eager=True)
             assert torch.equal(r.Omega, one.Omega) and torch.equal(r.B, one.B)
+        first = [(r.B.clone(), r.Omega.clone()) for r in res]
+        # the same call again replays the batch's graph into the same outputs
+        for o in outs:
+            o["B"].fill_(7.0)
+            o["Omega"].fill_(7.0)
+        res2 = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec, outs=outs)
+        for (B1, O1), r in zip(first, res2):
+            assert r.status == 0
+            assert torch.equal(r.B, B1) and torch.equal(r.Omega, O1)
     # and against the oracle on two of them
     for i in (0, 3):
         ref = oracle.spmesl(Xs[i], lams[i], tol=1e-12)
@@ -276,3 +286,63 @@ def test_scale_free_p20000_sampled_columns(ctx, prec, bar):
     for i in range(len(cols)):
         assert rel_err(B[:, i], ref["B"][:, i]) <= bar
         assert abs(sig[i] - ref["sigma"][i]) <= bar * ref["sigma"][i]
+
+
+# ---------------------------------------------------------------------------
+# graph replay and the asynchronous entry point
+# ---------------------------------------------------------------------------
+
+def test_graph_replays_match_eager(ctx):
+    """A repeated call replays the context's captured graph; every replay,
+    with other eager work and synchronisations between replays, equals the
+    eager (kernel by kernel) result."""
+    X = gpu(W.generate("er_n200_p1000"))
+    lam = W.workload("er_n200_p1000").lambda0
+    X2 = gpu(W.generate("ar1_n100_p200"))
+    lam2 = W.workload("ar1_n100_p200").lambda0
+    p = X.shape[1]
+    for prec in ("fp64", "mixed"):
+        ref = ctx.solve(X, lam, tol=1e-8, precision=prec, eager=True)
+        out = dict(B=torch.empty((p, p), dtype=torch.float64, device=X.device),
+                   sigma=torch.empty((p,), dtype=torch.float64, device=X.device),
+                   Omega=torch.empty((p, p), dtype=torch.float64, device=X.device))
+        for rep in range(4):
+            for t in out.values():
+                t.fill_(float(rep + 3))
+            r = ctx.solve(X, lam, tol=1e-8, precision=prec, out=out)
+            torch.cuda.synchronize()
+            assert r.status == 0, (prec, rep)
+            assert torch.equal(r.B, ref.B) and torch.equal(r.sigma, ref.sigma), (prec, rep)
+            assert torch.equal(r.Omega, ref.Omega), (prec, rep)
+            assert r.stats["total_updates"] == ref.stats["total_updates"], (prec, rep)
+            # other work between replays: an eager solve of another problem
+            # and plain torch kernels
+            other = ctx.solve(X2, lam2, tol=1e-8, precision=prec, eager=True)
+            assert other.status == 0
+            (X2 * 2.0).sum().item()
+
+
+def test_solve_async_status_and_outputs(ctx, sp):
+    X = gpu(W.generate("ar1_n100_p200"))
+    lam = W.workload("ar1_n100_p200").lambda0
+    p = X.shape[1]
+    status = torch.full((1,), 99, dtype=torch.int32, device=X.device)
+    for prec in ("fp64", "mixed"):
+        ref = ctx.solve(X, lam, tol=1e-8, precision=prec, eager=True)
+        out = dict(B=torch.zeros((p, p), dtype=torch.float64, device=X.device),
+                   sigma=torch.zeros((p,), dtype=torch.float64, device=X.device),
+                   Omega=torch.zeros((p, p), dtype=torch.float64, device=X.device))
+        for rep in range(3):
+            status.fill_(99)
+            r = ctx.solve_async(X, lam, status, tol=1e-8, precision=prec, out=out, eager=(rep == 0))
+            torch.cuda.synchronize()
+            assert int(status.item()) == 0
+            assert torch.equal(r.B, ref.B) and torch.equal(r.Omega, ref.Omega)
+            assert torch.equal(r.sigma, ref.sigma)
+    # a device-side failure is reported through the status word
+    Xz = X.clone()
+    Xz[:, 5] = 1.25
+    status.fill_(99)
+    ctx.solve_async(Xz, lam, status, tol=1e-8, precision="fp64")
+    torch.cuda.synchronize()
+    assert int(status.item()) == sp.EZEROVAR
