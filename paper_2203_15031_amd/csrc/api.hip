@@ -363,14 +363,16 @@ static void enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opt
     a.colinfo = (int *)(ws + L.colinfo);
     a.counters = dctl->counters;
     a.flags = &dctl->flags;
-    // first solves
+    // first solves (their screen lists were written with S)
     a.mode = 0;
+    a.screened = 1;
     a.defer_kkt = rj > 0;
     a.esc_cnt = &dctl->esc_a;
     a.esc_list = (int *)(ws + L.esclist);
     launch_colsolve(a, 0, s);
     mark(mk, s, "colsolve_first");
     a.mode = 1;
+    a.screened = 0;
     a.work_list = (const int *)(ws + L.esclist);
     a.work_cnt = &dctl->esc_a;
     launch_colsolve(a, 1, s);
@@ -444,13 +446,29 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     mark(mk, s, "standardize");
     if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
 
+    // the first solves' screen (|s_jk| > lambda0 + tol at beta = 0) is taken
+    // where S is written; the thresholds are formed in S's precision exactly
+    // as the column solver forms them
+    const double tol_cols = L.prec == SPMESL_FP64
+                                ? opt->tol
+                                : std::max(opt->tol, L.prec == SPMESL_MIXED ? kMixedFloatTol
+                                                                            : (double)SPMESL_FP32_TOL_FLOOR);
+    Screen sc;
+    sc.thr64 = opt->lambda0 + tol_cols;
+    {
+        volatile float a = (float)opt->lambda0, b = (float)tol_cols;
+        sc.thr32 = a + b;
+    }
+    sc.cnt = (int *)(ws + L.pendcnt);
+    sc.idx = (int *)(ws + L.pendidx);
+    launch_zero_words((uint32_t *)sc.cnt, p, s);
     if (L.prec == SPMESL_FP64)
-        launch_syrk_f64((const double *)(ws + L.xs), n, p, (double *)(ws + L.S), s);
+        launch_syrk_f64((const double *)(ws + L.xs), n, p, (double *)(ws + L.S), sc, s);
     else if (L.prec == SPMESL_FP32)
-        launch_syrk_f32((const float *)(ws + L.xs), n, p, (float *)(ws + L.S), s);
+        launch_syrk_f32((const float *)(ws + L.xs), n, p, (float *)(ws + L.S), sc, s);
     else
         launch_syrk_bf16x3((const uint16_t *)(ws + L.hi), (const uint16_t *)(ws + L.lo), n, L.npad,
-                           p, (float *)(ws + L.S), s);
+                           p, (float *)(ws + L.S), sc, s);
     mark(mk, s, L.prec == SPMESL_FP64 ? "syrk_f64" : (L.prec == SPMESL_FP32 ? "syrk_f32" : "syrk_bf16x3"));
     if (ev) HIPTRY(ctx, hipEventRecord(ev[2], s));
 
@@ -473,14 +491,11 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     }
 
     if (L.prec == SPMESL_FP64)
-        enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s,
+        enqueue_columns<double>(L, ws, dctl, opt, tol_cols, 0.0, max_outer, max_sweeps, max_rounds, s,
                                 mk);
     else
-        enqueue_columns<float>(L, ws, dctl, opt,
-                               std::max(opt->tol, L.prec == SPMESL_MIXED ? kMixedFloatTol
-                                                                         : (double)SPMESL_FP32_TOL_FLOOR),
-                               L.prec == SPMESL_MIXED ? kMixedBand : 0.0, max_outer, max_sweeps,
-                               max_rounds, s, mk);
+        enqueue_columns<float>(L, ws, dctl, opt, tol_cols, L.prec == SPMESL_MIXED ? kMixedBand : 0.0,
+                               max_outer, max_sweeps, max_rounds, s, mk);
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
 
     if (L.prec == SPMESL_MIXED) {
@@ -919,15 +934,15 @@ int spmesl_covariance(spmesl_ctx *ctx, const spmesl_problem *prob, int precision
                     &dctl->flags, s);
     if (precision == SPMESL_FP64) {
         launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
-        launch_syrk_f64((const double *)(ws + L.xs), n, p, (double *)S_out, s);
+        launch_syrk_f64((const double *)(ws + L.xs), n, p, (double *)S_out, Screen{}, s);
     } else if (precision == SPMESL_FP32) {
         launch_standardize_f32(prob->X, n, p, prob->ldx, mean, scale, (float *)(ws + L.xs), s);
-        launch_syrk_f32((const float *)(ws + L.xs), n, p, (float *)S_out, s);
+        launch_syrk_f32((const float *)(ws + L.xs), n, p, (float *)S_out, Screen{}, s);
     } else {
         launch_standardize_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
                                  (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
         launch_syrk_bf16x3((const uint16_t *)(ws + L.hi), (const uint16_t *)(ws + L.lo), n, L.npad, p,
-                           (float *)S_out, s);
+                           (float *)S_out, Screen{}, s);
     }
     HIPTRY(ctx, hipGetLastError());
     v = ensure_pinned(ctx, 1);

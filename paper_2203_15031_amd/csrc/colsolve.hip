@@ -122,6 +122,36 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         st.lam_used = A.lambda0;
 #pragma unroll
         for (int s = 0; s < ColState<T, LW>::NS; ++s) st.g[s] = st.b[s] = st.sv[s] = T(0);
+        int nc = A.screened ? A.pend_cnt[k] : -1;
+        if (nc > kPendMax) {
+            // too many candidates for the list: screen in the wave below
+            wave_sync();
+            if (lane == 0) A.pend_cnt[k] = 0;
+        } else if (nc >= 0) {
+            // the screen at beta = 0 came with S: W = its candidates
+            for (int i = lane; i < nc; i += kWave) sm.pend[i] = A.pend_idx[k * kPendMax + i];
+            wave_sync();
+            if (lane == 0) A.pend_cnt[k] = 0;
+            int np = nc > 0 ? sort_unique_small(sm.pend, nc) : 0;
+            if (np > LW) {
+                if (tier == 0) {
+                    escalate(A, k, sm, st, np, cnt, rounds);
+                    return;
+                }
+                np = LW;
+            }
+            if (np > 0) {
+                ++rounds;
+                merge_pending(sm, st, np);
+                load_working_set(A.S, p, k, sm, st, rlo, rhi);
+                status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+                if (A.defer_kkt && status == kColOk) deferred = true;
+            } else if (A.defer_kkt) {
+                // beta = 0 passes the screen; the row-tiled pass still
+                // records the column's near-threshold band (mixed form)
+                deferred = true;
+            }
+        }
     } else {
         st.w = A.w_cnt[k];
         st.w = st.w < 0 ? 0 : (st.w > LW ? LW : st.w);
@@ -164,7 +194,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         }
     }
 
-    while (status == kColOk) {
+    while (status == kColOk && !deferred) {
         int ns = build_support(sm, st);
         int npend = kkt_pass(A.S, p, k, sm, st.w, ns, st.lam_used + A.kkt_tol, band,
                              st.lam_used - A.band, A.band_cnt, A.band_idx);

@@ -125,10 +125,20 @@ void launch_standardize_split(const double *X, int64_t n, int64_t p, int64_t ldx
                               uint16_t *hi, uint16_t *lo, int64_t npad, hipStream_t s);
 
 // S = Xs^T Xs / n with unit diagonal (p x p row-major, full).
-void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, hipStream_t s);
-void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, hipStream_t s);
+// Screen of the first solves, done where S is written: for every column k
+// the entries j != k with |s_jk| > thr (lambda0 + tol in S's precision, the
+// KKT test at beta = 0) are appended to cnt[k] / idx[k * kPendMax + ...]
+// (cnt counts past kPendMax; cnt zeroed beforehand).  cnt == nullptr: none.
+struct Screen {
+    double thr64;
+    float thr32;
+    int *cnt;
+    int *idx;
+};
+void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, const Screen &sc, hipStream_t s);
+void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, const Screen &sc, hipStream_t s);
 void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
-                        int64_t p, float *S, hipStream_t s);
+                        int64_t p, float *S, const Screen &sc, hipStream_t s);
 
 // Per-column working-set scaled lasso (see colsolve.hip).
 template <typename T>
@@ -142,6 +152,7 @@ struct ColArgs {
     int max_outer, max_sweeps, max_rounds;
     int mode;            // 0: fresh (screen + solve); 1: resume from the stored state
     int defer_kkt;       // fresh mode: stop after the first solve (the row-tiled pass checks)
+    int screened;        // fresh mode: pend_cnt / pend_idx hold the screen (see Screen)
     const int *work_list;// resume mode: columns work_list[0 .. *work_cnt)
     const int *work_cnt;
     int *w_cnt;          // [p]

@@ -44,6 +44,49 @@ template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return 4 * r + (lane >> 4); }
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
 
+// The screen (see Screen): entry s_jk = v makes j a candidate of column k.
+// Candidates of a tile are collected in LDS (a short list; an LDS atomic
+// returns quickly) and flushed with one round of global atomics per tile, so
+// no wave waits on a global atomic inside the store loops.
+constexpr int kScreenTile = 512;  // candidates a tile collects before storing directly
+
+struct ScreenLds {
+    int n;
+    int jk[2 * kScreenTile];
+};
+
+template <typename T>
+__device__ __forceinline__ void screen_entry(ScreenLds &L, int *cnt, int *idx, T thr, int64_t j,
+                                             int64_t k, T v)
+{
+    const bool hit = cnt && j != k && (v < T(0) ? -v : v) > thr;
+    if (!__ballot(hit)) return;  // the common case: one wave-uniform branch
+    if (hit) {
+        const int q = atomicAdd(&L.n, 1);
+        if (q < kScreenTile) {
+            L.jk[2 * q] = (int)j;
+            L.jk[2 * q + 1] = (int)k;
+        } else {
+            const int pos = atomicAdd(&cnt[k], 1);
+            if (pos < kPendMax) idx[k * kPendMax + pos] = (int)j;
+        }
+    }
+}
+
+// After the tile's entries are collected (and a barrier): store them.  The
+// persistent kernel calls this for a tile while the next tile's first stage
+// is being copied, so the atomics' round trip overlaps the copy.
+__device__ __forceinline__ void screen_flush(ScreenLds &L, int *cnt, int *idx)
+{
+    if (!cnt) return;
+    const int m = L.n < kScreenTile ? L.n : kScreenTile;
+    for (int q = threadIdx.x; q < m; q += blockDim.x) {
+        const int j = L.jk[2 * q], k = L.jk[2 * q + 1];
+        const int pos = atomicAdd(&cnt[k], 1);
+        if (pos < kPendMax) idx[(int64_t)k * kPendMax + pos] = j;
+    }
+}
+
 // Map a linear block id to an upper-triangle tile (bj <= bk), with blocks
 // that share a row panel kept on the same XCD (blocks are dispatched to
 // the 8 XCDs round-robin).
@@ -65,7 +108,8 @@ constexpr int kSyrkKC = 32;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int64_t n, int64_t p,
-                                                   T *__restrict__ S, int Tt, T invn)
+                                                   T *__restrict__ S, int Tt, T invn, T thr,
+                                                   int *__restrict__ scnt, int *__restrict__ sidx)
 {
     typedef typename Acc<T>::type AccT;
     __shared__ union {
@@ -75,9 +119,11 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
         } in;
         T out[64][65];
     } sm;
+    __shared__ ScreenLds scr;
     int bj, bk;
     tile_of_block(Tt, &bj, &bk);
     const int64_t j0 = (int64_t)bj * 64, k0 = (int64_t)bk * 64;
+    if (threadIdx.x == 0) scr.n = 0;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
     AccT acc[2][2];
@@ -143,34 +189,43 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
     for (int e = tid; e < 64 * 64; e += 256) {
         int rr = e >> 6, cc = e & 63;
         int64_t j = j0 + rr, k = k0 + cc;
-        if (j < p && k < p)
-            S[j * p + k] = (j == k) ? T(1) : ((diag && rr > cc) ? sm.out[cc][rr] : sm.out[rr][cc]);
+        if (j < p && k < p) {
+            const T v = (j == k) ? T(1) : ((diag && rr > cc) ? sm.out[cc][rr] : sm.out[rr][cc]);
+            S[j * p + k] = v;
+            screen_entry(scr, scnt, sidx, thr, j, k, v);
+        }
     }
     if (bj != bk) {
         for (int e = tid; e < 64 * 64; e += 256) {
             int rr = e >> 6, cc = e & 63;  // row of the mirrored tile = k index
             int64_t k = k0 + rr, j = j0 + cc;
-            if (j < p && k < p) S[k * p + j] = sm.out[cc][rr];
+            if (j < p && k < p) {
+                const T v = sm.out[cc][rr];
+                S[k * p + j] = v;
+                screen_entry(scr, scnt, sidx, thr, k, j, v);
+            }
         }
     }
+    __syncthreads();
+    screen_flush(scr, scnt, sidx);
 }
 
 template <typename T>
-static void launch_syrk_t(const T *Xs, int64_t n, int64_t p, T *S, hipStream_t s)
+static void launch_syrk_t(const T *Xs, int64_t n, int64_t p, T *S, T thr, const Screen &sc, hipStream_t s)
 {
     int Tt = (int)((p + 63) / 64);
     int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
     hipLaunchKernelGGL(k_syrk_mfma<T>, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
-                       (T)(1.0 / (double)n));
+                       (T)(1.0 / (double)n), thr, sc.cnt, sc.idx);
 }
 
-void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, hipStream_t s)
+void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, const Screen &sc, hipStream_t s)
 {
-    launch_syrk_t<double>(Xs, n, p, S, s);
+    launch_syrk_t<double>(Xs, n, p, S, sc.thr64, sc, s);
 }
-void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, hipStream_t s)
+void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, const Screen &sc, hipStream_t s)
 {
-    launch_syrk_t<float>(Xs, n, p, S, s);
+    launch_syrk_t<float>(Xs, n, p, S, sc.thr32, sc, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -193,8 +248,9 @@ constexpr int kBfKC = 64;                   // samples per stage
 constexpr int kBfPanel = 128 * kBfKC * 2;   // bytes of one panel (16 KB)
 constexpr int kBfStage = 4 * kBfPanel;      // hi_J, lo_J, hi_K, lo_K
 constexpr int kBfOutLd = 129;               // padded row of the staged output tile
-constexpr int kBfLds = 128 * kBfOutLd * 4;  // output tile; the stage fits inside
-static_assert(kBfLds >= kBfStage, "stage and output tile share the LDS");
+constexpr int kBfOut = 128 * kBfOutLd * 4;  // output tile; the stage fits inside
+static_assert(kBfOut >= kBfStage, "stage and output tile share the LDS");
+constexpr int kBfLds = kBfOut + (int)sizeof(ScreenLds);  // + the tile's screen candidates
 
 __device__ __forceinline__ int bf_swz(int m) { return (m & 7) ^ ((m >> 3) & 1); }
 
@@ -235,7 +291,9 @@ __device__ __forceinline__ void bf_issue(const uint16_t *__restrict__ hi, const 
 __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict__ hi,
                                                      const uint16_t *__restrict__ lo,
                                                      int64_t npad, int64_t p,
-                                                     float *__restrict__ S, int Tt, float invn)
+                                                     float *__restrict__ S, int Tt, float invn,
+                                                     float thr, int *__restrict__ scnt,
+                                                     int *__restrict__ sidx)
 {
     extern __shared__ __align__(16) unsigned char bf_lds[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -248,6 +306,8 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
     const int tbeg = x * q + (x < r ? x : r), tend = tbeg + q + (x < r ? 1 : 0);
     const int nst = (int)(npad / kBfKC);
 
+    ScreenLds &scr = *reinterpret_cast<ScreenLds *>(bf_lds + kBfOut);
+    bool pending = false;  // the previous tile's screen candidates await their flush
     int t = tbeg + slot;
     for (; t < tend; t += nbx) {
         int bj, bk;
@@ -263,6 +323,7 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
         for (int st = 0; st < nst; ++st) {
             __syncthreads();
             bf_issue(hi, lo, npad, p, j0, k0, (int64_t)st * kBfKC, diag, bf_lds);
+            if (st == 0 && pending) screen_flush(scr, scnt, sidx);  // the previous tile's
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             const unsigned char *sb = bf_lds;
@@ -295,6 +356,8 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
             }
         }
         __syncthreads();
+        // every thread is past the previous tile's flush (stage barriers)
+        if (tid == 0) scr.n = 0;
         float *outc = reinterpret_cast<float *>(bf_lds);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -308,22 +371,34 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
         for (int e = tid; e < 128 * 128; e += 256) {
             const int rr = e >> 7, cc = e & 127;
             const int64_t j = j0 + rr, k = k0 + cc;
-            if (j < p && k < p)
-                S[j * p + k] = (j == k) ? 1.0f
-                                        : ((diag && rr > cc) ? outc[cc * kBfOutLd + rr] : outc[rr * kBfOutLd + cc]);
+            if (j < p && k < p) {
+                const float v = (j == k) ? 1.0f
+                                         : ((diag && rr > cc) ? outc[cc * kBfOutLd + rr] : outc[rr * kBfOutLd + cc]);
+                S[j * p + k] = v;
+                screen_entry(scr, scnt, sidx, thr, j, k, v);
+            }
         }
         if (!diag) {
             for (int e = tid; e < 128 * 128; e += 256) {
                 const int rr = e >> 7, cc = e & 127;
                 const int64_t k = k0 + rr, j = j0 + cc;
-                if (j < p && k < p) S[k * p + j] = outc[cc * kBfOutLd + rr];
+                if (j < p && k < p) {
+                    const float v = outc[cc * kBfOutLd + rr];
+                    S[k * p + j] = v;
+                    screen_entry(scr, scnt, sidx, thr, k, j, v);
+                }
             }
         }
+        pending = true;
+    }
+    if (pending) {
+        __syncthreads();
+        screen_flush(scr, scnt, sidx);
     }
 }
 
 void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
-                        int64_t p, float *S, hipStream_t s)
+                        int64_t p, float *S, const Screen &sc, hipStream_t s)
 {
     (void)n;
     int Tt = (int)((p + 127) / 128);
@@ -331,7 +406,7 @@ void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64
     // two blocks per CU (the LDS of a block), at most one per tile
     int64_t grid = ntiles < 512 ? ntiles : 512;
     hipLaunchKernelGGL(k_syrk_bf16x3, dim3((unsigned)grid), dim3(256), kBfLds, s, hi, lo, npad, p, S,
-                       Tt, (float)(1.0 / (double)n));
+                       Tt, (float)(1.0 / (double)n), sc.thr32, sc.cnt, sc.idx);
 }
 
 } // namespace spmesl
