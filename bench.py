@@ -53,6 +53,39 @@ def kernel_costs(n, p, prec):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blockar_n400_p5000_hbm_traffic.md")
+CSRC = os.path.join(ROOT, "paper_2203_15031_amd", "csrc")
+# step name -> (row label in the traffic summary, source files of its kernel)
+TRAFFIC_ROWS = {
+    ("syrk_bf16x3", None): ("syrk_bf16x3", ["syrk.hip"]),
+    ("syrk_f64", None): ("syrk_f64", ["syrk.hip"]),
+    ("kkt_rows", "fp64"): ("kkt_rows (double)", ["kkt.hip"]),
+    ("kkt_rows", "mixed"): ("kkt_rows (float)", ["kkt.hip"]),
+    ("fill_B", None): ("fill_B / fill_Omega", ["output.hip"]),
+    ("fill_Omega", None): ("fill_B / fill_Omega", ["output.hip"]),
+}
+
+
+def measured_traffic(step, prec):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or None when
+    there is none for this step or its kernel's source has changed since."""
+    import hashlib
+    key = TRAFFIC_ROWS.get((step, prec)) or TRAFFIC_ROWS.get((step, None))
+    if key is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    label, files = key
+    h = hashlib.sha1()
+    for fn in files:
+        with open(os.path.join(CSRC, fn), "rb") as fh:
+            h.update(fh.read())
+    for line in open(TRAFFIC_FILE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == label:
+            return float(cells[5]) if cells[6] == h.hexdigest()[:12] else None
+    return None
+
+
 def roofline_of(name, ms, cost):
     """Roofline of one kernel launch: algorithmic bytes or flops / its time."""
     nbytes, flops, fdt = cost
@@ -96,13 +129,18 @@ def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
     ms = e0.elapsed_time(e1) / steps
     if int(status.item()) != 0:
         raise RuntimeError(f"{prec} solve returned status {int(status.item())}")
-    # one call at a time: each call waits for its solve and reads its status
-    e0.record(stream)
-    for _ in range(steps):
+    # one call at a time: each call waits for its solve and reads its status;
+    # each call is bracketed by its own events (median, min, max per call)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
         r = ctx.solve(X, lam0, tol, prec, out=out)
-    e1.record(stream)
+        b.record(stream)
     torch.cuda.synchronize()
-    ms_sync = e0.elapsed_time(e1) / steps
+    per_call = sorted(a.elapsed_time(b) for a, b in ev)
+    ms_sync = {"median": per_call[len(per_call) // 2], "min": per_call[0], "max": per_call[-1],
+               "mean": sum(per_call) / len(per_call)}
     # the same solves with the library's HIP events: per phase, and per
     # kernel launch on the stream each kernel runs on
     ph = {k: 0.0 for k in ("standardize", "covariance", "solve", "polish", "output", "total")}
@@ -181,6 +219,18 @@ def bench_batch(args, torch, spmesl, workloads):
     print(json.dumps(line), flush=True)
 
 
+def copy_calibration(torch):
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiler run."""
+    nbytes = 512 << 20
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +238,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 512 MiB device to device five times (profiler calibration)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="blockar_n400_p5000 (headline), sf_n1000_p20000, or hub_batch64")
     args = ap.parse_args()
@@ -198,6 +250,8 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        return copy_calibration(torch)
     from paper_2203_15031_amd import spmesl, workloads
 
     if args.workload == "hub_batch64":
@@ -212,7 +266,7 @@ def main():
     for prec in forms:
         ms, ms_sync, ph, kern, r = time_form(ctx, X, lam0, tol, prec, args.steps, args.warmup, torch)
         res[prec] = (ms, ms_sync, ph, kern, r)
-        print(f"[bench] {prec}: {ms:.3f} ms/solve pipelined, {ms_sync:.3f} one call at a time; phases " +
+        print(f"[bench] {prec}: {ms:.3f} ms/solve pipelined, {ms_sync['median']:.3f} median one call at a time; phases " +
               " ".join(f"{k}={v:.4f}" for k, v in ph.items()), file=sys.stderr, flush=True)
         print(f"[bench] {prec} kernels: " +
               " ".join(f"{k}={v['ms_per_solve']:.4f}" for k, v in kern.items()), file=sys.stderr, flush=True)
@@ -227,9 +281,15 @@ def main():
     roof = roofline_of(dom, main[dom]["ms_per_launch"], costs.get(dom, (0.0, 0.0, None)))
     if dom not in costs:
         roof["note"] = "latency-bound step with no algorithmic byte count; achieved is 0"
-    kernels = {k: dict(ms_per_solve=round(v["ms_per_solve"], 5), launches=v["launches"],
-                       **({"roofline": roofline_of(k, v["ms_per_launch"], costs[k])} if k in costs else {}))
-               for k, v in kern.items()}
+    on_traffic = args.workload == WORKLOAD
+    roof["traffic"] = measured_traffic(dom, head) if on_traffic else None
+    kernels = {}
+    for k, v in kern.items():
+        kernels[k] = dict(ms_per_solve=round(v["ms_per_solve"], 5), launches=v["launches"])
+        if k in costs:
+            rk = roofline_of(k, v["ms_per_launch"], costs[k])
+            rk["traffic"] = measured_traffic(k, head) if on_traffic else None
+            kernels[k]["roofline"] = rk
     line = {
         "metric": "full SPMESL solves/s at p=5000 (mixed vs FP64), % MFMA/HBM roofline",
         "value": round(1000.0 / ms, 3),
@@ -238,7 +298,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
-        "ms_per_solve_one_call_at_a_time": round(ms_sync, 4),
+        "ms_per_solve_one_call_at_a_time": {k: round(v, 4) for k, v in ms_sync.items()},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -256,7 +316,7 @@ def main():
     for prec in forms[1:]:
         ms2, ms2_sync, ph2, kern2, r2 = res[prec]
         line[prec] = {"value": round(1000.0 / ms2, 3), "ms_per_step": round(ms2, 4),
-                      "ms_per_solve_one_call_at_a_time": round(ms2_sync, 4),
+                      "ms_per_solve_one_call_at_a_time": {k: round(v, 4) for k, v in ms2_sync.items()},
                       "phases_ms": {k: round(v, 4) for k, v in ph2.items()},
                       "kernels_ms": {k: round(v["ms_per_solve"], 5) for k, v in kern2.items()}}
         line["speedup_vs_" + prec] = round(ms2 / ms, 3)

@@ -434,7 +434,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     launch_zero_words((uint32_t *)dctl, sizeof(Ctl) / 4, s);
     mark(mk, s, "zero_control");
     launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
-                    &dctl->flags, s);
+                    &dctl->flags, (int *)(ws + L.pendcnt), s);
     mark(mk, s, "colstats");
     if (L.prec == SPMESL_FP64)
         launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
@@ -459,9 +459,8 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         volatile float a = (float)opt->lambda0, b = (float)tol_cols;
         sc.thr32 = a + b;
     }
-    sc.cnt = (int *)(ws + L.pendcnt);
+    sc.cnt = (int *)(ws + L.pendcnt);  // zeroed by the column statistics
     sc.idx = (int *)(ws + L.pendidx);
-    launch_zero_words((uint32_t *)sc.cnt, p, s);
     if (L.prec == SPMESL_FP64)
         launch_syrk_f64((const double *)(ws + L.xs), n, p, (double *)(ws + L.S), sc, s);
     else if (L.prec == SPMESL_FP32)
@@ -931,7 +930,7 @@ int spmesl_covariance(spmesl_ctx *ctx, const spmesl_problem *prob, int precision
     double *scale = scale_out ? scale_out : (double *)(ws + L.scale);
     launch_zero_words((uint32_t *)dctl, sizeof(Ctl) / 4, s);
     launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
-                    &dctl->flags, s);
+                    &dctl->flags, nullptr, s);
     if (precision == SPMESL_FP64) {
         launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
         launch_syrk_f64((const double *)(ws + L.xs), n, p, (double *)S_out, Screen{}, s);

@@ -108,7 +108,7 @@ __device__ __forceinline__ T soft_threshold(T a, T lam)
 // 2 * rchunks * p doubles.  flags[0] |= 1 on a non-finite value, |= 2 on a
 // zero-variance column.
 void launch_colstats(const double *X, int64_t n, int64_t p, int64_t ldx, double *partial,
-                     int rchunks, double *mean, double *scale, int *flags, hipStream_t s);
+                     int rchunks, double *mean, double *scale, int *flags, int *zero_cnt, hipStream_t s);
 int colstats_rchunks(int64_t n, int64_t p);
 
 // Xs = (X - mean) * scale, n x p row-major (ld p), double.

@@ -54,10 +54,12 @@ __global__ __launch_bounds__(256) void k_colstats_final(const double *__restrict
                                                         const double *__restrict__ partial,
                                                         double *__restrict__ mean,
                                                         double *__restrict__ scale,
-                                                        int *__restrict__ flags)
+                                                        int *__restrict__ flags,
+                                                        int *__restrict__ zero_cnt)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= p) return;
+    if (zero_cnt) zero_cnt[j] = 0;  // a per-column counter the covariance kernel appends to
     double s1 = 0.0, s2 = 0.0;
     // fixed summation order; loads issued eight chunks at a time
     for (int r0 = 0; r0 < rchunks; r0 += 8) {
@@ -106,13 +108,13 @@ int colstats_rchunks(int64_t n, int64_t p)
 }
 
 void launch_colstats(const double *X, int64_t n, int64_t p, int64_t ldx, double *partial,
-                     int rchunks, double *mean, double *scale, int *flags, hipStream_t s)
+                     int rchunks, double *mean, double *scale, int *flags, int *zero_cnt, hipStream_t s)
 {
     int64_t rows_per = (n + rchunks - 1) / rchunks;
     dim3 g((unsigned)((p + 255) / 256), (unsigned)rchunks);
     hipLaunchKernelGGL(k_colstats_partial, g, dim3(256), 0, s, X, n, p, ldx, rows_per, partial);
     hipLaunchKernelGGL(k_colstats_final, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, s, X, n,
-                       p, rchunks, partial, mean, scale, flags);
+                       p, rchunks, partial, mean, scale, flags, zero_cnt);
 }
 
 template <typename T>
