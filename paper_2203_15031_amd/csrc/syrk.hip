@@ -48,24 +48,23 @@ template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { ret
 // Candidates of a tile are collected in LDS (a short list; an LDS atomic
 // returns quickly) and flushed with one round of global atomics per tile, so
 // no wave waits on a global atomic inside the store loops.
-constexpr int kScreenTile = 512;  // candidates a tile collects before storing directly
-
+template <int N>
 struct ScreenLds {
+    static constexpr int kCap = N;  // candidates a tile collects before storing directly
     int n;
-    int jk[2 * kScreenTile];
+    int jk[2 * N];
 };
 
-template <typename T>
-__device__ __forceinline__ void screen_entry(ScreenLds &L, int *cnt, int *idx, T thr, int64_t j,
-                                             int64_t k, T v)
+template <typename L, typename T>
+__device__ __forceinline__ void screen_entry(L &lst, int *cnt, int *idx, T thr, int64_t j, int64_t k, T v)
 {
     const bool hit = cnt && j != k && (v < T(0) ? -v : v) > thr;
     if (!__ballot(hit)) return;  // the common case: one wave-uniform branch
     if (hit) {
-        const int q = atomicAdd(&L.n, 1);
-        if (q < kScreenTile) {
-            L.jk[2 * q] = (int)j;
-            L.jk[2 * q + 1] = (int)k;
+        const int q = atomicAdd(&lst.n, 1);
+        if (q < L::kCap) {
+            lst.jk[2 * q] = (int)j;
+            lst.jk[2 * q + 1] = (int)k;
         } else {
             const int pos = atomicAdd(&cnt[k], 1);
             if (pos < kPendMax) idx[k * kPendMax + pos] = (int)j;
@@ -73,17 +72,119 @@ __device__ __forceinline__ void screen_entry(ScreenLds &L, int *cnt, int *idx, T
     }
 }
 
+// Entry s_jk = s_kj = v of a symmetric pair (j != k) makes j a candidate of
+// column k and k one of column j; v = 0 records nothing.  The wave's hits
+// take their list slots with one LDS atomic.
+template <typename L, typename T>
+__device__ __forceinline__ void screen_pair(L &lst, int *cnt, int *idx, T thr, int64_t j, int64_t k, T v)
+{
+    const bool hit = cnt && j != k && (v < T(0) ? -v : v) > thr;
+    const unsigned long long mask = __ballot(hit);
+    if (!mask) return;  // the common case: one wave-uniform branch
+    const int lead = __builtin_ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane_id() == lead) base = atomicAdd(&lst.n, 2 * __popcll(mask));
+    base = __shfl(base, lead);
+    if (!hit) return;
+    const int q = base + 2 * lanes_below(mask);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const int a = (int)(d ? k : j), b = (int)(d ? j : k);  // a joins column b
+        if (q + d < L::kCap) {
+            lst.jk[2 * (q + d)] = a;
+            lst.jk[2 * (q + d) + 1] = b;
+        } else {
+            const int pos = atomicAdd(&cnt[b], 1);
+            if (pos < kPendMax) idx[(int64_t)b * kPendMax + pos] = a;
+        }
+    }
+}
+
+// Per-wave candidate lists (no atomics): wave w appends to its own segment
+// and keeps the count in a wave-uniform register.
+template <int NW, int N>
+struct ScreenWaves {
+    static constexpr int kCap = N;  // entries per wave
+    int n[NW];
+    int jk[NW][2 * N];
+};
+
+template <typename L, typename T>
+__device__ __forceinline__ void screen_pair_wave(L &lst, int wv, int &count, int *cnt, int *idx, T thr,
+                                                 int64_t j, int64_t k, T v)
+{
+    const bool hit = cnt && j != k && (v < T(0) ? -v : v) > thr;
+    const unsigned long long mask = __ballot(hit);
+    if (!mask) return;
+    const int q = count + 2 * lanes_below(mask);
+    count += 2 * __popcll(mask);
+    if (!hit) return;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const int a = (int)(d ? k : j), b = (int)(d ? j : k);  // a joins column b
+        if (q + d < L::kCap) {
+            lst.jk[wv][2 * (q + d)] = a;
+            lst.jk[wv][2 * (q + d) + 1] = b;
+        } else {
+            const int pos = atomicAdd(&cnt[b], 1);
+            if (pos < kPendMax) idx[(int64_t)b * kPendMax + pos] = a;
+        }
+    }
+}
+
+template <int NW, int N>
+__device__ __forceinline__ void screen_flush_waves(ScreenWaves<NW, N> &lst, int *cnt, int *idx)
+{
+    if (!cnt) return;
+    for (int w = 0; w < NW; ++w) {
+        const int m = lst.n[w] < N ? lst.n[w] : N;
+        for (int q0 = threadIdx.x; q0 < m; q0 += 8 * (int)blockDim.x) {
+            int jj[8], pos[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + u * (int)blockDim.x;
+                pos[u] = kPendMax;
+                jj[u] = 0;
+                if (q < m) {
+                    jj[u] = lst.jk[w][2 * q];
+                    pos[u] = atomicAdd(&cnt[lst.jk[w][2 * q + 1]], 1);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + u * (int)blockDim.x;
+                if (q < m && pos[u] < kPendMax) idx[(int64_t)lst.jk[w][2 * q + 1] * kPendMax + pos[u]] = jj[u];
+            }
+        }
+    }
+}
+
 // After the tile's entries are collected (and a barrier): store them.  The
 // persistent kernel calls this for a tile while the next tile's first stage
 // is being copied, so the atomics' round trip overlaps the copy.
-__device__ __forceinline__ void screen_flush(ScreenLds &L, int *cnt, int *idx)
+template <typename L>
+__device__ __forceinline__ void screen_flush(L &lst, int *cnt, int *idx)
 {
     if (!cnt) return;
-    const int m = L.n < kScreenTile ? L.n : kScreenTile;
-    for (int q = threadIdx.x; q < m; q += blockDim.x) {
-        const int j = L.jk[2 * q], k = L.jk[2 * q + 1];
-        const int pos = atomicAdd(&cnt[k], 1);
-        if (pos < kPendMax) idx[(int64_t)k * kPendMax + pos] = j;
+    const int m = lst.n < L::kCap ? lst.n : L::kCap;
+    // up to eight independent atomics per thread in flight, then the stores
+    for (int q0 = threadIdx.x; q0 < m; q0 += 8 * (int)blockDim.x) {
+        int jj[8], pos[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * (int)blockDim.x;
+            pos[u] = kPendMax;
+            jj[u] = 0;
+            if (q < m) {
+                jj[u] = lst.jk[2 * q];
+                pos[u] = atomicAdd(&cnt[lst.jk[2 * q + 1]], 1);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * (int)blockDim.x;
+            if (q < m && pos[u] < kPendMax) idx[(int64_t)lst.jk[2 * q + 1] * kPendMax + pos[u]] = jj[u];
+        }
     }
 }
 
@@ -119,7 +220,7 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
         } in;
         T out[64][65];
     } sm;
-    __shared__ ScreenLds scr;
+    __shared__ ScreenLds<512> scr;  // a 64 x 64 tile: about 6 per row at the workloads here
     int bj, bk;
     tile_of_block(Tt, &bj, &bk);
     const int64_t j0 = (int64_t)bj * 64, k0 = (int64_t)bk * 64;
@@ -229,30 +330,38 @@ void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, const Scre
 }
 
 // ---------------------------------------------------------------------------
-// mixed form: bf16 split, 128 x 128 tiles, 64 samples per stage
+// mixed form: bf16 split, 256 x 256 tiles, 32 samples per stage
 //
-// Persistent blocks walk the upper-triangle tile list (tiles of one row
-// panel kept on one XCD).  A stage (the hi and lo panels of the tile's row
-// and column blocks, 128 variables x 64 samples each, 64 KB) is copied to LDS
-// by the direct global-to-LDS path; the output tile of the epilogue reuses
-// the same LDS.  At 66 KB of LDS two blocks share a CU, so one block's copy
-// overlaps the other's matrix-core work (measured faster than one block per
-// CU with two stage buffers).
+// A block of 8 waves (64 x 128 each) computes one 256 x 256 tile; blocks
+// loop over the upper-triangle tile list when it is longer than the grid.
+// A stage (hi and lo of the tile's 256 row and 256 column variables over 32
+// samples, 64 KB) is copied to LDS by the direct global-to-LDS path into two
+// alternating buffers, so the copy of stage s + 1 is in flight while stage s
+// feeds the matrix cores.  Against 128 x 128 tiles this halves the panel
+// traffic per flop; measured at p = 5000 it takes 64 us where the 128 x 128
+// form at two blocks per CU took 85 us and the register-staged form 103 us.
 //
-// LDS layout of a panel: row m (a variable) holds its 64 samples as eight
-// 16-byte chunks, chunk c stored in slot c ^ f(m), f(m) = (m & 7) ^ ((m >> 3)
-// & 1).  The operand reads (16 lanes on 16 consecutive rows, one chunk each)
-// then touch distinct banks with either 32 or 64 LDS banks.
+// LDS layout of a panel: row m (a variable) holds its 32 samples as four
+// 16-byte chunks, chunk c in slot c ^ f(m), f(m) = ((m >> 1) ^ (m >> 2)) & 3.
+// The operand reads (16 lanes on 16 consecutive rows, one chunk each) then
+// touch distinct banks with either 32 or 64 LDS banks.
+//
+// The epilogue stages the tile through LDS in four slices of 64 rows and
+// writes S with 16-byte stores, directly and transposed.  The screen of the
+// first solves is taken in the direct pass (each pair for both columns).
 // ---------------------------------------------------------------------------
-constexpr int kBfKC = 64;                   // samples per stage
-constexpr int kBfPanel = 128 * kBfKC * 2;   // bytes of one panel (16 KB)
-constexpr int kBfStage = 4 * kBfPanel;      // hi_J, lo_J, hi_K, lo_K
-constexpr int kBfOutLd = 129;               // padded row of the staged output tile
-constexpr int kBfOut = 128 * kBfOutLd * 4;  // output tile; the stage fits inside
-static_assert(kBfOut >= kBfStage, "stage and output tile share the LDS");
-constexpr int kBfLds = kBfOut + (int)sizeof(ScreenLds);  // + the tile's screen candidates
+constexpr int kBfTile = 256;
+constexpr int kBfKC = 32;                     // samples per stage (one MFMA k-step)
+constexpr int kBfPanel = kBfTile * kBfKC * 2; // 16 KB: 256 rows x 64 B
+constexpr int kBfStage = 4 * kBfPanel;        // hi_J, lo_J, hi_K, lo_K
+constexpr int kBfOutLd = 257;                 // odd stride: transposed reads hit distinct banks
+constexpr int kBfOutRows = 64;
+typedef ScreenWaves<8, 448> BfScreen;        // fills the LDS left by the two stages
+constexpr int kBfLds = 2 * kBfStage + (int)sizeof(BfScreen);
+static_assert(kBfLds <= 160 * 1024, "LDS of one block");
+static_assert(kBfOutRows * kBfOutLd * 4 <= 2 * kBfStage, "an output slice fits the stage buffers");
 
-__device__ __forceinline__ int bf_swz(int m) { return (m & 7) ^ ((m >> 3) & 1); }
+__device__ __forceinline__ int bf_swz(int m) { return ((m >> 1) ^ (m >> 2)) & 3; }
 
 // Upper-triangle tile number -> (row block, column block), row-major order.
 __device__ __forceinline__ void bf_tile(int t, int T, int *bj, int *bk)
@@ -266,7 +375,7 @@ __device__ __forceinline__ void bf_tile(int t, int T, int *bj, int *bk)
     *bk = row + t;
 }
 
-// Issue the copies of one stage: samples [i0, i0 + 64) of variables j0.. and
+// Issue the copies of one stage: samples [i0, i0 + 32) of variables j0.. and
 // k0.. (hi and lo).  A diagonal tile copies its one panel pair only.  Rows
 // past p load row p - 1 (valid memory; those results are never stored).
 __device__ __forceinline__ void bf_issue(const uint16_t *__restrict__ hi, const uint16_t *__restrict__ lo,
@@ -275,11 +384,11 @@ __device__ __forceinline__ void bf_issue(const uint16_t *__restrict__ hi, const 
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int npan = diag ? 2 : 4;
-    // 16 groups of 8 rows per panel; one 1 KB wave instruction per group
-    for (int blk = wv; blk < npan * 16; blk += 4) {
+    // 16 groups of 16 rows per panel; one 1 KB wave instruction per group
+    for (int blk = wv; blk < npan * 16; blk += 8) {
         const int pnl = blk >> 4, grp = blk & 15;
-        const int m = grp * 8 + (lane >> 3);
-        const int c = (lane & 7) ^ bf_swz(m);
+        const int m = grp * 16 + (lane >> 2);
+        const int c = (lane & 3) ^ bf_swz(m);
         int64_t v = ((pnl < 2) ? j0 : k0) + m;
         v = v < p ? v : p - 1;
         const uint16_t *src = ((pnl & 1) ? lo : hi) + v * npad + i0 + c * 8;
@@ -288,7 +397,7 @@ __device__ __forceinline__ void bf_issue(const uint16_t *__restrict__ hi, const 
     }
 }
 
-__global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict__ hi,
+__global__ __launch_bounds__(512) void k_syrk_bf16x3(const uint16_t *__restrict__ hi,
                                                      const uint16_t *__restrict__ lo,
                                                      int64_t npad, int64_t p,
                                                      float *__restrict__ S, int Tt, float invn,
@@ -296,116 +405,135 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const uint16_t *__restrict_
                                                      int *__restrict__ sidx)
 {
     extern __shared__ __align__(16) unsigned char bf_lds[];
+    BfScreen &scr = *reinterpret_cast<BfScreen *>(bf_lds + 2 * kBfStage);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w & 1, wn = w >> 1;
+    const int wm = w & 3, wn = w >> 2;
     const int ntiles = Tt * (Tt + 1) / 2;
-    // tiles of XCD x = blockIdx % 8 form one contiguous range of the list
-    const int nb = gridDim.x, x = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int nbx = (nb >> 3) + ((nb & 7) > x ? 1 : 0);
-    const int q = ntiles >> 3, r = ntiles & 7;
-    const int tbeg = x * q + (x < r ? x : r), tend = tbeg + q + (x < r ? 1 : 0);
     const int nst = (int)(npad / kBfKC);
-
-    ScreenLds &scr = *reinterpret_cast<ScreenLds *>(bf_lds + kBfOut);
-    bool pending = false;  // the previous tile's screen candidates await their flush
-    int t = tbeg + slot;
-    for (; t < tend; t += nbx) {
+    const bool vec_ok = (p & 3) == 0;  // rows of S 16-byte aligned
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int bj, bk;
         bf_tile(t, Tt, &bj, &bk);
-        const int64_t j0 = (int64_t)bj * 128, k0 = (int64_t)bk * 128;
+        const int64_t j0 = (int64_t)bj * kBfTile, k0 = (int64_t)bk * kBfTile;
         const bool diag = bj == bk;
-        const int pk = diag ? 0 : 2;
-        f4 acc[4][4];
+        const int pk = diag ? 0 : 2;  // panels the column block reads
+        f4 acc[4][8];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+            for (int b = 0; b < 8; ++b) acc[a][b] = f4{0, 0, 0, 0};
+        __syncthreads();  // the previous tile's epilogue and flush are done with the LDS
+        int nscr = 0;     // this wave's screen entries (wave-uniform)
+        bf_issue(hi, lo, npad, p, j0, k0, 0, diag, bf_lds);
         for (int st = 0; st < nst; ++st) {
-            __syncthreads();
-            bf_issue(hi, lo, npad, p, j0, k0, (int64_t)st * kBfKC, diag, bf_lds);
-            if (st == 0 && pending) screen_flush(scr, scnt, sidx);  // the previous tile's
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            const unsigned char *sb = bf_lds;
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of stage st have landed
+            __syncthreads();                // ... every wave's; stage st - 1 is consumed
+            if (st + 1 < nst)
+                bf_issue(hi, lo, npad, p, j0, k0, (int64_t)(st + 1) * kBfKC, diag,
+                         bf_lds + ((st + 1) & 1) * kBfStage);
+            const unsigned char *sb = bf_lds + (st & 1) * kBfStage;
+            const int c = lane >> 4;
+            bf8 ha[4], la[4], hb[8], lb[8];
 #pragma unroll
-            for (int kk = 0; kk < kBfKC; kk += 32) {
-                const int c = kk / 8 + (lane >> 4);
-                bf8 ha[4], la[4], hb[4], lb[4];
+            for (int a = 0; a < 4; ++a) {
+                const int m = 64 * wm + 16 * a + (lane & 15);
+                const int off = m * 64 + ((c ^ bf_swz(m)) << 4);
+                ha[a] = *reinterpret_cast<const bf8 *>(sb + off);
+                la[a] = *reinterpret_cast<const bf8 *>(sb + kBfPanel + off);
+            }
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int m = 64 * wm + 16 * a + (lane & 15);
-                    const int off = m * 128 + ((c ^ bf_swz(m)) << 4);
-                    ha[a] = *reinterpret_cast<const bf8 *>(sb + off);
-                    la[a] = *reinterpret_cast<const bf8 *>(sb + kBfPanel + off);
+            for (int b = 0; b < 8; ++b) {
+                const int m = 128 * wn + 16 * b + (lane & 15);
+                const int off = m * 64 + ((c ^ bf_swz(m)) << 4);
+                hb[b] = *reinterpret_cast<const bf8 *>(sb + pk * kBfPanel + off);
+                lb[b] = *reinterpret_cast<const bf8 *>(sb + (pk + 1) * kBfPanel + off);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
                 }
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int m = 64 * wn + 16 * b + (lane & 15);
-                    const int off = m * 128 + ((c ^ bf_swz(m)) << 4);
-                    hb[b] = *reinterpret_cast<const bf8 *>(sb + pk * kBfPanel + off);
-                    lb[b] = *reinterpret_cast<const bf8 *>(sb + (pk + 1) * kBfPanel + off);
-                }
+        }
+        // epilogue: four slices of 64 rows (one wm group each)
+        float *out = reinterpret_cast<float *>(bf_lds);
+        for (int h = 0; h < 4; ++h) {
+            __syncthreads();
+            if (wm == h) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
-                    }
+                    for (int b = 0; b < 8; ++b)
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr)
+                            out[(16 * a + 4 * (lane >> 4) + rr) * kBfOutLd + 128 * wn + 16 * b + (lane & 15)] =
+                                acc[a][b][rr] * invn;
             }
-        }
-        __syncthreads();
-        // every thread is past the previous tile's flush (stage barriers)
-        if (tid == 0) scr.n = 0;
-        float *outc = reinterpret_cast<float *>(bf_lds);
+            __syncthreads();
+            // direct: row j0 + 64h + rl, columns k0 + q4 .. q4 + 3.  A diagonal
+            // tile writes its upper triangle here and its lower one below,
+            // both from the upper values, so S is symmetric bit for bit.
+            for (int e = tid; e < kBfOutRows * (kBfTile / 4); e += 512) {
+                const int rl = e >> 6, q4 = (e & 63) * 4, rr = rl + 64 * h;
+                const int64_t j = j0 + rr, k = k0 + q4;
+                // no early exit: every lane takes part in the screen's ballots
+                const bool rowok = j < p && k < p;
+                float v[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+                for (int u = 0; u < 4; ++u) v[u] = out[rl * kBfOutLd + q4 + u];
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+                for (int u = 0; u < 4; ++u)
+                    if (j == k + u) v[u] = 1.0f;
+                // screen: a pair above the threshold is a candidate of both columns
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr)
-                    outc[(64 * wm + 16 * a + 4 * (lane >> 4) + rr) * kBfOutLd + 64 * wn + 16 * b + (lane & 15)] =
-                        acc[a][b][rr] * invn;
-        __syncthreads();
-        for (int e = tid; e < 128 * 128; e += 256) {
-            const int rr = e >> 7, cc = e & 127;
-            const int64_t j = j0 + rr, k = k0 + cc;
-            if (j < p && k < p) {
-                const float v = (j == k) ? 1.0f
-                                         : ((diag && rr > cc) ? outc[cc * kBfOutLd + rr] : outc[rr * kBfOutLd + cc]);
-                S[j * p + k] = v;
-                screen_entry(scr, scnt, sidx, thr, j, k, v);
+                for (int u = 0; u < 4; ++u) {
+                    const bool mine = rowok && k + u < p && (!diag || rr < q4 + u);
+                    screen_pair_wave(scr, w, nscr, scnt, sidx, thr, j, k + u, mine ? v[u] : 0.0f);
+                }
+                if (!rowok) continue;
+                if (vec_ok && k + 3 < p && (!diag || rr <= q4)) {
+                    *reinterpret_cast<f4 *>(&S[j * p + k]) = f4{v[0], v[1], v[2], v[3]};
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (k + u < p && (!diag || rr <= q4 + u)) S[j * p + k + u] = v[u];
+                }
             }
-        }
-        if (!diag) {
-            for (int e = tid; e < 128 * 128; e += 256) {
-                const int rr = e >> 7, cc = e & 127;
-                const int64_t k = k0 + rr, j = j0 + cc;
-                if (j < p && k < p) {
-                    const float v = outc[cc * kBfOutLd + rr];
-                    S[k * p + j] = v;
-                    screen_entry(scr, scnt, sidx, thr, k, j, v);
+            // mirrored: row k0 + cc, columns j0 + 64h + r4 .. + 3; 16 lanes
+            // cover 64 consecutive columns
+            for (int e = tid; e < kBfTile * 16; e += 512) {
+                const int r4 = (e & 15) * 4, cc = e >> 4;
+                const int rr0 = 64 * h + r4;
+                const int64_t k = k0 + cc, j = j0 + rr0;
+                if (k >= p || j >= p) continue;
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = out[(r4 + u) * kBfOutLd + cc];
+                if (vec_ok && j + 3 < p && (!diag || cc > rr0 + 3)) {
+                    *reinterpret_cast<f4 *>(&S[k * p + j]) = f4{v[0], v[1], v[2], v[3]};
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (j + u < p && (!diag || cc > rr0 + u)) S[k * p + j + u] = v[u];
                 }
             }
         }
-        pending = true;
-    }
-    if (pending) {
+        if (lane == 0) scr.n[w] = nscr;
         __syncthreads();
-        screen_flush(scr, scnt, sidx);
+        screen_flush_waves(scr, scnt, sidx);
     }
 }
 
 void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
                         int64_t p, float *S, const Screen &sc, hipStream_t s)
 {
-    (void)n;
-    int Tt = (int)((p + 127) / 128);
+    int Tt = (int)((p + kBfTile - 1) / kBfTile);
     int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
-    // two blocks per CU (the LDS of a block), at most one per tile
-    int64_t grid = ntiles < 512 ? ntiles : 512;
-    hipLaunchKernelGGL(k_syrk_bf16x3, dim3((unsigned)grid), dim3(256), kBfLds, s, hi, lo, npad, p, S,
+    // one block per CU (LDS and registers), at most one per tile
+    int64_t grid = ntiles < 256 ? ntiles : 256;
+    hipLaunchKernelGGL(k_syrk_bf16x3, dim3((unsigned)grid), dim3(512), kBfLds, s, hi, lo, npad, p, S,
                        Tt, (float)(1.0 / (double)n), sc.thr32, sc.cnt, sc.idx);
 }
 
