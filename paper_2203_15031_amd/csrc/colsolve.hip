@@ -38,10 +38,13 @@
 
 namespace spmesl {
 
-template <typename T, int LW>
+template <typename T, int LW, int KCH>
 __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier);
 
-template <typename T, int LW, int NW>
+// KCH: groups per lane in flight in the in-wave KKT passes (4 for the first
+// solves, whose kernel covers every column; 8 for the resumes, which are few
+// and spend their time in those passes).
+template <typename T, int LW, int NW, int KCH>
 __global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A, int tier)
 {
     __shared__ WaveSm<T, LW> smem[NW];
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A, int tier)
     const int64_t nwork = A.mode ? (int64_t)*A.work_cnt : A.p;
     for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
         const int64_t k = A.mode ? (int64_t)A.work_list[gw] : gw;
-        solve_column<T, LW>(A, sm, k, tier);
+        solve_column<T, LW, KCH>(A, sm, k, tier);
     }
 }
 
@@ -89,7 +92,7 @@ __device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const W
     }
 }
 
-template <typename T, int LW>
+template <typename T, int LW, int KCH>
 __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier)
 {
     const int lane = lane_id();
@@ -196,8 +199,10 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
 
     while (status == kColOk && !deferred) {
         int ns = build_support(sm, st);
-        int npend = kkt_pass(A.S, p, k, sm, st.w, ns, st.lam_used + A.kkt_tol, band,
-                             st.lam_used - A.band, A.band_cnt, A.band_idx);
+        int npend = kkt_pass<T, T, LW, KCH, 2>(A.S, p, k, sm, st.w, ns,
+                                                              st.lam_used + A.kkt_tol, band,
+                                                              st.lam_used - A.band, A.band_cnt,
+                                                              A.band_idx);
         if (npend == 0) break;
         if (rounds >= A.max_rounds) {
             status = kColNoconv;
@@ -240,15 +245,20 @@ template <typename T>
 void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
 {
     if (tier == 0) {
-        constexpr int NW = 4;
+        // one column per workgroup: a column's slot frees as soon as it is done
+        constexpr int NW = 1;
         int64_t blocks = (a.p + NW - 1) / NW;
-        if (a.mode && blocks > 2048) blocks = 2048;  // resume walks a work list
-        hipLaunchKernelGGL((k_colsolve<T, 32, NW>), dim3((unsigned)blocks), dim3(kWave * NW), 0, s, a,
-                           0);
+        if (a.mode && blocks > 8192) blocks = 8192;  // resume walks a work list
+        if (a.mode)
+            hipLaunchKernelGGL((k_colsolve<T, 32, NW, 8>), dim3((unsigned)blocks), dim3(kWave * NW), 0, s,
+                               a, 0);
+        else
+            hipLaunchKernelGGL((k_colsolve<T, 32, NW, 4>), dim3((unsigned)blocks), dim3(kWave * NW), 0, s,
+                               a, 0);
     } else {
         // one wave per block walking the (short) escalation queue
         unsigned blocks = (unsigned)(a.p < 256 ? a.p : 256);
-        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1>), dim3(blocks), dim3(kWave), 0, s, a, 1);
+        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1, 4>), dim3(blocks), dim3(kWave), 0, s, a, 1);
     }
 }
 

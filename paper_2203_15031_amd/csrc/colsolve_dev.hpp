@@ -139,12 +139,12 @@ __device__ __forceinline__ int lane_prefix(int c, int *total)
     return r;
 }
 
-template <typename TS, typename T, int LW, int V>
+template <typename TS, typename T, int LW, int V, int CHV, int UV>
 __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
                           int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
 {
-    constexpr int CH = V == 1 ? 8 : 4;
-    constexpr int U = V == 1 ? 4 : 2;
+    constexpr int CH = V == 1 ? 8 : CHV;
+    constexpr int U = V == 1 ? 4 : UV;
     constexpr int STEP = kWave * V * CH;
     const int lane = lane_id();
     const TS *Sk = S + k * p;
@@ -255,7 +255,10 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
     return npend;
 }
 
-template <typename TS, typename T, int LW>
+// CH groups of V per lane in flight and U support rows at a time: the
+// defaults keep the register use of the first solves' kernel; the resume
+// kernel (few columns) takes deeper settings.
+template <typename TS, typename T, int LW, int CH = 4, int U = 2>
 __device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
                         int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
 {
@@ -263,8 +266,9 @@ __device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T
     // rows of S start 16-byte aligned when p is a multiple of V (S itself
     // is 256-byte aligned)
     if (p % V == 0)
-        return kkt_pass_v<TS, T, LW, V>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx);
-    return kkt_pass_v<TS, T, LW, 1>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx);
+        return kkt_pass_v<TS, T, LW, V, CH, U>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt,
+                                              band_idx);
+    return kkt_pass_v<TS, T, LW, 1, CH, U>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx);
 }
 
 // Support list (nonzero coefficients, ascending) from the slot registers.

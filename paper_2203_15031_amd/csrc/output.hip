@@ -129,7 +129,9 @@ void launch_fill_zero(double *A, int64_t count, hipStream_t s)
     }
     int64_t nvec = count / 2;
     int64_t blocks = (nvec + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    // a modest grid: the fill runs beside the column solves on the second
+    // stream, and a few long-lived blocks take fewer of their wave slots
+    if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, A, count);
 }

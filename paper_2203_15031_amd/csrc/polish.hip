@@ -286,7 +286,8 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
 
 void launch_polish(const PolishArgs &a, hipStream_t s)
 {
-    constexpr int NW = 4;
+    // one column per workgroup: a column's slot frees as soon as it is done
+    constexpr int NW = 1;
     hipLaunchKernelGGL((k_polish<32, NW>), dim3((unsigned)((a.p + NW - 1) / NW)),
                        dim3(kWave * NW), 0, s, a, 0);
     hipLaunchKernelGGL((k_polish<kWMax, 1>), dim3((unsigned)(a.p < 256 ? a.p : 256)), dim3(kWave), 0,
