@@ -74,23 +74,47 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+// Cross-lane moves by DPP (register to register, no LDS round trip).  Lanes
+// that a pattern does not write (rows outside ROWS) take `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float old, float v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double old, double v)
+{
+    const long long o = __double_as_longlong(old), b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Reduction over the 64 lanes: pairs and quads (quad permutes), half rows
+// and rows of 16 (mirrors), then the four rows (broadcasts of lane 15 into
+// rows 1 and 3, and of lane 31 into rows 2 and 3); lane 63 ends with the
+// total, which every lane then reads.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, T identity, Op op)
+{
+    v = op(v, dpp_move<0xB1, 0xF>(identity, v));   // quad_perm [1, 0, 3, 2]
+    v = op(v, dpp_move<0x4E, 0xF>(identity, v));   // quad_perm [2, 3, 0, 1]
+    v = op(v, dpp_move<0x141, 0xF>(identity, v));  // row_half_mirror
+    v = op(v, dpp_move<0x140, 0xF>(identity, v));  // row_mirror
+    v = op(v, dpp_move<0x142, 0xA>(identity, v));  // row_bcast:15
+    v = op(v, dpp_move<0x143, 0xC>(identity, v));  // row_bcast:31
+    return bcast(v, 63);
 }
 
 template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    return wave_reduce(v, T(0), [](T a, T b) { return a + b; });
+}
+template <typename T>
 __device__ __forceinline__ T wave_max(T v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        T o = __shfl_xor(v, off, kWave);
-        v = o > v ? o : v;
-    }
-    return v;
+    return wave_reduce(v, -__builtin_huge_valf(), [](T a, T b) { return b > a ? b : a; });
 }
 
 // Soft_lambda(a) = sign(a) (|a| - lambda)_+ ; 0 at |a| == lambda.
