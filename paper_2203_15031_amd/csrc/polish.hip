@@ -25,6 +25,46 @@ __device__ __forceinline__ int64_t clamp_index(int v, int64_t p)
     return v < 0 ? 0 : (v >= p ? p - 1 : (int64_t)v);
 }
 
+// Working sets of at most three variables: the four rows (x_k and W') are
+// read for four 64-sample chunks at a time with every load in flight
+// together, so the n-sample products cost ceil(n / 256) memory round trips
+// rather than one per 64 samples.
+constexpr int kSmallW = 3;
+
+template <int LW>
+__device__ __forceinline__ void gram_small(const double *__restrict__ Xt, int64_t n, int64_t p, int64_t k,
+                                           const WaveSm<double, LW> &sm, int w, double *pr)
+{
+    const int lane = lane_id();
+    const double *r[4];
+    r[0] = Xt + k * n;
+#pragma unroll
+    for (int q = 1; q < 4; ++q) r[q] = Xt + (q <= w ? clamp_index(sm.widx[q - 1], p) : k) * n;
+    // pairs: (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = 0; i0 < n; i0 += 4 * kWave) {
+        double v[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t i = i0 + c * kWave + lane;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q][c] = (q <= w && i < n) ? r[q][i] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            acc[0] += v[0][c] * v[1][c];
+            acc[1] += v[0][c] * v[2][c];
+            acc[2] += v[0][c] * v[3][c];
+            acc[3] += v[1][c] * v[2][c];
+            acc[4] += v[1][c] * v[3][c];
+            acc[5] += v[2][c] * v[3][c];
+        }
+    }
+    const double invn = 1.0 / (double)n;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) pr[u] = wave_sum(acc[u]) * invn;
+}
+
 template <int LW>
 __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t p,
                                     int64_t k, WaveSm<double, LW> &sm, ColState<double, LW> &st,
@@ -37,7 +77,27 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
     const int P = ntri + w;
     const double invn = 1.0 / (double)n;
     const double *xk = Xt + k * n;
-    for (int t0 = 0; t0 < P; t0 += 4) {
+    if (w <= kSmallW) {
+        double pr[6];
+        gram_small(Xt, n, p, k, sm, w, pr);
+        if (lane == 0) {
+            // rows 1..3 of the product list are W'[0..2]; row 0 is x_k
+            if (w > 0) sm.tbeta[0] = pr[0];
+            if (w > 1) {
+                sm.tbeta[1] = pr[1];
+                sm.sww[1 * LW + 0] = pr[3];
+                sm.sww[0 * LW + 1] = pr[3];
+            }
+            if (w > 2) {
+                sm.tbeta[2] = pr[2];
+                sm.sww[2 * LW + 0] = pr[4];
+                sm.sww[0 * LW + 2] = pr[4];
+                sm.sww[2 * LW + 1] = pr[5];
+                sm.sww[1 * LW + 2] = pr[5];
+            }
+        }
+    }
+    for (int t0 = w <= kSmallW ? P : 0; t0 < P; t0 += 4) {
         const double *ra[4], *rb[4];
         int qa[4], qb[4];
 #pragma unroll
@@ -130,7 +190,20 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
 {
     constexpr int NS = ColState<double, LW>::NS;
     const int lane = lane_id();
-    if (*A.flags) {
+    // everything the column's set-up reads, in one round of loads: the
+    // counts, the first 64 entries of the float list and the band (both
+    // arrays hold kWMax >= 64 and kBandMax entries per column), sigma, lambda
+    const int flagged = *A.flags;
+    int w32 = A.w_cnt32[k];
+    int nb = A.band_cnt[k];
+    const int st32 = A.col_status32[k];
+    const double sig32 = A.sigma32[k];
+    const double lam32 = A.lam32[k];
+    const float bfirst = A.w_beta32[k * kWMax + lane];
+    const int ifirst = A.w_idx32[k * kWMax + lane];
+    const int bandfirst = lane < kBandMax ? A.band_idx[k * kBandMax + lane] : 0;
+    asm volatile("" ::"v"(bfirst), "v"(ifirst), "v"(bandfirst));
+    if (flagged) {
         if (lane == 0) {
             A.w_cnt[k] = 0;
             A.sigma[k] = 1.0;
@@ -147,30 +220,27 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     int status = kColOk, rounds = 0, checks = 0, added = 0;
 
     // --- W' = float support U float band --------------------------------
-    int w32 = A.w_cnt32[k];
     w32 = w32 < 0 ? 0 : (w32 > kWMax ? kWMax : w32);
-    int nb = A.band_cnt[k];
     nb = nb < 0 ? 0 : nb;
-    const int st32 = A.col_status32[k];
     bool full = nb > kBandMax || (st32 != kColOk && st32 != kColDeferred);
     nb = nb < kBandMax ? nb : kBandMax;
     double norm32 = 0.0;
     int ns = 0;
     for (int q0 = 0; q0 < w32; q0 += kWave) {
         int q = q0 + lane;
-        float b = q < w32 ? A.w_beta32[k * kWMax + q] : 0.0f;
+        float b = q < w32 ? (q0 == 0 ? bfirst : A.w_beta32[k * kWMax + q]) : 0.0f;
         bool nz = b != 0.0f;
         unsigned long long m = __ballot(nz);
         int pos = ns + lanes_below(m);
         if (nz && pos < LW) {
-            sm.widx[pos] = A.w_idx32[k * kWMax + q];
+            sm.widx[pos] = q0 == 0 ? ifirst : A.w_idx32[k * kWMax + q];
             sm.wbeta[pos] = (double)b;
         }
         norm32 += nz ? fabs((double)b) : 0.0;
         ns += __popcll(m);
     }
     norm32 = wave_sum(norm32);
-    for (int i = lane; i < nb; i += kWave) sm.pend[i] = A.band_idx[k * kBandMax + i];
+    if (lane < nb) sm.pend[lane] = bandfirst;
     wave_sync();
     nb = sort_unique_small(sm.pend, nb);  // the row-tiled pass appends in any order
     if (ns + nb > LW) {
@@ -193,14 +263,17 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     }
     wave_sync();
     merge_pending(sm, st, nb);
+    // beta32 over W' (zero on the band), kept for the first bound check:
+    // every nonzero of the float solution is in W'
+    double b32[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int q = s * kWave + lane;
         st.b[s] = q < st.w ? sm.wbeta[q] : 0.0;
+        b32[s] = st.b[s];
     }
-    st.sigma = A.sigma32[k];
-    st.lam_used = A.lam32[k];
-    const double lam32 = A.lam32[k];
+    st.sigma = sig32;
+    st.lam_used = lam32;
 
     while (status == kColOk) {
         load_working_set_xt(A.Xt, A.n, A.p, k, sm, st, rlo, rhi);
@@ -212,7 +285,9 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
         for (int s = 0; s < NS; ++s) {
             int q = s * kWave + lane;
             if (q < st.w) {
-                part += fabs(st.b[s] - beta32_of(A, k, sm.widx[q]));
+                // after a merge W' is reordered: look the float value up
+                const double f = added == 0 ? b32[s] : beta32_of(A, k, sm.widx[q]);
+                part += fabs(st.b[s] - f);
                 nrm += fabs(st.b[s]);
             }
         }
@@ -222,6 +297,15 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
         lamdrop = lamdrop > 0.0 ? lamdrop : 0.0;
         double bound = l1d + A.eps * (1.0 + norm32) + lamdrop;
         if (!full && bound < (double)A.band) break;
+        if constexpr (LW < kWMax) {
+            // the full pass below is left to the wide kernel, which redoes
+            // the column (rare; keeps this kernel's registers low)
+            if (lane == 0) {
+                int pos = atomicAdd(A.esc_cnt, 1);
+                A.esc_list[pos] = (int)k;
+            }
+            return;
+        } else {
         // full pass: every j whose float-S gradient is within the error
         // margin of lambda64 joins W'
         int nsup = build_support(sm, st);
@@ -260,6 +344,7 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
         merge_pending(sm, st, np);
         added += np;
         full = true;
+        }
     }
     // store the double lists
 #pragma unroll
