@@ -44,8 +44,8 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, 
 // KCH: groups per lane in flight in the in-wave KKT passes (4 for the first
 // solves, whose kernel covers every column; 8 for the resumes, which are few
 // and spend their time in those passes).
-template <typename T, int LW, int NW, int KCH>
-__global__ __launch_bounds__(kWave *NW) void k_colsolve(ColArgs<T> A, int tier)
+template <typename T, int LW, int NW, int KCH, int MINW = 1>
+__global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW))) void k_colsolve(ColArgs<T> A, int tier)
 {
     __shared__ WaveSm<T, LW> smem[NW];
     const int wv = threadIdx.x / kWave;
@@ -253,8 +253,9 @@ void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
             hipLaunchKernelGGL((k_colsolve<T, 32, NW, 8>), dim3((unsigned)blocks), dim3(kWave * NW), 0, s,
                                a, 0);
         else
-            hipLaunchKernelGGL((k_colsolve<T, 32, NW, 4>), dim3((unsigned)blocks), dim3(kWave * NW), 0, s,
-                               a, 0);
+            // float first solves: three waves per SIMD to hide their load latency
+            hipLaunchKernelGGL((k_colsolve<T, 32, NW, 4, sizeof(T) == 4 ? 3 : 1>), dim3((unsigned)blocks),
+                               dim3(kWave * NW), 0, s, a, 0);
     } else {
         // one wave per block walking the (short) escalation queue
         unsigned blocks = (unsigned)(a.p < 256 ? a.p : 256);

@@ -14,6 +14,9 @@ __device__ __forceinline__ void wave_sync()
 template <typename T> struct DegenerateFloor;
 template <> struct DegenerateFloor<double> { static constexpr double v = 1e-12; };
 template <> struct DegenerateFloor<float> { static constexpr float v = 1e-6f; };
+template <typename T> struct Eps;
+template <> struct Eps<double> { static constexpr double v = 0x1p-52; };
+template <> struct Eps<float> { static constexpr float v = 0x1p-23f; };
 
 // LDS of one wave.
 template <typename T, int LW>
@@ -407,7 +410,18 @@ struct SolveCounts {
     int outer, sweeps, updates;
 };
 
-// Algorithm 1 on the working set: outer sigma loop around cyclic sweeps.
+// Algorithm 1 on the working set: outer sigma loop around cyclic sweeps,
+// with a secant step on the sigma update.  While the support A and the signs
+// z of beta stay fixed, the lasso solution at lambda = lambda0 sigma is
+// affine in sigma (S_AA beta_A = s_A - lambda0 sigma z_A), and the updated
+// value h(sigma)^2 = 1 - beta'(s + g) then works out to C0 + C2 sigma^2 with
+// C0 = 1 - s_A' S_AA^-1 s_A and C2 = lambda0^2 z_A' S_AA^-1 z_A.  Two updates
+// on the same support and signs give C0 and C2, hence the fixed point
+// sigma* = sqrt(C0 / (1 - C2)) of the outer iteration, and beta moves
+// along its affine path to sigma*.  The sweeps at lambda0 sigma* and the
+// stopping test |h(sigma) - sigma| < tol are those of the plain iteration,
+// so the result is the same minimiser (Eq. (eq:spmesl)), reached in fewer
+// outer passes; a step that fails its checks is not taken.
 // Returns kColOk, kColNoconv or kColDegenerate.
 template <typename T, int LW>
 __device__ __forceinline__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st,
@@ -417,6 +431,17 @@ __device__ __forceinline__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW>
 {
     constexpr int NS = ColState<T, LW>::NS;
     const int lane = lane_id();
+    // the previous update: sigma, h(sigma), beta, support and sign masks
+    bool have = false;
+    T sp = T(0), hp = T(0);
+    T bp[NS];
+    unsigned long long pnz[NS], png[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        bp[s] = T(0);
+        pnz[s] = 0ull;
+        png[s] = 0ull;
+    }
     for (;;) {
         if (cnt.outer >= max_outer) return kColNoconv;
         ++cnt.outer;
@@ -502,11 +527,47 @@ __device__ __forceinline__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW>
             return kColDegenerate;
         }
         T sn = sqrt(s2);
-        T ds = sn - st.sigma;
+        const T so = st.sigma;
+        T ds = sn - so;
         ds = ds < T(0) ? -ds : ds;
         st.sigma = sn;
         if (!inner_ok) return kColNoconv;
         if (ds < tol) return kColOk;
+        bool same = have;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const bool in = s * kWave + lane < st.w;
+            const unsigned long long nz = __ballot(in && st.b[s] != T(0));
+            const unsigned long long ng = __ballot(in && st.b[s] < T(0));
+            same = same && nz == pnz[s] && ng == png[s];
+            pnz[s] = nz;
+            png[s] = ng;
+        }
+        bool jumped = false;
+        if (same) {
+            const T c2 = (sn * sn - hp * hp) / (so * so - sp * sp);
+            const T c0 = sn * sn - c2 * so * so;
+            T dsp = so - sp;
+            dsp = dsp < T(0) ? -dsp : dsp;
+            if (dsp > T(64) * Eps<T>::v * so && c2 >= T(0) && c2 < T(1) && c0 > T(0)) {
+                const T ss = sqrt(c0 / (T(1) - c2));
+                T jump = ss - sn;
+                jump = jump < T(0) ? -jump : jump;
+                if (jump <= T(16) * ds) {
+                    const T f = (ss - so) / (so - sp);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) st.b[s] += f * (st.b[s] - bp[s]);
+                    st.sigma = ss;
+                    jumped = true;
+                }
+            }
+        }
+        // a step needs two fresh updates on one support
+        have = !jumped;
+        sp = so;
+        hp = sn;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bp[s] = st.b[s];
     }
 }
 
