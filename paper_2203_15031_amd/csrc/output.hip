@@ -129,9 +129,11 @@ void launch_fill_zero(double *A, int64_t count, hipStream_t s)
     }
     int64_t nvec = count / 2;
     int64_t blocks = (nvec + 255) / 256;
-    // a modest grid: the fill runs beside the column solves on the second
-    // stream, and a few long-lived blocks take fewer of their wave slots
-    if (blocks > 256) blocks = 256;
+    // a small grid: the fill runs beside the latency-bound column solves on
+    // the second stream; 64 blocks of nontemporal 16-byte stores still write
+    // about 5 TB/s, and leave the solves their wave slots (with 256 blocks
+    // the re-solves of flagged columns took 90 us instead of 65 at p = 5000)
+    if (blocks > 64) blocks = 64;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, A, count);
 }
