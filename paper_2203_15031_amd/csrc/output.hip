@@ -30,7 +30,10 @@ void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s)
 }
 
 // One block: sums and maxima of the per-column counters, status bits from
-// the final per-column statuses.
+// the final per-column statuses.  Each thread takes four columns per pass
+// with every load of the pass in flight together (16-byte loads of the
+// counter records); sums are carried in double (exact below 2^53) through
+// DPP wave reductions, then one LDS step across the block's waves.
 __global__ __launch_bounds__(1024) void k_reduce_stats(int64_t p, const int *__restrict__ colinfo,
                                                        const int *__restrict__ polinfo,
                                                        const int *__restrict__ w_cnt,
@@ -38,61 +41,78 @@ __global__ __launch_bounds__(1024) void k_reduce_stats(int64_t p, const int *__r
                                                        unsigned long long *__restrict__ counters,
                                                        int *__restrict__ status_bits)
 {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    constexpr int U = 4;
     // outer, sweeps, updates, rounds, polish checks, polish added, noconv
-    unsigned long long sum[7] = {0, 0, 0, 0, 0, 0, 0};
+    double sum[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int maxw = 0, maxo = 0, bits = 0;
-    for (int64_t k = threadIdx.x; k < p; k += blockDim.x) {
-        const int *ci = colinfo + k * 4;
-        int o = ci[0];
-        sum[0] += (unsigned)o;
-        sum[1] += (unsigned)ci[1];
-        sum[2] += (unsigned)ci[2];
-        sum[3] += (unsigned)ci[3];
-        if (polinfo) {
-            const int *pi = polinfo + k * 8;
-            o += pi[0];
-            sum[0] += (unsigned)pi[0];
-            sum[1] += (unsigned)pi[1];
-            sum[2] += (unsigned)pi[2];
-            sum[4] += (unsigned)pi[3];
-            sum[5] += (unsigned)pi[4];
+    const int64_t nt = blockDim.x;
+    for (int64_t k0 = threadIdx.x; k0 < p; k0 += U * nt) {
+        i4 ci[U], pa[U], pb[U];
+        int wc[U], cs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = k0 + u * nt;
+            const bool in = k < p;
+            const i4 z = {0, 0, 0, 0};
+            ci[u] = in ? *reinterpret_cast<const i4 *>(colinfo + k * 4) : z;
+            pa[u] = in && polinfo ? *reinterpret_cast<const i4 *>(polinfo + k * 8) : z;
+            pb[u] = in && polinfo ? *reinterpret_cast<const i4 *>(polinfo + k * 8 + 4) : z;
+            wc[u] = in ? w_cnt[k] : 0;
+            cs[u] = in ? col_status[k] : 0;
         }
-        maxo = o > maxo ? o : maxo;
-        maxw = w_cnt[k] > maxw ? w_cnt[k] : maxw;
-        int st = col_status[k];
-        if (st < 0) {
-            ++sum[6];
-            bits |= st == kColWorkset ? 4 : (st == kColDegenerate ? 2 : 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sum[0] += (double)(unsigned)ci[u].x + (double)(unsigned)pa[u].x;
+            sum[1] += (double)(unsigned)ci[u].y + (double)(unsigned)pa[u].y;
+            sum[2] += (double)(unsigned)ci[u].z + (double)(unsigned)pa[u].z;
+            sum[3] += (double)(unsigned)ci[u].w;
+            sum[4] += (double)(unsigned)pa[u].w;
+            sum[5] += (double)(unsigned)pb[u].x;
+            const int o = ci[u].x + pa[u].x;
+            maxo = o > maxo ? o : maxo;
+            maxw = wc[u] > maxw ? wc[u] : maxw;
+            if (cs[u] < 0) {
+                sum[6] += 1.0;
+                bits |= cs[u] == kColWorkset ? 4 : (cs[u] == kColDegenerate ? 2 : 1);
+            }
         }
     }
-    __shared__ unsigned long long red[7][1024];
-    __shared__ int redi[3][1024];
-    for (int i = 0; i < 7; ++i) red[i][threadIdx.x] = sum[i];
-    redi[0][threadIdx.x] = maxw;
-    redi[1][threadIdx.x] = maxo;
-    redi[2][threadIdx.x] = bits;
+    __shared__ double red[7][32];
+    __shared__ int redi[3][32];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) sum[i] = wave_sum(sum[i]);
+    // maxima below 2^24 are exact in float
+    const int wmaxw = (int)wave_max((float)maxw), wmaxo = (int)wave_max((float)maxo);
+    const int wbits = (__ballot(bits & 1) ? 1 : 0) | (__ballot(bits & 2) ? 2 : 0) | (__ballot(bits & 4) ? 4 : 0);
+    if (lane == 0) {
+        for (int i = 0; i < 7; ++i) red[i][wv] = sum[i];
+        redi[0][wv] = wmaxw;
+        redi[1][wv] = wmaxo;
+        redi[2][wv] = wbits;
+    }
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            for (int i = 0; i < 7; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + off];
-            int a = redi[0][threadIdx.x + off], b = redi[1][threadIdx.x + off];
-            redi[0][threadIdx.x] = redi[0][threadIdx.x] > a ? redi[0][threadIdx.x] : a;
-            redi[1][threadIdx.x] = redi[1][threadIdx.x] > b ? redi[1][threadIdx.x] : b;
-            redi[2][threadIdx.x] |= redi[2][threadIdx.x + off];
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        counters[kCntOuter] = red[0][0];
-        counters[kCntSweeps] = red[1][0];
-        counters[kCntUpdates] = red[2][0];
-        counters[kCntRounds] = red[3][0];
-        counters[kCntPolishChecks] = red[4][0];
-        counters[kCntPolishAdded] = red[5][0];
-        counters[kCntNoconv] = red[6][0];
-        counters[kCntMaxW] = (unsigned long long)redi[0][0];
-        counters[kCntMaxOuter] = (unsigned long long)redi[1][0];
-        *status_bits = redi[2][0];
+        const int nw = (int)(blockDim.x / kWave);
+        double t[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int mw = 0, mo = 0, bb = 0;
+        for (int w = 0; w < nw; ++w) {
+            for (int i = 0; i < 7; ++i) t[i] += red[i][w];
+            mw = redi[0][w] > mw ? redi[0][w] : mw;
+            mo = redi[1][w] > mo ? redi[1][w] : mo;
+            bb |= redi[2][w];
+        }
+        counters[kCntOuter] = (unsigned long long)t[0];
+        counters[kCntSweeps] = (unsigned long long)t[1];
+        counters[kCntUpdates] = (unsigned long long)t[2];
+        counters[kCntRounds] = (unsigned long long)t[3];
+        counters[kCntPolishChecks] = (unsigned long long)t[4];
+        counters[kCntPolishAdded] = (unsigned long long)t[5];
+        counters[kCntNoconv] = (unsigned long long)t[6];
+        counters[kCntMaxW] = (unsigned long long)mw;
+        counters[kCntMaxOuter] = (unsigned long long)mo;
+        *status_bits = bb;
     }
 }
 
