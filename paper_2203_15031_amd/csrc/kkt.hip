@@ -215,6 +215,10 @@ __global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t 
                 T acc[RJ];
 #pragma unroll
                 for (int r = 0; r < RJ; ++r) acc[r] = cur[r * p + k];
+                // rows of this tile that are in the column's support: they sit
+                // at |g| = lambda and are neither violators nor band entries,
+                // so they must not take the rare path below
+                unsigned supm = 0u;
                 // slots in two groups of four, each without per-slot
                 // branches (padding adds zero), so their gathers issue
                 // together
@@ -233,6 +237,8 @@ __global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t 
                         const T v = (T)v32;
 #pragma unroll
                         for (int r = 0; r < RJ; ++r) acc[r] -= v * cur[r * p + l];
+                        const unsigned d = (unsigned)(l - (int)j0);
+                        if (q < cu && d < (unsigned)RJ) supm |= 1u << d;
                     }
                 }
                 for (int q = kKktQ; q < cu; ++q) {
@@ -241,11 +247,14 @@ __global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t 
                     const T v = A.supp_val[(int64_t)q * p + k];
 #pragma unroll
                     for (int r = 0; r < RJ; ++r) acc[r] -= v * cur[r * p + l];
+                    const unsigned d = (unsigned)(l - j0);
+                    if (d < (unsigned)RJ) supm |= 1u << d;
                 }
 #pragma unroll
                 for (int r = 0; r < RJ; ++r) {
                     const T a = acc[r] < T(0) ? -acc[r] : acc[r];
-                    if (r < nr && j0 + r != k && a > thr[u]) flagged |= 1ull << (u * RJ + r);
+                    if (r < nr && j0 + r != k && a > thr[u] && !((supm >> r) & 1u))
+                        flagged |= 1ull << (u * RJ + r);
                 }
             }
             while (flagged) {
