@@ -35,22 +35,28 @@ def kernel_costs(n, p, prec):
 
     S = Xs^T Xs / n needs n p (p + 1) flops (the upper triangle, one
     multiply-add per sample and pair); the mixed form issues three bf16
-    products per term.  The screen of the first solves reads row k of S for
-    every column (p rows), and the row-tiled KKT pass reads S once; the zero
-    fill writes one dense p x p double output.
+    products per term, and writes S (4 p^2 bytes).  The mixed form's
+    standardisation reads X once and writes Xt (double) and the bf16 split
+    (8np + 8np + 4 npad p bytes).  The row-tiled KKT pass reads S once; the
+    zero fill writes one dense p x p double output.  The column solves and
+    the polish are latency-bound chains of small gathers and have no such
+    figure.
     """
     tsz = 8 if prec == "fp64" else 4
     fl = float(n) * p * (p + 1)
+    npad = (n + 63) // 64 * 64
     syrk = {"fp64": ("syrk_f64", (8.0 * p * p, fl, "fp64")),
             "fp32": ("syrk_f32", (4.0 * p * p, fl, "fp32")),
             "mixed": ("syrk_bf16x3", (4.0 * p * p, 3 * fl, "bf16"))}[prec]
-    return {
+    costs = {
         syrk[0]: syrk[1],
-        "colsolve_first": (float(tsz) * p * p, 0.0, None),
         "kkt_rows": (float(tsz) * p * p, 0.0, None),
         "fill_B": (8.0 * p * p, 0.0, None),
         "fill_Omega": (8.0 * p * p, 0.0, None),
     }
+    if prec == "mixed":
+        costs["standardize"] = (16.0 * n * p + 4.0 * npad * p, 0.0, None)
+    return costs
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blockar_n400_p5000_hbm_traffic.md")

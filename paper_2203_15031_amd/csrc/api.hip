@@ -462,17 +462,24 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     mark(mk, s, nullptr);
     launch_zero_words((uint32_t *)dctl, sizeof(Ctl) / 4, s);
     mark(mk, s, "zero_control");
-    launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
-                    &dctl->flags, (int *)(ws + L.pendcnt), s);
-    mark(mk, s, "colstats");
-    if (L.prec == SPMESL_FP64)
-        launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
-    else if (L.prec == SPMESL_FP32)
-        launch_standardize_f32(prob->X, n, p, prob->ldx, mean, scale, (float *)(ws + L.xs), s);
-    else
-        launch_standardize_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
-                                 (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
-    mark(mk, s, "standardize");
+    if (L.prec == SPMESL_MIXED &&
+        launch_stats_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
+                           (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, &dctl->flags,
+                           (int *)(ws + L.pendcnt), s)) {
+        mark(mk, s, "standardize");
+    } else {
+        launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
+                        &dctl->flags, (int *)(ws + L.pendcnt), s);
+        mark(mk, s, "colstats");
+        if (L.prec == SPMESL_FP64)
+            launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
+        else if (L.prec == SPMESL_FP32)
+            launch_standardize_f32(prob->X, n, p, prob->ldx, mean, scale, (float *)(ws + L.xs), s);
+        else
+            launch_standardize_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
+                                     (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
+        mark(mk, s, "standardize");
+    }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
 
     // the first solves' working sets, {j : |s_jk| > kScreenFactor lambda0 +

@@ -144,6 +144,12 @@ void launch_standardize_f32(const double *X, int64_t n, int64_t p, int64_t ldx,
 // Transposed standardised data for the mixed form: Xt (p x n double) and
 // the two-term bfloat16 split hi/lo of float(x), p x npad (npad = n padded
 // to a multiple of 32, zero-filled).
+// Mixed form: column statistics and the split in one kernel (X read once).
+// Returns false (nothing launched) when a strip of n samples does not fit
+// the kernel's LDS budget; the caller then takes the two-kernel path.
+bool launch_stats_split(const double *X, int64_t n, int64_t p, int64_t ldx, double *mean,
+                        double *scale, double *Xt, uint16_t *hi, uint16_t *lo, int64_t npad,
+                        int *flags, int *zero_cnt, hipStream_t s);
 void launch_standardize_split(const double *X, int64_t n, int64_t p, int64_t ldx,
                               const double *mean, const double *scale, double *Xt,
                               uint16_t *hi, uint16_t *lo, int64_t npad, hipStream_t s);

@@ -193,6 +193,118 @@ __global__ __launch_bounds__(256) void k_standardize_split(
     }
 }
 
+// The mixed form's statistics and split in one pass over X.  A block owns a
+// strip of SW variables over all n samples: the strip is read once into LDS
+// (coalesced rows of SW doubles), the column means and centred sums of
+// squares are taken from LDS in two passes in a fixed order, and the same
+// block writes Xt and the bf16 split variable-major.  It also zeroes the
+// strip's screen counters (the covariance kernel appends to them).
+template <int SW>
+__global__ __launch_bounds__(256) void k_stats_split(const double *__restrict__ X, int64_t n, int64_t p,
+                                                     int64_t ldx, double *__restrict__ mean,
+                                                     double *__restrict__ scale, double *__restrict__ Xt,
+                                                     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                     int64_t npad, int *__restrict__ flags,
+                                                     int *__restrict__ zero_cnt)
+{
+    constexpr int SWP = SW + 1;         // odd row stride: by-variable reads hit distinct banks
+    constexpr int G = 256 / SW;         // row groups
+    extern __shared__ double strip[];   // n x SWP
+    __shared__ double part[G][SW];
+    __shared__ double mv[SW], cv[SW];
+    const int t = threadIdx.x;
+    const int v = t % SW, g = t / SW;
+    const int64_t j0 = (int64_t)blockIdx.x * SW;
+    const int64_t j = j0 + v;
+    for (int64_t i = g; i < n; i += G) strip[i * SWP + v] = j < p ? X[i * ldx + j] : 0.0;
+    __syncthreads();
+    double s1 = 0.0;
+    for (int64_t i = g; i < n; i += G) s1 += strip[i * SWP + v];
+    part[g][v] = s1;
+    __syncthreads();
+    if (t < SW) {
+        double a = 0.0;
+        for (int q = 0; q < G; ++q) a += part[q][t];
+        mv[t] = a / (double)n;
+    }
+    __syncthreads();
+    const double m = mv[v];
+    double s2 = 0.0;
+    for (int64_t i = g; i < n; i += G) {
+        const double d = strip[i * SWP + v] - m;
+        s2 += d * d;
+    }
+    __syncthreads();  // every thread has read mv and part before part is reused
+    part[g][v] = s2;
+    __syncthreads();
+    if (t < SW) {
+        double a = 0.0;
+        for (int q = 0; q < G; ++q) a += part[q][t];
+        const int64_t jj = j0 + t;
+        const double mm = mv[t];
+        double c;
+        if (!isfinite(mm) || !isfinite(a)) {
+            if (jj < p) atomicOr(flags, 1);
+            mv[t] = 0.0;
+            c = 1.0;
+        } else if (!(a > 0.0)) {
+            if (jj < p) atomicOr(flags, 2);
+            c = 1.0;
+        } else {
+            c = 1.0 / sqrt(a / (double)n);
+        }
+        cv[t] = c;
+        if (jj < p) {
+            mean[jj] = mv[t];
+            scale[jj] = c;
+            if (zero_cnt) zero_cnt[jj] = 0;
+        }
+    }
+    __syncthreads();
+    for (int w = 0; w < SW; ++w) {
+        const int64_t jj = j0 + w;
+        if (jj >= p) break;
+        const double mm = mv[w], cc = cv[w];
+        for (int64_t i = t; i < npad; i += 256) {
+            const double x = i < n ? (strip[i * SWP + w] - mm) * cc : 0.0;
+            if (i < n) Xt[jj * n + i] = x;
+            const float f = (float)x;
+            const uint16_t h = bf16_bits(f);
+            hi[jj * npad + i] = h;
+            lo[jj * npad + i] = bf16_bits(f - bf16_value(h));
+        }
+    }
+}
+
+// Strip width for the fused kernel: the widest of 16, 8, 4 whose LDS strip
+// fits 64 KB (several blocks per CU); 0 when none does.
+static int stats_split_width(int64_t n)
+{
+    for (int sw = 16; sw >= 4; sw >>= 1)
+        if ((size_t)n * (sw + 1) * 8 <= (size_t)64 * 1024) return sw;
+    return 0;
+}
+
+bool launch_stats_split(const double *X, int64_t n, int64_t p, int64_t ldx, double *mean,
+                        double *scale, double *Xt, uint16_t *hi, uint16_t *lo, int64_t npad,
+                        int *flags, int *zero_cnt, hipStream_t s)
+{
+    const int sw = stats_split_width(n);
+    if (sw == 0) return false;
+    const size_t lds = (size_t)n * (sw + 1) * 8;
+    const unsigned blocks = (unsigned)((p + sw - 1) / sw);
+    if (sw == 16)
+        hipLaunchKernelGGL(k_stats_split<16>, dim3(blocks), dim3(256), lds, s, X, n, p, ldx, mean, scale,
+                           Xt, hi, lo, npad, flags, zero_cnt);
+    else if (sw == 8)
+        hipLaunchKernelGGL(k_stats_split<8>, dim3(blocks), dim3(256), lds, s, X, n, p, ldx, mean, scale,
+                           Xt, hi, lo, npad, flags, zero_cnt);
+    else
+        hipLaunchKernelGGL(k_stats_split<4>, dim3(blocks), dim3(256), lds, s, X, n, p, ldx, mean, scale,
+                           Xt, hi, lo, npad, flags, zero_cnt);
+    return true;
+}
+
 void launch_standardize_split(const double *X, int64_t n, int64_t p, int64_t ldx,
                               const double *mean, const double *scale, double *Xt,
                               uint16_t *hi, uint16_t *lo, int64_t npad, hipStream_t s)
