@@ -332,8 +332,9 @@ static int validate(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
 }
 
 // The zero fill of the dense outputs needs nothing of the solve: it is
-// forked onto the context's second stream where the column solves turn
-// latency-bound (after the row-tiled KKT pass), and the scatter waits for it.
+// forked onto the context's second stream at a point where the main stream
+// leaves HBM to it (chosen per form by the caller), and the scatter waits
+// for it.
 static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p, hipStream_t s, Marker *mk)
 {
     if (!res->B && !res->Omega) return SPMESL_OK;
@@ -480,6 +481,16 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                                      (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
         mark(mk, s, "standardize");
     }
+    // The zero fill of the outputs goes on the second stream where the main
+    // stream leaves HBM to it: under the double covariance kernel (MFMA-bound,
+    // 290 us at p = 5000, little HBM traffic), else after the row-tiled KKT
+    // pass, under the latency-bound re-solves and polish (under the mixed
+    // form's covariance kernel it slowed that kernel from 87 to 109 us).
+    const bool fill_early = L.prec == SPMESL_FP64;
+    if (fill_early) {
+        const int v0 = fork_output_fill(ctx, res, p, s, mk);
+        if (v0 != SPMESL_OK) return v0;
+    }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
 
     // the first solves' working sets, {j : |s_jk| > kScreenFactor lambda0 +
@@ -512,7 +523,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
 
 
     const bool fill = res->B || res->Omega;
-    auto fork = [&] { return fork_output_fill(ctx, res, p, s, mk); };
+    auto fork = [&] { return fill_early ? (int)SPMESL_OK : fork_output_fill(ctx, res, p, s, mk); };
     int vc;
     if (L.prec == SPMESL_FP64)
         vc = enqueue_columns<double>(L, ws, dctl, opt, tol_cols, 0.0, max_outer, max_sweeps, max_rounds, s,
