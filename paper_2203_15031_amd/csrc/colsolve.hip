@@ -38,23 +38,37 @@
 
 namespace spmesl {
 
-template <typename T, int LW, int KCH>
-__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier);
+template <typename T, int LW, int KCH, int KU>
+__device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier, int part = 0,
+                             int nparts = 1, KktCoop *cp = nullptr);
 
-// KCH: groups per lane in flight in the in-wave KKT passes (4 for the first
-// solves, whose kernel covers every column; 8 for the resumes, which are few
-// and spend their time in those passes).
-template <typename T, int LW, int NW, int KCH, int MINW = 1>
+// KCH, KU: groups per lane in flight and support rows per step in the
+// in-wave KKT passes.  NW > 1 (the re-solves of flagged columns): when the
+// flagged columns fit one per block, the block's waves work on one column
+// together.  Each wave runs the column's solve itself (same inputs, same
+// instructions, so the same path and values in every wave), the KKT passes
+// are split over the waves by ranges of j, and only the first wave writes
+// the column's results.
+template <typename T, int LW, int NW, int KCH, int KU, int MINW = 1>
 __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW))) void k_colsolve(ColArgs<T> A, int tier)
 {
+    static_assert(NW <= kCoopMax, "waves sharing a KKT pass");
     __shared__ WaveSm<T, LW> smem[NW];
     const int wv = threadIdx.x / kWave;
     WaveSm<T, LW> &sm = smem[wv];
-    const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
     const int64_t nwork = A.mode ? (int64_t)*A.work_cnt : A.p;
+    if constexpr (NW > 1) {
+        if (A.mode && nwork <= (int64_t)gridDim.x) {
+            __shared__ KktCoop coop;
+            for (int64_t gw = blockIdx.x; gw < nwork; gw += gridDim.x)
+                solve_column<T, LW, KCH, KU>(A, sm, (int64_t)A.work_list[gw], tier, wv, NW, &coop);
+            return;
+        }
+    }
+    const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
     for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
         const int64_t k = A.mode ? (int64_t)A.work_list[gw] : gw;
-        solve_column<T, LW, KCH>(A, sm, k, tier);
+        solve_column<T, LW, KCH, KU>(A, sm, k, tier);
     }
 }
 
@@ -92,13 +106,15 @@ __device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const W
     }
 }
 
-template <typename T, int LW, int KCH>
-__device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier)
+template <typename T, int LW, int KCH, int KU>
+__device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier,
+                                             int part, int nparts, KktCoop *cp)
 {
     const int lane = lane_id();
+    const bool writer = part == 0;  // the wave that writes the column's results
     if (*A.flags) {
         // bad input: leave an empty, well-formed column for every consumer
-        if (lane == 0) {
+        if (writer && lane == 0) {
             A.w_cnt[k] = 0;
             A.supp_cnt[k] = 0;
             A.pend_cnt[k] = 0;
@@ -129,16 +145,16 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         if (nc > kPendMax) {
             // too many candidates for the list: screen in the wave below
             wave_sync();
-            if (lane == 0) A.pend_cnt[k] = 0;
+            if (writer && lane == 0) A.pend_cnt[k] = 0;
         } else if (nc >= 0) {
             // the screen at beta = 0 came with S: W = its candidates
             for (int i = lane; i < nc; i += kWave) sm.pend[i] = A.pend_idx[k * kPendMax + i];
             wave_sync();
-            if (lane == 0) A.pend_cnt[k] = 0;
+            if (writer && lane == 0) A.pend_cnt[k] = 0;
             int np = nc > 0 ? sort_unique_small(sm.pend, nc) : 0;
             if (np > LW) {
                 if (tier == 0) {
-                    escalate(A, k, sm, st, np, cnt, rounds);
+                    if (writer) escalate(A, k, sm, st, np, cnt, rounds);
                     return;
                 }
                 np = LW;
@@ -174,12 +190,15 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         np = np < 0 ? 0 : (np > kPendMax ? kPendMax : np);
         for (int i = lane; i < np; i += kWave) sm.pend[i] = A.pend_idx[k * kPendMax + i];
         wave_sync();
-        if (lane == 0) A.pend_cnt[k] = 0;
+        // every wave of a shared column has read its state before the
+        // first write to it (the barrier also completes those loads)
+        if (cp) __syncthreads();
+        if (writer && lane == 0) A.pend_cnt[k] = 0;
         if (np > 0) {
             np = sort_unique_small(sm.pend, np);
             if (st.w + np > LW) {
                 if (tier == 0) {
-                    escalate(A, k, sm, st, np, cnt, rounds);
+                    if (writer) escalate(A, k, sm, st, np, cnt, rounds);
                     return;
                 }
                 np = LW - st.w;
@@ -199,10 +218,9 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
 
     while (status == kColOk && !deferred) {
         int ns = build_support(sm, st);
-        int npend = kkt_pass<T, T, LW, KCH, 2>(A.S, p, k, sm, st.w, ns,
-                                                              st.lam_used + A.kkt_tol, band,
-                                                              st.lam_used - A.band, A.band_cnt,
-                                                              A.band_idx);
+        int npend = kkt_pass<T, T, LW, KCH, KU>(A.S, p, k, sm, st.w, ns, st.lam_used + A.kkt_tol, band,
+                                                st.lam_used - A.band, A.band_cnt, A.band_idx, part,
+                                                nparts, cp);
         if (npend == 0) break;
         if (rounds >= A.max_rounds) {
             status = kColNoconv;
@@ -211,7 +229,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         int np = npend < kPendMax ? npend : kPendMax;
         if (st.w + np > LW) {
             if (tier == 0) {
-                escalate(A, k, sm, st, np, cnt, rounds);
+                if (writer) escalate(A, k, sm, st, np, cnt, rounds);
                 return;
             }
             np = LW - st.w;
@@ -229,6 +247,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
             break;
         }
     }
+    if (!writer) return;
     store_column(A, k, sm, st, deferred ? (int)kColDeferred : status, true);
     if (lane == 0) {
         // deferred: the row-tiled pass appends to these lists; error: the
@@ -244,22 +263,22 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
 template <typename T>
 void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
 {
-    if (tier == 0) {
-        // one column per workgroup: a column's slot frees as soon as it is done
-        constexpr int NW = 1;
-        int64_t blocks = (a.p + NW - 1) / NW;
-        if (a.mode && blocks > 8192) blocks = 8192;  // resume walks a work list
-        if (a.mode)
-            hipLaunchKernelGGL((k_colsolve<T, 32, NW, 8>), dim3((unsigned)blocks), dim3(kWave * NW), 0, s,
-                               a, 0);
-        else
-            // float first solves: three waves per SIMD to hide their load latency
-            hipLaunchKernelGGL((k_colsolve<T, 32, NW, 4, sizeof(T) == 4 ? 3 : 1>), dim3((unsigned)blocks),
-                               dim3(kWave * NW), 0, s, a, 0);
+    if (tier == 0 && a.mode) {
+        // re-solves of flagged columns: 512 blocks of four waves.  Up to 512
+        // columns (the usual case) get a block each and share its waves in
+        // their KKT passes, which stream rows of S and are bound by the bytes
+        // one wave can hold in flight; more columns take one wave each.
+        hipLaunchKernelGGL((k_colsolve<T, 32, 4, 4, 4>), dim3(512), dim3(kWave * 4), 0, s, a, 0);
+    } else if (tier == 0) {
+        // first solves: one column per workgroup, so a column's slot frees as
+        // soon as it is done; float: three waves per SIMD to hide the load
+        // latency
+        hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, sizeof(T) == 4 ? 3 : 1>), dim3((unsigned)a.p),
+                           dim3(kWave), 0, s, a, 0);
     } else {
         // one wave per block walking the (short) escalation queue
         unsigned blocks = (unsigned)(a.p < 256 ? a.p : 256);
-        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1, 4>), dim3(blocks), dim3(kWave), 0, s, a, 1);
+        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1, 4, 2>), dim3(blocks), dim3(kWave), 0, s, a, 1);
     }
 }
 

@@ -142,9 +142,21 @@ __device__ __forceinline__ int lane_prefix(int c, int *total)
     return r;
 }
 
+// Block-shared lists of a cooperative KKT pass: the waves of a block take
+// contiguous, ascending ranges of j for one column, so the lists
+// concatenated in wave order are exactly those one wave would produce.
+constexpr int kCoopMax = 4;
+struct KktCoop {
+    int pend[kCoopMax][kPendMax];
+    int npend[kCoopMax];
+    int band[kCoopMax][kBandMax];
+    int nband[kCoopMax];
+};
+
 template <typename TS, typename T, int LW, int V, int CHV, int UV>
 __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
-                          int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
+                          int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx,
+                          int part, int nparts, KktCoop *cp)
 {
     constexpr int CH = V == 1 ? 8 : CHV;
     constexpr int U = V == 1 ? 4 : UV;
@@ -152,7 +164,13 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
     const int lane = lane_id();
     const TS *Sk = S + k * p;
     int npend = 0, nband = 0;
-    for (int64_t base = 0; base < p; base += STEP) {
+    // this wave's violators and band entries (its own lists, or its part of
+    // the block's when the pass is shared)
+    int *const plist = cp ? cp->pend[part] : sm.pend;
+    int *const blist = cp ? cp->band[part] : band_idx + k * kBandMax;
+    const int64_t nit = (p + STEP - 1) / STEP;
+    const int64_t it0 = part * nit / nparts, it1 = (part + 1) * nit / nparts;
+    for (int64_t base = it0 * STEP; base < it1 * STEP; base += STEP) {
         T acc[CH][V];
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -235,7 +253,7 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
 #pragma unroll
                 for (int e = 0; e < V; ++e)
                     if ((vm >> e) & 1u) {
-                        if (pos < kPendMax) sm.pend[pos] = (int)(j0 + e);
+                        if (pos < kPendMax) plist[pos] = (int)(j0 + e);
                         ++pos;
                     }
                 npend += tot;
@@ -246,16 +264,43 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
 #pragma unroll
                 for (int e = 0; e < V; ++e)
                     if ((bm >> e) & 1u) {
-                        if (pos < kBandMax) band_idx[k * kBandMax + pos] = (int)(j0 + e);
+                        if (pos < kBandMax) blist[pos] = (int)(j0 + e);
                         ++pos;
                     }
                 nband += tot;
             }
         }
     }
-    if (record_band && lane == 0) band_cnt[k] = nband;
-    wave_sync();
-    return npend;
+    if (!cp) {
+        if (record_band && lane == 0) band_cnt[k] = nband;
+        wave_sync();
+        return npend;
+    }
+    // shared pass: every wave takes the concatenated violators into its own
+    // list; part 0 writes the band list of the column
+    if (lane == 0) {
+        cp->npend[part] = npend;
+        cp->nband[part] = nband;
+    }
+    __syncthreads();
+    int tot = 0, btot = 0;
+    for (int q = 0; q < nparts; ++q) {
+        const int c = cp->npend[q];
+        const int cc = c < kPendMax ? c : kPendMax;
+        for (int i = lane; i < cc; i += kWave)
+            if (tot + i < kPendMax) sm.pend[tot + i] = cp->pend[q][i];
+        tot += c;
+        if (record_band && part == 0) {
+            const int b = cp->nband[q];
+            const int bb = b < kBandMax ? b : kBandMax;
+            for (int i = lane; i < bb; i += kWave)
+                if (btot + i < kBandMax) band_idx[k * kBandMax + btot + i] = cp->band[q][i];
+        }
+        btot += cp->nband[q];
+    }
+    if (record_band && part == 0 && lane == 0) band_cnt[k] = btot;
+    __syncthreads();  // the shared lists are free for the next pass
+    return tot;
 }
 
 // CH groups of V per lane in flight and U support rows at a time: the
@@ -263,15 +308,17 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
 // kernel (few columns) takes deeper settings.
 template <typename TS, typename T, int LW, int CH = 4, int U = 2>
 __device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
-                        int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx)
+                        int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx,
+                        int part = 0, int nparts = 1, KktCoop *cp = nullptr)
 {
     constexpr int V = 16 / sizeof(TS);
     // rows of S start 16-byte aligned when p is a multiple of V (S itself
     // is 256-byte aligned)
     if (p % V == 0)
         return kkt_pass_v<TS, T, LW, V, CH, U>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt,
-                                              band_idx);
-    return kkt_pass_v<TS, T, LW, 1, CH, U>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx);
+                                              band_idx, part, nparts, cp);
+    return kkt_pass_v<TS, T, LW, 1, CH, U>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx,
+                                          part, nparts, cp);
 }
 
 // Support list (nonzero coefficients, ascending) from the slot registers.
