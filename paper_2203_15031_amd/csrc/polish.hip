@@ -25,45 +25,68 @@ __device__ __forceinline__ int64_t clamp_index(int v, int64_t p)
     return v < 0 ? 0 : (v >= p ? p - 1 : (int64_t)v);
 }
 
-// Working sets of at most three variables: the four rows (x_k and W') are
-// read for four 64-sample chunks at a time with every load in flight
-// together, so the n-sample products cost ceil(n / 256) memory round trips
-// rather than one per 64 samples.
-constexpr int kSmallW = 3;
-
-template <int LW>
-__device__ __forceinline__ void gram_small(const double *__restrict__ Xt, int64_t n, int64_t p, int64_t k,
-                                           const WaveSm<double, LW> &sm, int w, double *pr)
+// Small working sets: the R rows x_k, x_{W'[0]}, .., x_{W'[R-2]} are read for
+// C 64-sample chunks at a time with every load of a batch in flight together,
+// so the n-sample dot products take ceil(n / (64 C)) memory round trips
+// rather than one per 64 samples for each group of pairs.  pr[] receives the
+// R (R - 1) / 2 products of rows a < b in row-major pair order, divided by n.
+template <int R, int C, int LW>
+__device__ __forceinline__ void gram_rows(const double *__restrict__ Xt, int64_t n, int64_t p, int64_t k,
+                                          const WaveSm<double, LW> &sm, int w, double *pr)
 {
+    constexpr int NP = R * (R - 1) / 2;
     const int lane = lane_id();
-    const double *r[4];
+    const double *r[R];
     r[0] = Xt + k * n;
 #pragma unroll
-    for (int q = 1; q < 4; ++q) r[q] = Xt + (q <= w ? clamp_index(sm.widx[q - 1], p) : k) * n;
-    // pairs: (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t i0 = 0; i0 < n; i0 += 4 * kWave) {
-        double v[4][4];
+    for (int q = 1; q < R; ++q) r[q] = Xt + (q <= w ? clamp_index(sm.widx[q - 1], p) : k) * n;
+    double acc[NP];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+    for (int u = 0; u < NP; ++u) acc[u] = 0.0;
+    for (int64_t i0 = 0; i0 < n; i0 += C * kWave) {
+        double v[R][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
             const int64_t i = i0 + c * kWave + lane;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q][c] = (q <= w && i < n) ? r[q][i] : 0.0;
+            for (int q = 0; q < R; ++q) v[q][c] = (q <= w && i < n) ? r[q][i] : 0.0;
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            acc[0] += v[0][c] * v[1][c];
-            acc[1] += v[0][c] * v[2][c];
-            acc[2] += v[0][c] * v[3][c];
-            acc[3] += v[1][c] * v[2][c];
-            acc[4] += v[1][c] * v[3][c];
-            acc[5] += v[2][c] * v[3][c];
+        for (int c = 0; c < C; ++c) {
+            int u = 0;
+#pragma unroll
+            for (int a = 0; a < R; ++a)
+#pragma unroll
+                for (int b = a + 1; b < R; ++b) acc[u++] += v[a][c] * v[b][c];
         }
     }
     const double invn = 1.0 / (double)n;
 #pragma unroll
-    for (int u = 0; u < 6; ++u) pr[u] = wave_sum(acc[u]) * invn;
+    for (int u = 0; u < NP; ++u) pr[u] = wave_sum(acc[u]) * invn;
 }
+
+// Products of rows a < b (row 0 = x_k) into s_W' (tbeta, staged) and S_W'W'.
+template <int R, int LW>
+__device__ __forceinline__ void store_gram_rows(WaveSm<double, LW> &sm, int w, const double *pr)
+{
+    if (lane_id() != 0) return;
+    int u = 0;
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = a + 1; b < R; ++b, ++u) {
+            if (b > w) continue;
+            if (a == 0) {
+                sm.tbeta[b - 1] = pr[u];
+            } else {
+                sm.sww[(b - 1) * LW + (a - 1)] = pr[u];
+                sm.sww[(a - 1) * LW + (b - 1)] = pr[u];
+            }
+        }
+}
+
+constexpr int kSmallW = 3;   // four rows, four chunks per batch
+constexpr int kMidW = 7;     // eight rows, two chunks per batch
 
 template <int LW>
 __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t p,
@@ -79,25 +102,14 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
     const double *xk = Xt + k * n;
     if (w <= kSmallW) {
         double pr[6];
-        gram_small(Xt, n, p, k, sm, w, pr);
-        if (lane == 0) {
-            // rows 1..3 of the product list are W'[0..2]; row 0 is x_k
-            if (w > 0) sm.tbeta[0] = pr[0];
-            if (w > 1) {
-                sm.tbeta[1] = pr[1];
-                sm.sww[1 * LW + 0] = pr[3];
-                sm.sww[0 * LW + 1] = pr[3];
-            }
-            if (w > 2) {
-                sm.tbeta[2] = pr[2];
-                sm.sww[2 * LW + 0] = pr[4];
-                sm.sww[0 * LW + 2] = pr[4];
-                sm.sww[2 * LW + 1] = pr[5];
-                sm.sww[1 * LW + 2] = pr[5];
-            }
-        }
+        gram_rows<4, 4>(Xt, n, p, k, sm, w, pr);
+        store_gram_rows<4>(sm, w, pr);
+    } else if (kMidW < LW && w <= kMidW) {
+        double pr[28];
+        gram_rows<8, 2>(Xt, n, p, k, sm, w, pr);
+        store_gram_rows<8>(sm, w, pr);
     }
-    for (int t0 = w <= kSmallW ? P : 0; t0 < P; t0 += 4) {
+    for (int t0 = w <= kMidW ? P : 0; t0 < P; t0 += 4) {
         const double *ra[4], *rb[4];
         int qa[4], qb[4];
 #pragma unroll
