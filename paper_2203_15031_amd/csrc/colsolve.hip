@@ -141,14 +141,17 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         st.lam_used = A.lambda0;
 #pragma unroll
         for (int s = 0; s < ColState<T, LW>::NS; ++s) st.g[s] = st.b[s] = st.sv[s] = T(0);
+        // the count and (speculatively: the list holds kPendMax = 64 slots
+        // per column) the candidates, in one round of loads
         int nc = A.screened ? A.pend_cnt[k] : -1;
+        const int cfirst = A.screened ? A.pend_idx[k * kPendMax + lane] : 0;
         if (nc > kPendMax) {
             // too many candidates for the list: screen in the wave below
             wave_sync();
             if (writer && lane == 0) A.pend_cnt[k] = 0;
         } else if (nc >= 0) {
-            // the screen at beta = 0 came with S: W = its candidates
-            for (int i = lane; i < nc; i += kWave) sm.pend[i] = A.pend_idx[k * kPendMax + i];
+            // the screen taken with S: W = its candidates
+            if (lane < nc) sm.pend[lane] = cfirst;
             wave_sync();
             if (writer && lane == 0) A.pend_cnt[k] = 0;
             int np = nc > 0 ? sort_unique_small(sm.pend, nc) : 0;

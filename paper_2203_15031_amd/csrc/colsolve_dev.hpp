@@ -411,13 +411,22 @@ __device__ __forceinline__ void load_working_set(const T *__restrict__ S, int64_
         }
         st.g[s] = T(0);
     }
-    const int tot = w * w;
+    // S is stored symmetric bit for bit: the upper triangle (with the unit
+    // diagonal) is gathered and mirrored, w (w + 1) / 2 entries, one load per
+    // lane for w <= 10
+    const int tot = w * (w + 1) / 2;
     for (int e = lane; e < tot; e += kWave) {
-        int qj = e / w, qi = e - qj * w;
+        // e = qj (qj + 1) / 2 + qi, qi <= qj
+        int qj = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        while (qj * (qj + 1) / 2 > e) --qj;
+        while ((qj + 1) * (qj + 2) / 2 <= e) ++qj;
+        const int qi = e - qj * (qj + 1) / 2;
         int64_t a = sm.widx[qj], b = sm.widx[qi];
         a = a < 0 ? 0 : (a >= p ? p - 1 : a);
         b = b < 0 ? 0 : (b >= p ? p - 1 : b);
-        sm.sww[qj * LW + qi] = S[a * p + b];
+        const T v = S[a * p + b];
+        sm.sww[qj * LW + qi] = v;
+        sm.sww[qi * LW + qj] = v;
     }
     wave_sync();
     rows_to_registers(sm, st, rlo, rhi);
