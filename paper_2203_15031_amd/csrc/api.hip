@@ -158,6 +158,7 @@ struct spmesl_ctx {
     // outputs, which overlaps the latency-bound column solves
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork2 = nullptr, join2 = nullptr;  // statistics reduction beside the scatter
     // per-launch timing (SPMESL_FLAG_TIMING): events in enqueue order, each
     // with the index of the previous event on its stream
     static constexpr int kMaxMarks = 48;
@@ -571,13 +572,20 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         mark(mk, s, "polish");
     }
     {
+        // the statistics reduction reads only the column results: it runs on
+        // the second stream (behind the fill it may still hold) while the
+        // scatter runs here, and the solve ends when both are done
         const bool mixed = L.prec == SPMESL_MIXED;
+        HIPTRY(ctx, hipEventRecord(ctx->fork2, s));
+        HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork2, 0));
+        mark(mk, ctx->side, nullptr);
         launch_reduce_stats(p, (const int *)(ws + L.colinfo),
                             mixed ? (const int *)(ws + L.polinfo) : nullptr,
                             (const int *)(ws + (mixed ? L.wcnt64 : L.wcnt)),
                             (const int *)(ws + (mixed ? L.cstat64 : L.cstat)), dctl->counters,
-                            &dctl->status1, s);
-        mark(mk, s, "reduce_stats");
+                            &dctl->status1, ctx->side);
+        mark(mk, ctx->side, "reduce_stats");
+        HIPTRY(ctx, hipEventRecord(ctx->join2, ctx->side));
     }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[4], s));
 
@@ -599,6 +607,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                                        (const double *)(ws + L.sigma64), scale, original, res->B,
                                        res->sigma, res->Omega, &dctl->flags, s);
     mark(mk, s, "scatter");
+    HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join2, 0));
     if (ev) HIPTRY(ctx, hipEventRecord(ev[5], s));
     HIPTRY(ctx, hipGetLastError());
     return SPMESL_OK;
@@ -699,6 +708,8 @@ int spmesl_create(spmesl_ctx **out, int device, void *hip_stream)
     ok = ok && hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ctx->fork2, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ctx->join2, hipEventDisableTiming) == hipSuccess;
     bool kok = ok;
     for (int i = 0; i < spmesl_ctx::kMaxMarks && kok; ++i) kok = hipEventCreate(&ctx->kev[i]) == hipSuccess;
     ctx->kev_ok = kok;
@@ -729,6 +740,8 @@ void spmesl_destroy(spmesl_ctx *ctx)
             if (ctx->kev[i]) (void)hipEventDestroy(ctx->kev[i]);
         if (ctx->fork) (void)hipEventDestroy(ctx->fork);
         if (ctx->join) (void)hipEventDestroy(ctx->join);
+        if (ctx->fork2) (void)hipEventDestroy(ctx->fork2);
+        if (ctx->join2) (void)hipEventDestroy(ctx->join2);
         if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         for (int i = 0; i < 6; ++i)
