@@ -27,8 +27,17 @@ static int64_t kkt_buffer_elems(int64_t p, int rj, size_t elem)
     return ((int64_t)rj * p + 2 * v + v - 1) / v * v;
 }
 
+// Flagged pairs of a block, examined after its row tiles (so that the few
+// long chains of global loads they take hold no barrier of the tile loop).
+constexpr int kKktFlagCap = 384;
+struct KktFlagList {
+    int n;
+    int jk[2 * kKktFlagCap];
+};
+
 int kkt_rows_per_block(int64_t p, size_t elem, size_t lds_budget)
 {
+    lds_budget -= sizeof(KktFlagList);
     for (int rj = 4; rj >= 1; rj >>= 1)
         if (2 * (size_t)kkt_buffer_elems(p, rj, elem) * elem <= lds_budget) return rj;
     return 0;
@@ -129,8 +138,10 @@ template <typename T, int RJ, int CPT, bool PK>
 __global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t rpb, int64_t bstride)
 {
     extern __shared__ __align__(16) unsigned char kkt_lds[];
+    __shared__ KktFlagList fl;
     T *const buf0 = reinterpret_cast<T *>(kkt_lds);
     if (*A.flags) return;
+    if (threadIdx.x == 0) fl.n = 0;  // visible after the chunk loop's first barrier
     const int64_t p = A.p;
     const int64_t rb = (int64_t)blockIdx.x * rpb;
     const int64_t re = rb + rpb < p ? rb + rpb : p;
@@ -262,9 +273,24 @@ __global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t 
                 flagged &= flagged - 1;
                 const int u = bit / RJ, r = bit % RJ;
                 const int64_t k = cbase + (int64_t)u * kKktThreads + tid;
-                kkt_flagged<T>(A, k, j0 + r, cur + (int64_t)r * p);
+                const int pos = atomicAdd(&fl.n, 1);
+                if (pos < kKktFlagCap) {
+                    fl.jk[2 * pos] = (int)(j0 + r);
+                    fl.jk[2 * pos + 1] = (int)k;
+                } else {
+                    kkt_flagged<T>(A, k, j0 + r, cur + (int64_t)r * p);  // list full
+                }
             }
         }
+        // the chunk's flagged pairs, re-read from S in global memory
+        __syncthreads();
+        const int nf = fl.n < kKktFlagCap ? fl.n : kKktFlagCap;
+        for (int i = tid; i < nf; i += kKktThreads) {
+            const int64_t j = fl.jk[2 * i], k = fl.jk[2 * i + 1];
+            kkt_flagged<T>(A, k, j, A.S + j * p);
+        }
+        __syncthreads();
+        if (tid == 0) fl.n = 0;
     }
 }
 
