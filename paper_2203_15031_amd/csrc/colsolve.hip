@@ -38,7 +38,7 @@
 
 namespace spmesl {
 
-template <typename T, int LW, int KCH, int KU>
+template <typename T, int LW, int KCH, int KU, bool FIRST = false>
 __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier, int part = 0,
                              int nparts = 1, KktCoop *cp = nullptr);
 
@@ -48,8 +48,11 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, 
 // together.  Each wave runs the column's solve itself (same inputs, same
 // instructions, so the same path and values in every wave), the KKT passes
 // are split over the waves by ranges of j, and only the first wave writes
-// the column's results.
-template <typename T, int LW, int NW, int KCH, int KU, int MINW = 1>
+// the column's results.  FIRST: the first solves when the row-tiled KKT pass
+// follows (each column is left deferred after one working-set solve), with
+// none of the other paths compiled in; the rare column with more candidates
+// than its list holds is handed to the wide kernel, which screens in the wave.
+template <typename T, int LW, int NW, int KCH, int KU, int MINW = 1, bool FIRST = false>
 __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW))) void k_colsolve(ColArgs<T> A, int tier)
 {
     static_assert(NW <= kCoopMax, "waves sharing a KKT pass");
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW)
     const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
     for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
         const int64_t k = A.mode ? (int64_t)A.work_list[gw] : gw;
-        solve_column<T, LW, KCH, KU>(A, sm, k, tier);
+        solve_column<T, LW, KCH, KU, FIRST>(A, sm, k, tier);
     }
 }
 
@@ -106,7 +109,7 @@ __device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const W
     }
 }
 
-template <typename T, int LW, int KCH, int KU>
+template <typename T, int LW, int KCH, int KU, bool FIRST>
 __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier,
                                              int part, int nparts, KktCoop *cp)
 {
@@ -135,7 +138,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
     int rounds = 0, status = kColOk;
     bool deferred = false;
 
-    if (A.mode == 0) {
+    if (FIRST || A.mode == 0) {
         st.w = 0;
         st.sigma = T(1);
         st.lam_used = A.lambda0;
@@ -145,7 +148,12 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         // per column) the candidates, in one round of loads
         int nc = A.screened ? A.pend_cnt[k] : -1;
         const int cfirst = A.screened ? A.pend_idx[k * kPendMax + lane] : 0;
-        if (nc > kPendMax) {
+        if (FIRST && !(nc >= 0 && nc <= kPendMax)) {
+            // too many candidates for the list: the wide kernel screens in
+            // the wave (resumed from W = {} with no pending candidates)
+            if (writer) escalate(A, k, sm, st, 0, cnt, rounds);
+            return;
+        } else if (nc > kPendMax) {
             // too many candidates for the list: screen in the wave below
             wave_sync();
             if (writer && lane == 0) A.pend_cnt[k] = 0;
@@ -174,7 +182,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
                 deferred = true;
             }
         }
-    } else {
+    } else if constexpr (!FIRST) {
         st.w = A.w_cnt[k];
         st.w = st.w < 0 ? 0 : (st.w > LW ? LW : st.w);
         for (int q = lane; q < st.w; q += kWave) {
@@ -219,7 +227,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         }
     }
 
-    while (status == kColOk && !deferred) {
+    while (!FIRST && status == kColOk && !deferred) {
         int ns = build_support(sm, st);
         int npend = kkt_pass<T, T, LW, KCH, KU>(A.S, p, k, sm, st.w, ns, st.lam_used + A.kkt_tol, band,
                                                 st.lam_used - A.band, A.band_cnt, A.band_idx, part,
@@ -272,10 +280,14 @@ void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
         // their KKT passes, which stream rows of S and are bound by the bytes
         // one wave can hold in flight; more columns take one wave each.
         hipLaunchKernelGGL((k_colsolve<T, 32, 4, 4, 4>), dim3(512), dim3(kWave * 4), 0, s, a, 0);
-    } else if (tier == 0) {
+    } else if (tier == 0 && a.defer_kkt && a.screened) {
         // first solves: one column per workgroup, so a column's slot frees as
-        // soon as it is done; float: three waves per SIMD to hide the load
-        // latency
+        // soon as it is done
+        hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, 1, true>), dim3((unsigned)a.p), dim3(kWave), 0, s, a,
+                           0);
+    } else if (tier == 0) {
+        // first solves with in-wave KKT passes; float: three waves per SIMD
+        // to hide the load latency
         hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, sizeof(T) == 4 ? 3 : 1>), dim3((unsigned)a.p),
                            dim3(kWave), 0, s, a, 0);
     } else {
