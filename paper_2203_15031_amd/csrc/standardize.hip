@@ -276,11 +276,13 @@ __global__ __launch_bounds__(256) void k_stats_split(const double *__restrict__ 
     }
 }
 
-// Strip width for the fused kernel: the widest of 16, 8, 4 whose LDS strip
-// fits 64 KB (several blocks per CU); 0 when none does.
+// Strip width for the fused kernel: 8 variables (64-byte row segments) when
+// the LDS strip fits 64 KB, else 4; 0 when neither does.  At n = 400,
+// p = 5000 the 8-wide strips (625 blocks, about five per CU) take 17 us where
+// 16-wide ones (313 blocks, two per CU) took 23 us and 4-wide ones 20 us.
 static int stats_split_width(int64_t n)
 {
-    for (int sw = 16; sw >= 4; sw >>= 1)
+    for (int sw = 8; sw >= 4; sw >>= 1)
         if ((size_t)n * (sw + 1) * 8 <= (size_t)64 * 1024) return sw;
     return 0;
 }
@@ -293,10 +295,7 @@ bool launch_stats_split(const double *X, int64_t n, int64_t p, int64_t ldx, doub
     if (sw == 0) return false;
     const size_t lds = (size_t)n * (sw + 1) * 8;
     const unsigned blocks = (unsigned)((p + sw - 1) / sw);
-    if (sw == 16)
-        hipLaunchKernelGGL(k_stats_split<16>, dim3(blocks), dim3(256), lds, s, X, n, p, ldx, mean, scale,
-                           Xt, hi, lo, npad, flags, zero_cnt);
-    else if (sw == 8)
+    if (sw == 8)
         hipLaunchKernelGGL(k_stats_split<8>, dim3(blocks), dim3(256), lds, s, X, n, p, ldx, mean, scale,
                            Xt, hi, lo, npad, flags, zero_cnt);
     else
