@@ -482,12 +482,15 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                                      (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
         mark(mk, s, "standardize");
     }
-    // The zero fill of the outputs goes on the second stream where the main
-    // stream leaves HBM to it: under the double covariance kernel (MFMA-bound,
-    // 290 us at p = 5000, little HBM traffic), else after the row-tiled KKT
-    // pass, under the latency-bound re-solves and polish (under the mixed
-    // form's covariance kernel it slowed that kernel from 87 to 109 us).
-    const bool fill_early = L.prec == SPMESL_FP64;
+    // The zero fill of the outputs goes on the second stream under the
+    // covariance kernel, which leaves HBM to it (double: MFMA-bound, 290 us at
+    // p = 5000; mixed: it slows that kernel from 86 to about 102 us), so that
+    // the latency-bound column solves after it run without the fill's 400 MB
+    // of writes beside them.  Measured at p = 5000, mixed: 0.262 ms per solve
+    // against 0.269 with the fill after the row-tiled KKT pass (which left the
+    // polish at 52-57 us instead of 36) and 0.311 with it under the column
+    // solves at a low rate (the KKT pass doubled).
+    const bool fill_early = true;
     if (fill_early) {
         const int v0 = fork_output_fill(ctx, res, p, s, mk);
         if (v0 != SPMESL_OK) return v0;

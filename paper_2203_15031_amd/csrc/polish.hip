@@ -154,7 +154,6 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
     }
     for (int q = lane; q < w; q += kWave) sm.sww[q * LW + q] = 1.0;
     wave_sync();
-    rows_to_registers(sm, st, rlo, rhi);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         int q = s * kWave + lane;
@@ -163,6 +162,83 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
         st.g[s] = 0.0;
     }
     wave_sync();
+}
+
+// Direct solve of the scaled lasso on W' for the float solution's support A
+// and signs z.  With A and z fixed the lasso solution at lambda = lambda0
+// sigma is beta_A = u - lambda v with u = S_AA^-1 s_A, v = S_AA^-1 z_A, and
+// the noise update of Eq. (eq:sigma) becomes sigma^2 = 1 - u's_A +
+// lambda0^2 sigma^2 z_A'v, so the fixed point of the outer iteration is
+// sigma^2 = (1 - u's_A) / (1 - lambda0^2 z_A'v).  When the resulting beta_A
+// has the signs z and every other j in W' has |g_j| <= lambda (+ tol), it is
+// the minimiser of Eq. (eq:spmesl) on W' exactly (the KKT conditions of
+// Eq. (eqn:lasso) hold with the sigma that is its own update); otherwise
+// (the support or a sign changes, or the system is degenerate) nothing is
+// changed and coordinate descent runs.  The |A| x |A| system is solved by
+// Gauss-Jordan elimination, one row per lane (S_AA is symmetric positive
+// definite, so no pivoting).
+constexpr int kDirectMax = 8;
+
+template <int LW>
+__device__ bool polish_direct(WaveSm<double, LW> &sm, ColState<double, LW> &st, double lambda0, double tol)
+{
+    static_assert(ColState<double, LW>::NS == 1, "one coordinate per lane");
+    const int lane = lane_id();
+    const int w = st.w;
+    const bool inA = lane < w && st.b[0] != 0.0;
+    const unsigned long long mA = __ballot(inA);
+    const int m = __popcll(mA);
+    if (m == 0 || m > kDirectMax) return false;
+    const int r0 = lanes_below(mA);  // compact position of this lane's coordinate
+    if (inA) sm.tidx[r0] = lane;
+    wave_sync();
+    // compact row r = lane: S_AA, s_A, z_A (rows of the lanes below m)
+    const bool row = lane < m;
+    const int qr = row ? sm.tidx[lane] : 0;
+    double a[kDirectMax];
+#pragma unroll
+    for (int c = 0; c < kDirectMax; ++c) a[c] = (row && c < m) ? sm.sww[qr * LW + sm.tidx[c]] : 0.0;
+    const double s0 = row ? sm.tbeta[qr] : 0.0;  // s_W' as staged by the Gram
+    const double z0 = row ? (sm.wbeta[qr] > 0.0 ? 1.0 : -1.0) : 0.0;
+    double xs = s0, xz = z0;
+#pragma unroll
+    for (int c = 0; c < kDirectMax; ++c) {
+        if (c >= m) break;
+        const double pc = bcast(a[c], c);
+        if (!(pc > 1e-12)) return false;
+        const double rs = bcast(xs, c), rz = bcast(xz, c);
+        // lane c's own row is left as it is (f = 0), so its entries read
+        // here are those of the pivot row at this step
+        const double f = (row && lane != c) ? a[c] / pc : 0.0;
+#pragma unroll
+        for (int e = 0; e < kDirectMax; ++e) a[e] -= f * bcast(a[e], c);
+        xs -= f * rs;
+        xz -= f * rz;
+    }
+    double d = 1.0;
+#pragma unroll
+    for (int c = 0; c < kDirectMax; ++c)
+        if (c == lane) d = a[c];
+    const double u = row ? xs / d : 0.0, v = row ? xz / d : 0.0;
+    const double us = wave_sum(u * s0), vz = wave_sum(v * z0);
+    const double c0 = 1.0 - us, c2 = lambda0 * lambda0 * vz;
+    if (!(c0 > DegenerateFloor<double>::v) || !(c2 < 1.0)) return false;
+    const double sigma = sqrt(c0 / (1.0 - c2));
+    const double lam = lambda0 * sigma;
+    const double beta = u - lam * v;
+    if (__ballot(row && !(z0 > 0.0 ? beta > 0.0 : beta < 0.0))) return false;
+    // gradients of the coordinates of W' outside A
+    if (row) sm.sval[lane] = beta;
+    wave_sync();
+    double g = lane < w ? st.sv[0] : 0.0;
+    for (int r = 0; r < m; ++r) g -= (lane < w ? sm.sww[lane * LW + sm.tidx[r]] : 0.0) * sm.sval[r];
+    const double ag = g < 0.0 ? -g : g;
+    if (__ballot(lane < w && !inA && ag > lam + tol)) return false;
+    st.b[0] = inA ? sm.sval[r0] : 0.0;
+    st.sigma = sigma;
+    st.lam_used = lam;
+    wave_sync();
+    return true;
 }
 
 // beta32 of variable j in column k's float list (0 if absent)
@@ -183,8 +259,9 @@ __device__ __forceinline__ double beta32_of(const PolishArgs &A, int64_t k, int 
 template <int LW>
 __device__ void polish_column(const PolishArgs &A, WaveSm<double, LW> &sm, int64_t k, int tier2);
 
-template <int LW, int NW>
-__global__ __launch_bounds__(kWave *NW) void k_polish(PolishArgs A, int tier2)
+template <int LW, int NW, int MINW = 1>
+__global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW))) void k_polish(PolishArgs A,
+                                                                                                 int tier2)
 {
     __shared__ WaveSm<double, LW> smem[NW];
     const int wv = threadIdx.x / kWave;
@@ -288,8 +365,21 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     st.lam_used = lam32;
 
     while (status == kColOk) {
+        // the direct solve first (first round, one coordinate per lane);
+        // the register rows of S_W'W' are filled only for coordinate descent
+        constexpr bool kTryDirect = ColState<double, LW>::NS == 1;
+        const bool try_direct = kTryDirect && !full;
         load_working_set_xt(A.Xt, A.n, A.p, k, sm, st, rlo, rhi);
-        status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+        bool direct = false;
+        if constexpr (kTryDirect) {
+            if (try_direct) direct = polish_direct(sm, st, A.lambda0, A.tol);
+        }
+        if (direct) {
+            ++cnt.outer;
+        } else {
+            rows_to_registers(sm, st, rlo, rhi);
+            status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+        }
         if (status != kColOk) break;
         // bound on the change of any gradient outside W'
         double part = 0.0, nrm = 0.0;
@@ -385,7 +475,7 @@ void launch_polish(const PolishArgs &a, hipStream_t s)
 {
     // one column per workgroup: a column's slot frees as soon as it is done
     constexpr int NW = 1;
-    hipLaunchKernelGGL((k_polish<32, NW>), dim3((unsigned)((a.p + NW - 1) / NW)),
+    hipLaunchKernelGGL((k_polish<32, NW, 3>), dim3((unsigned)((a.p + NW - 1) / NW)),
                        dim3(kWave * NW), 0, s, a, 0);
     hipLaunchKernelGGL((k_polish<kWMax, 1>), dim3((unsigned)(a.p < 256 ? a.p : 256)), dim3(kWave), 0,
                        s, a, 1);
