@@ -67,6 +67,7 @@ TRAFFIC_ROWS = {
     ("syrk_f64", None): ("syrk_f64", ["syrk.hip"]),
     ("kkt_rows", "fp64"): ("kkt_rows (double)", ["kkt.hip"]),
     ("kkt_rows", "mixed"): ("kkt_rows (float)", ["kkt.hip"]),
+    ("standardize", "mixed"): ("standardize (mixed)", ["standardize.hip"]),
     ("fill_B", None): ("fill_B / fill_Omega", ["output.hip"]),
     ("fill_Omega", None): ("fill_B / fill_Omega", ["output.hip"]),
 }
