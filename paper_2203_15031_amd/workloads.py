@@ -229,10 +229,12 @@ def paper_network(kind: str, p: int, rng) -> np.ndarray:
 
     kind: "ar1" (omega_ii = 1, omega_{i,i+-1} = 0.48), "ar4"
     (0.6^|i-j| for |i-j| <= 4), "sf" (Barabasi-Albert scale-free) or "hub"
-    (10 hubs of degree about 15 per 100 nodes).  "sf" and "hub" are built as
+    (10 hubs per 100 nodes, each non-hub joined to 1-3 of them).  "sf" and "hub" are built as
     p/100 subnetworks of 100 nodes with off-diagonal magnitudes raised to at
     least 0.1, through the steps: U([-1,-0.5] U [0.5,1]) weights, row
-    division by 1.5 x the row's absolute sum, symmetrisation, unit diagonal.
+    division by 1.5 x the row's absolute sum, symmetrisation, unit diagonal,
+    then (not positive definite otherwise) a diagonal shift to a smallest
+    eigenvalue of 0.1 per subnetwork.
     """
     if kind == "ar1":
         Om = np.eye(p)
@@ -262,6 +264,12 @@ def paper_network(kind: str, p: int, rng) -> np.ndarray:
         small = (T != 0) & (np.abs(T) < 0.1)
         T[small] = np.sign(T[small]) * 0.1
         np.fill_diagonal(T, 1.0)
+        # these steps do not give a positive definite matrix when a node has
+        # many neighbours (a hub row sums to about 5); the diagonal is then
+        # raised until the smallest eigenvalue is 0.1
+        ev = np.linalg.eigvalsh(T).min()
+        if ev < 0.1:
+            T += (0.1 - ev) * np.eye(100)
         Om[s:s + 100, s:s + 100] = T
     return Om
 
@@ -285,9 +293,12 @@ def _hub_edges(m_nodes: int, rng):
     hubs = rng.choice(m_nodes, size=10, replace=False)
     others = np.setdiff1d(np.arange(m_nodes), hubs)
     edges = set()
-    # each non-hub joins 1-3 hubs; hubs end near degree 15 on average
+    # each non-hub joins 1-3 hubs, one with probability 0.8, two with 0.18,
+    # three with 0.02 (mean 1.22): about 110 edges per 100 nodes, the edge
+    # count the paper's hub networks have at p = 500 (551); hubs then average
+    # degree 11
     for v in others:
-        k = rng.integers(1, 4)
+        k = int(rng.choice(3, p=[0.8, 0.18, 0.02])) + 1
         for h in rng.choice(hubs, size=k, replace=False):
             edges.add((min(h, v), max(h, v)))
     return sorted(edges)
