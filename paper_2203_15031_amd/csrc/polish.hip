@@ -134,10 +134,24 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
                 ra[u] = Xt + clamp_index(sm.widx[t - ntri], p) * n;
             }
         }
+        // four 64-sample chunks per step, every load of a step in flight
+        // together (a round trip per 256 samples instead of per 64)
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t i = lane; i < n; i += kWave) {
+        for (int64_t i0 = lane; i0 < n; i0 += 4 * kWave) {
+            double xa[4][4], xb[4][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += ra[u][i] * rb[u][i];
+            for (int c = 0; c < 4; ++c) {
+                const int64_t i = i0 + c * kWave;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xa[c][u] = i < n ? ra[u][i] : 0.0;
+                    xb[c][u] = i < n ? rb[u][i] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] += xa[c][u] * xb[c][u];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
