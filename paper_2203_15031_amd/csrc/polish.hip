@@ -88,6 +88,76 @@ __device__ __forceinline__ void store_gram_rows(WaveSm<double, LW> &sm, int w, c
 constexpr int kSmallW = 3;   // four rows, four chunks per batch
 constexpr int kMidW = 7;     // eight rows, two chunks per batch
 
+// Larger working sets: the rows x_k, x_{W'[0]}, .. (R = w + 1 of them) in
+// blocks of four; each pair of blocks reads its eight rows for two 64-sample
+// chunks at a time (all loads of a step in flight) and accumulates the 16
+// products in registers, so a row is re-read once per block rather than once
+// per pair.  Products of rows a < b go to s_W' (a = 0, staged in tbeta) or to
+// S_W'W' (mirrored), divided by n.
+template <int LW>
+__device__ void gram_blocked(const double *__restrict__ Xt, int64_t n, int64_t p, int64_t k,
+                             WaveSm<double, LW> &sm, int w)
+{
+    const int lane = lane_id();
+    const int R = w + 1;
+    const int nb = (R + 3) / 4;
+    const double invn = 1.0 / (double)n;
+    auto row = [&](int r) -> const double * {
+        return Xt + (r == 0 || r > w ? k : clamp_index(sm.widx[r - 1], p)) * n;
+    };
+    for (int bi = 0; bi < nb; ++bi)
+        for (int bj = bi; bj < nb; ++bj) {
+            const double *ra[4], *rb[4];
+            bool va[4], vb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                va[u] = 4 * bi + u < R;
+                vb[u] = 4 * bj + u < R;
+                ra[u] = row(4 * bi + u);
+                rb[u] = row(4 * bj + u);
+            }
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+            for (int64_t i0 = lane; i0 < n; i0 += 2 * kWave) {
+                double xa[2][4], xb[2][4];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int64_t i = i0 + c * kWave;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        xa[c][u] = (va[u] && i < n) ? ra[u][i] : 0.0;
+                        xb[c][u] = (vb[u] && i < n) ? rb[u][i] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] += xa[c][u] * xb[c][v];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int a = 4 * bi + u, b = 4 * bj + v;
+                    if (!(a < b && b < R)) continue;  // wave-uniform
+                    const double val = wave_sum(acc[u][v]) * invn;
+                    if (lane == 0) {
+                        if (a == 0) {
+                            sm.tbeta[b - 1] = val;
+                        } else {
+                            sm.sww[(b - 1) * LW + (a - 1)] = val;
+                            sm.sww[(a - 1) * LW + (b - 1)] = val;
+                        }
+                    }
+                }
+        }
+}
+
 template <int LW>
 __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ Xt, int64_t n, int64_t p,
                                     int64_t k, WaveSm<double, LW> &sm, ColState<double, LW> &st,
@@ -96,10 +166,6 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
     constexpr int NS = ColState<double, LW>::NS;
     const int lane = lane_id();
     const int w = st.w;
-    const int ntri = w * (w - 1) / 2;
-    const int P = ntri + w;
-    const double invn = 1.0 / (double)n;
-    const double *xk = Xt + k * n;
     if (w <= kSmallW) {
         double pr[6];
         gram_rows<4, 4>(Xt, n, p, k, sm, w, pr);
@@ -109,63 +175,7 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
         gram_rows<8, 2>(Xt, n, p, k, sm, w, pr);
         store_gram_rows<8>(sm, w, pr);
     }
-    for (int t0 = w <= kMidW ? P : 0; t0 < P; t0 += 4) {
-        const double *ra[4], *rb[4];
-        int qa[4], qb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int t = t0 + u;
-            qa[u] = -1;
-            qb[u] = -1;
-            ra[u] = xk;
-            rb[u] = xk;
-            if (t < ntri) {
-                // t = qj (qj - 1) / 2 + qi, qi < qj
-                int qj = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
-                while (qj * (qj - 1) / 2 > t) --qj;
-                while ((qj + 1) * qj / 2 <= t) ++qj;
-                int qi = t - qj * (qj - 1) / 2;
-                qa[u] = qi;
-                qb[u] = qj;
-                ra[u] = Xt + clamp_index(sm.widx[qi], p) * n;
-                rb[u] = Xt + clamp_index(sm.widx[qj], p) * n;
-            } else if (t < P) {
-                qa[u] = t - ntri;
-                ra[u] = Xt + clamp_index(sm.widx[t - ntri], p) * n;
-            }
-        }
-        // four 64-sample chunks per step, every load of a step in flight
-        // together (a round trip per 256 samples instead of per 64)
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t i0 = lane; i0 < n; i0 += 4 * kWave) {
-            double xa[4][4], xb[4][4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int64_t i = i0 + c * kWave;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    xa[c][u] = i < n ? ra[u][i] : 0.0;
-                    xb[c][u] = i < n ? rb[u][i] : 0.0;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc[u] += xa[c][u] * xb[c][u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            double v = wave_sum(acc[u]) * invn;
-            if (lane == 0 && qa[u] >= 0) {
-                if (qb[u] >= 0) {
-                    sm.sww[qb[u] * LW + qa[u]] = v;
-                    sm.sww[qa[u] * LW + qb[u]] = v;
-                } else {
-                    sm.tbeta[qa[u]] = v;  // s_W' entry, staged
-                }
-            }
-        }
-    }
+    if (w > kMidW) gram_blocked(Xt, n, p, k, sm, w);
     for (int q = lane; q < w; q += kWave) sm.sww[q * LW + q] = 1.0;
     wave_sync();
 #pragma unroll
