@@ -226,6 +226,51 @@ def bench_batch(args, torch, spmesl, workloads):
     print(json.dumps(line), flush=True)
 
 
+def bench_lasso(args, torch, spmesl, workloads):
+    """The scaled lasso on its own: the regression example of Section 3
+    (n = 250, p = 500, beta = (2 x 5, -1 x 5, 0 x 490)) with 256 responses on
+    one design (noise levels sigma from 1 to 8), one library call per step
+    (double form, tol 1e-8, lambda0 = sqrt(2 log p / n))."""
+    import numpy as np
+    m = 256
+    X_np, Y_np, _ = workloads.sparse_regression(sigmas=np.linspace(1.0, 8.0, m))
+    n, p = X_np.shape
+    lam0 = math.sqrt(2 * math.log(p) / n)
+    X = torch.from_numpy(X_np).to("cuda:0")
+    Y = torch.from_numpy(Y_np).to("cuda:0")
+    ctx = spmesl.Context(0)
+    for _ in range(args.warmup):
+        ctx.scaled_lasso(X, Y, lam0, 1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, outer, st, stats = ctx.scaled_lasso(X, Y, lam0, 1e-8)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000 / args.steps
+    line = {"metric": "scaled lassos/s (Section 3 regression example, 256 responses on one design)",
+            "unit": "lassos/s", "value": round(m * 1000 / ms, 1), "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "lasso_n250_p500_m256", "n": n, "p": p, "responses": m,
+                       "lambda0": round(lam0, 6), "tol": 1e-8},
+            "status": st, "max_sigma_updates": int(outer.max().item()), "stats": stats}
+    if not args.no_cpu:
+        import oracle
+        Xs, _, _ = oracle.standardize(X_np)
+        sample = 16
+        t0 = time.perf_counter()
+        for r in range(0, m, m // sample):
+            ys, _, _ = oracle.standardize(Y_np[:, r:r + 1])
+            oracle.scaled_lasso(Xs, ys[:, 0], lam0, tol=1e-8)
+        sec = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(sample / sec, 1), "unit": "lassos/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"every {m // sample}th of {m} responses (Algorithm 1 in residual form, "
+                                          "one thread)"}
+    print(f"[bench] scaled lasso: {ms:.3f} ms per {m} responses", file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
 def copy_calibration(torch):
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiler run."""
@@ -248,7 +293,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB device to device five times (profiler calibration)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    help="blockar_n400_p5000 (headline), sf_n1000_p20000, or hub_batch64")
+                    help="blockar_n400_p5000 (headline), sf_n1000_p20000, hub_batch64, or "
+                         "lasso_n250_p500_m256 (the scaled lasso on its own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -263,6 +309,8 @@ def main():
 
     if args.workload == "hub_batch64":
         return bench_batch(args, torch, spmesl, workloads)
+    if args.workload == "lasso_n250_p500_m256":
+        return bench_lasso(args, torch, spmesl, workloads)
     w = workloads.workload(args.workload)
     X_np = workloads.generate(args.workload)
     X = torch.from_numpy(X_np).to("cuda:0")

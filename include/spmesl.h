@@ -208,6 +208,34 @@ int spmesl_kernel_times(const spmesl_ctx *ctx, int cap, const char **names, doub
 int spmesl_covariance(spmesl_ctx *ctx, const spmesl_problem *prob, int precision,
                       void *S_out, double *mean, double *scale);
 
+/* The scaled lasso on its own (Section 3.1, Algorithm 1; objective Eq. (1)),
+ * for m responses Y (device, n x m row-major, row stride ldy >= m) on the
+ * design prob->X (n x p, p >= 1).  Each response is treated as SPMESL treats
+ * one of its variables: the columns of X and of Y are centred and scaled to
+ * unit variance, and response r is regressed on the p design columns only
+ * (never on the other responses):
+ *     (beta_r, sigma_r) = argmin_{beta, sigma > 0}
+ *         ||y_r - X beta||^2 / (2 n sigma) + sigma / 2 + lambda0 ||beta||_1
+ * by Algorithm 1 in covariance form from beta = 0, sigma = 1.  Outputs
+ * (device, caller-owned): beta, p x m row-major (column r = beta_r, every
+ * entry written), and sigma[m]; with SPMESL_SCALE_ORIGINAL these are on the
+ * caller's scales (Proposition 1 with the response as column k:
+ * beta_jr * c_j / c_r and sigma_r / c_r, i.e. the coefficients of the raw x_j
+ * for the centred y_r, and the noise level in y_r's units), with
+ * SPMESL_SCALE_STANDARDIZED those of the standardised problem.  outer
+ * (device int[m], or NULL) receives each response's count of sigma updates.
+ * opt: lambda0, tol, the caps and output_scale as for spmesl_solve;
+ * precision must be SPMESL_FP64 (else SPMESL_EINVAL).  stats (host, or NULL)
+ * counts over the m regressions.  Returns after the work is done: SPMESL_OK,
+ * SPMESL_ENOCONV, or an error code as spmesl_solve (SPMESL_EZEROVAR also for
+ * a constant response).  The workspace holds S of the p + m variables. */
+int spmesl_scaled_lasso(spmesl_ctx *ctx, const spmesl_problem *prob, const double *Y,
+                        int64_t m, int64_t ldy, const spmesl_options *opt, double *beta,
+                        double *sigma, int *outer, spmesl_stats *stats);
+/* Workspace (device bytes) spmesl_scaled_lasso needs for n samples, p design
+ * columns and m responses. */
+int spmesl_scaled_lasso_workspace_size(int64_t n, int64_t p, int64_t m, size_t *bytes);
+
 /* Step 4's symmetrisation alone (Eq. (eq:symm)): Omega = symm(Omega1), p x p
  * row-major device arrays; for j < k both entries become the one of smaller
  * magnitude, and on a tie the upper entry Omega1[j*p+k]. */

@@ -357,17 +357,22 @@ static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p
 // The p regressions: first solves (screen + one working-set solve), the
 // escalations, the row-tiled KKT pass over every column, and the re-solves of
 // the columns it flagged.  When one row of S does not fit in LDS the first
-// solves run their own in-wave KKT passes instead.
+// solves run their own in-wave KKT passes instead.  With k0 > 0 only the
+// columns k0 .. p-1 are solved, each on the predictors 0 .. k0-1 (the scaled
+// lassos of responses appended to a design): no screen lists, in-wave KKT
+// passes.
 template <typename T, typename F>
 static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt,
                            double tol, double band, int max_outer, int max_sweeps, int max_rounds,
-                           hipStream_t s, Marker *mk, F &&after_kkt)
+                           hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0)
 {
     const int64_t p = L.p;
-    const int rj = kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
+    const int rj = k0 > 0 ? 0 : kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
     ColArgs<T> a{};
     a.S = (const T *)(ws + L.S);
     a.p = p;
+    a.k0 = k0;
+    a.pv = k0 > 0 ? k0 : p;
     a.lambda0 = (T)opt->lambda0;
     a.tol = (T)tol;
     a.kkt_tol = (T)tol;
@@ -393,7 +398,7 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.flags = &dctl->flags;
     // first solves (their screen lists were written with S)
     a.mode = 0;
-    a.screened = 1;
+    a.screened = k0 > 0 ? 0 : 1;
     a.defer_kkt = rj > 0;
     a.esc_cnt = &dctl->esc_a;
     a.esc_list = (int *)(ws + L.esclist);
@@ -1004,6 +1009,94 @@ int spmesl_covariance(spmesl_ctx *ctx, const spmesl_problem *prob, int precision
     if (ctx->pinned[0].flags & 1) return fail(ctx, SPMESL_ENONFINITE, "X holds a NaN or Inf");
     if (ctx->pinned[0].flags & 2) return fail(ctx, SPMESL_EZEROVAR, "a column of X has zero variance");
     return SPMESL_OK;
+}
+
+// workspace of spmesl_scaled_lasso: the plan of p + m double variables, the
+// packed data [X | Y], and the control block
+static size_t lasso_layout(int64_t n, int64_t pa, Plan *L, size_t *xa_off, size_t *ctl_off)
+{
+    *L = make_plan(n, pa, SPMESL_FP64);
+    *xa_off = align_up(L->total, 256);
+    *ctl_off = align_up(*xa_off + 8 * (size_t)n * (size_t)pa, 256);
+    return *ctl_off + sizeof(Ctl);
+}
+
+int spmesl_scaled_lasso_workspace_size(int64_t n, int64_t p, int64_t m, size_t *bytes)
+{
+    if (!bytes || n < 2 || p < 1 || m < 1 || p > ((int64_t)1 << 30) - m) return SPMESL_EINVAL;
+    Plan L;
+    size_t xa, ctl;
+    *bytes = lasso_layout(n, p + m, &L, &xa, &ctl);
+    return SPMESL_OK;
+}
+
+int spmesl_scaled_lasso(spmesl_ctx *ctx, const spmesl_problem *prob, const double *Y, int64_t m,
+                        int64_t ldy, const spmesl_options *opt, double *beta, double *sigma, int *outer,
+                        spmesl_stats *stats)
+{
+    if (!ctx) return SPMESL_EINVAL;
+    if (!prob || !opt) return fail(ctx, SPMESL_EINVAL, "null problem or options");
+    if (!prob->X || !Y) return fail(ctx, SPMESL_EINVAL, "X or Y is null");
+    if (!beta || !sigma) return fail(ctx, SPMESL_EINVAL, "beta or sigma is null");
+    if (prob->p < 1) return fail(ctx, SPMESL_EINVAL, "p must be >= 1");
+    if (m < 1) return fail(ctx, SPMESL_EINVAL, "m must be >= 1");
+    if (prob->ldx < prob->p) return fail(ctx, SPMESL_EINVAL, "ldx must be >= p");
+    if (ldy < m) return fail(ctx, SPMESL_EINVAL, "ldy must be >= m");
+    if (prob->p > ((int64_t)1 << 30) - m) return fail(ctx, SPMESL_EINVAL, "p + m too large");
+    if (opt->precision != SPMESL_FP64)
+        return fail(ctx, SPMESL_EINVAL, "the scaled lasso entry runs in SPMESL_FP64 only");
+    // the design and the responses as one problem of p + m variables
+    spmesl_problem aug = *prob;
+    aug.p = prob->p + m;
+    aug.ldx = aug.p;
+    int v = validate(ctx, &aug, opt);
+    if (v != SPMESL_OK) return v;
+    DevGuard g(ctx->device);
+    const int64_t n = prob->n, px = prob->p, pa = aug.p;
+    Plan L;
+    size_t xa_off, ctl_off;
+    v = ensure_workspace(ctx, lasso_layout(n, pa, &L, &xa_off, &ctl_off));
+    if (v != SPMESL_OK) return v;
+    v = ensure_pinned(ctx, 1);
+    if (v != SPMESL_OK) return v;
+    char *ws = ctx->ws;
+    Ctl *dctl = (Ctl *)(ws + ctl_off);
+    double *Xa = (double *)(ws + xa_off);
+    double *mean = (double *)(ws + L.mean);
+    double *scale = (double *)(ws + L.scale);
+    hipStream_t s = ctx->stream;
+    const int max_outer = opt->max_outer > 0 ? opt->max_outer : 1000;
+    const int max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 100000;
+    const int max_rounds = opt->max_rounds > 0 ? opt->max_rounds : 64;
+    ctx->nmarks = 0;
+
+    launch_zero_words((uint32_t *)dctl, sizeof(Ctl) / 4, s);
+    launch_pack_columns(prob->X, n, px, prob->ldx, Y, m, ldy, Xa, s);
+    launch_colstats(Xa, n, pa, pa, (double *)(ws + L.partial), L.rchunks, mean, scale, &dctl->flags,
+                    (int *)(ws + L.pendcnt), s);
+    launch_standardize_f64(Xa, n, pa, pa, mean, scale, (double *)(ws + L.xs), s);
+    launch_syrk_f64((const double *)(ws + L.xs), n, pa, (double *)(ws + L.S), Screen{}, s);
+    v = enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s,
+                                nullptr, [] { return (int)SPMESL_OK; }, px);
+    if (v != SPMESL_OK) return v;
+    launch_reduce_stats(m, (const int *)(ws + L.colinfo) + 4 * px, nullptr, (const int *)(ws + L.wcnt) + px,
+                        (const int *)(ws + L.cstat) + px, dctl->counters, &dctl->status1, s);
+    launch_fill_zero(beta, px * m, s);
+    launch_scatter_lasso<double>(px, m, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
+                                 (const double *)(ws + L.wbeta), (const double *)(ws + L.sigma), scale,
+                                 opt->output_scale == SPMESL_SCALE_ORIGINAL, (const int *)(ws + L.colinfo),
+                                 beta, sigma, outer, &dctl->flags, s);
+    HIPTRY(ctx, hipGetLastError());
+    HIPTRY(ctx, hipMemcpyAsync(ctx->pinned, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPTRY(ctx, hipStreamSynchronize(s));
+    const int st = decode(ctx->pinned[0], m, stats);
+    if (stats) stats->nnz_B = -1;
+    if (st == SPMESL_ENONFINITE) ctx->err = "X or Y holds a NaN or Inf";
+    else if (st == SPMESL_EZEROVAR) ctx->err = "a column of X or Y has zero variance";
+    else if (st == SPMESL_EWORKSET) ctx->err = "a working set exceeded SPMESL_MAX_WORKING_SET";
+    else if (st == SPMESL_EDEGENERATE) ctx->err = "a residual variance fell to zero";
+    else if (st == SPMESL_ENOCONV) ctx->err = "an iteration cap was reached";
+    return st;
 }
 
 int spmesl_symmetrize(spmesl_ctx *ctx, int64_t p, const double *Omega1, double *Omega)

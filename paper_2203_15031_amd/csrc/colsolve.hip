@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW)
     __shared__ WaveSm<T, LW> smem[NW];
     const int wv = threadIdx.x / kWave;
     WaveSm<T, LW> &sm = smem[wv];
-    const int64_t nwork = A.mode ? (int64_t)*A.work_cnt : A.p;
+    const int64_t nwork = A.mode ? (int64_t)*A.work_cnt : A.p - A.k0;
     if constexpr (NW > 1) {
         if (A.mode && nwork <= (int64_t)gridDim.x) {
             __shared__ KktCoop coop;
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW)
     }
     const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
     for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
-        const int64_t k = A.mode ? (int64_t)A.work_list[gw] : gw;
+        const int64_t k = A.mode ? (int64_t)A.work_list[gw] : A.k0 + gw;
         solve_column<T, LW, KCH, KU, FIRST>(A, sm, k, tier);
     }
 }
@@ -229,7 +229,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
 
     while (!FIRST && status == kColOk && !deferred) {
         int ns = build_support(sm, st);
-        int npend = kkt_pass<T, T, LW, KCH, KU>(A.S, p, k, sm, st.w, ns, st.lam_used + A.kkt_tol, band,
+        int npend = kkt_pass<T, T, LW, KCH, KU>(A.S, p, A.pv, k, sm, st.w, ns, st.lam_used + A.kkt_tol, band,
                                                 st.lam_used - A.band, A.band_cnt, A.band_idx, part,
                                                 nparts, cp);
         if (npend == 0) break;
@@ -283,12 +283,12 @@ void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
     } else if (tier == 0 && a.defer_kkt && a.screened) {
         // first solves: one column per workgroup, so a column's slot frees as
         // soon as it is done
-        hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, 1, true>), dim3((unsigned)a.p), dim3(kWave), 0, s, a,
-                           0);
+        hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, 1, true>), dim3((unsigned)(a.p - a.k0)), dim3(kWave), 0,
+                           s, a, 0);
     } else if (tier == 0) {
         // first solves with in-wave KKT passes; float: three waves per SIMD
         // to hide the load latency
-        hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, sizeof(T) == 4 ? 3 : 1>), dim3((unsigned)a.p),
+        hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, sizeof(T) == 4 ? 3 : 1>), dim3((unsigned)(a.p - a.k0)),
                            dim3(kWave), 0, s, a, 0);
     } else {
         // one wave per block walking the (short) escalation queue

@@ -154,7 +154,7 @@ struct KktCoop {
 };
 
 template <typename TS, typename T, int LW, int V, int CHV, int UV>
-__device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
+__device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t jend, int64_t k, WaveSm<T, LW> &sm, int w,
                           int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx,
                           int part, int nparts, KktCoop *cp)
 {
@@ -168,7 +168,7 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
     // the block's when the pass is shared)
     int *const plist = cp ? cp->pend[part] : sm.pend;
     int *const blist = cp ? cp->band[part] : band_idx + k * kBandMax;
-    const int64_t nit = (p + STEP - 1) / STEP;
+    const int64_t nit = (jend + STEP - 1) / STEP;
     const int64_t it0 = part * nit / nparts, it1 = (part + 1) * nit / nparts;
     for (int64_t base = it0 * STEP; base < it1 * STEP; base += STEP) {
         T acc[CH][V];
@@ -176,7 +176,7 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
         for (int c = 0; c < CH; ++c) {
             const int64_t j = base + (int64_t)(c * kWave + lane) * V;
             TS x[V];
-            if (j < p) {
+            if (j < jend) {
                 load_group<TS, V>(Sk + j, x);
             } else {
 #pragma unroll
@@ -202,7 +202,7 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int64_t j = base + (int64_t)(c * kWave + lane) * V;
-                    if (j < p) {
+                    if (j < jend) {
                         load_group<TS, V>(rows[u] + j, x[u][c]);
                     } else {
 #pragma unroll
@@ -225,7 +225,7 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
             for (int e = 0; e < V; ++e) {
                 const int64_t j = j0 + e;
                 const T aa = acc[c][e] < T(0) ? -acc[c][e] : acc[c][e];
-                const bool live = j < p && j != k;
+                const bool live = j < jend && j != k;
                 if (live && aa > thr) vm |= 1u << e;
                 if (record_band && live && aa > bthr) bm |= 1u << e;
             }
@@ -307,7 +307,7 @@ __device__ int kkt_pass_v(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm
 // defaults keep the register use of the first solves' kernel; the resume
 // kernel (few columns) takes deeper settings.
 template <typename TS, typename T, int LW, int CH = 4, int U = 2>
-__device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T, LW> &sm, int w,
+__device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t jend, int64_t k, WaveSm<T, LW> &sm, int w,
                         int ns, T thr, bool record_band, T bthr, int *band_cnt, int *band_idx,
                         int part = 0, int nparts = 1, KktCoop *cp = nullptr)
 {
@@ -315,9 +315,9 @@ __device__ int kkt_pass(const TS *__restrict__ S, int64_t p, int64_t k, WaveSm<T
     // rows of S start 16-byte aligned when p is a multiple of V (S itself
     // is 256-byte aligned)
     if (p % V == 0)
-        return kkt_pass_v<TS, T, LW, V, CH, U>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt,
+        return kkt_pass_v<TS, T, LW, V, CH, U>(S, p, jend, k, sm, w, ns, thr, record_band, bthr, band_cnt,
                                               band_idx, part, nparts, cp);
-    return kkt_pass_v<TS, T, LW, 1, CH, U>(S, p, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx,
+    return kkt_pass_v<TS, T, LW, 1, CH, U>(S, p, jend, k, sm, w, ns, thr, record_band, bthr, band_cnt, band_idx,
                                           part, nparts, cp);
 }
 

@@ -134,6 +134,10 @@ __device__ __forceinline__ T soft_threshold(T a, T lam)
 void launch_colstats(const double *X, int64_t n, int64_t p, int64_t ldx, double *partial,
                      int rchunks, double *mean, double *scale, int *flags, int *zero_cnt, hipStream_t s);
 int colstats_rchunks(int64_t n, int64_t p);
+// Xa (n x (p + m), row-major, contiguous) = [X | Y] for the scaled lassos of
+// the m responses Y on the design X.
+void launch_pack_columns(const double *X, int64_t n, int64_t p, int64_t ldx, const double *Y, int64_t m,
+                         int64_t ldy, double *Xa, hipStream_t s);
 
 // Xs = (X - mean) * scale, n x p row-major (ld p), double.
 void launch_standardize_f64(const double *X, int64_t n, int64_t p, int64_t ldx,
@@ -181,6 +185,9 @@ struct ColArgs {
     T band;              // record j off the support with |g| > lambda - band (0: off)
     int max_outer, max_sweeps, max_rounds;
     int mode;            // 0: fresh (screen + solve); 1: resume from the stored state
+    int64_t k0;          // fresh mode: the columns k0 .. p-1 are solved (0: all)
+    int64_t pv;          // candidate variables j < pv (p: all; smaller when the
+                         // last columns are responses only, not predictors)
     int defer_kkt;       // fresh mode: stop after the first solve (the row-tiled pass checks)
     int screened;        // fresh mode: pend_cnt / pend_idx hold the screen (see Screen)
     const int *work_list;// resume mode: columns work_list[0 .. *work_cnt)
@@ -278,5 +285,10 @@ void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const
                             double *B, double *sig_out, double *Omega, const int *flags,
                             hipStream_t s);
 void launch_symmetrize_dense(int64_t p, const double *Om1, double *Om, hipStream_t s);
+template <typename T>
+void launch_scatter_lasso(int64_t k0, int64_t m, const int *w_cnt, const int *w_idx, const T *w_beta,
+                          const double *sigma, const double *scale, int original_scale,
+                          const int *colinfo, double *beta, double *sig_out, int *outer,
+                          const int *flags, hipStream_t s);
 
 } // namespace spmesl

@@ -232,6 +232,57 @@ template void launch_scatter_outputs<float>(int64_t, const int *, const int *, c
                                             const double *, const double *, int, double *,
                                             double *, double *, const int *, hipStream_t);
 
+// The scaled lassos of the response columns k0 .. k0 + m - 1 (design columns
+// 0 .. k0 - 1), one wave per response r: beta (k0 x m row-major, zero-filled
+// beforehand) takes the nonzero coefficients of column k0 + r, with
+// Proposition 1's factor c_j / c_k when `original`, and sigma the noise level
+// sigma_k / c_k (sigma_k when not); outer (may be null) the column's count of
+// sigma updates.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_lasso(int64_t k0, int64_t m, const int *__restrict__ w_cnt,
+                                                       const int *__restrict__ w_idx,
+                                                       const T *__restrict__ w_beta,
+                                                       const double *__restrict__ sigma,
+                                                       const double *__restrict__ scale, int original,
+                                                       const int *__restrict__ colinfo,
+                                                       double *__restrict__ beta,
+                                                       double *__restrict__ sig_out, int *__restrict__ outer,
+                                                       const int *__restrict__ flags)
+{
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= m || *flags) return;
+    const int64_t k = k0 + r;
+    int wk = w_cnt[k];
+    wk = wk < 0 ? 0 : (wk > kWMax ? kWMax : wk);
+    const double ck = original ? scale[k] : 1.0;
+    for (int q = lane; q < wk; q += kWave) {
+        const int j = w_idx[k * kWMax + q];
+        const double b = (double)w_beta[k * kWMax + q];
+        if (b == 0.0 || j < 0 || (int64_t)j >= k0) continue;
+        const double cj = original ? scale[j] : 1.0;
+        beta[(int64_t)j * m + r] = b * (cj / ck);
+    }
+    if (lane == 0) {
+        sig_out[r] = sigma[k] / ck;
+        if (outer) outer[r] = colinfo[k * 4];
+    }
+}
+
+template <typename T>
+void launch_scatter_lasso(int64_t k0, int64_t m, const int *w_cnt, const int *w_idx, const T *w_beta,
+                          const double *sigma, const double *scale, int original_scale,
+                          const int *colinfo, double *beta, double *sig_out, int *outer,
+                          const int *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter_lasso<T>, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, k0, m, w_cnt,
+                       w_idx, w_beta, sigma, scale, original_scale, colinfo, beta, sig_out, outer, flags);
+}
+
+template void launch_scatter_lasso<double>(int64_t, int64_t, const int *, const int *, const double *,
+                                           const double *, const double *, int, const int *, double *,
+                                           double *, int *, const int *, hipStream_t);
+
 // Dense symmetrisation of a given Omega_1 (32 x 32 tiles; the partner tile
 // is read transposed through LDS so both reads are coalesced).
 __global__ __launch_bounds__(256) void k_symmetrize_dense(int64_t p, const double *__restrict__ M,

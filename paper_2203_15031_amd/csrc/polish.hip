@@ -437,7 +437,7 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
         int nsup = build_support(sm, st);
         double margin = A.eps * (1.0 + norm64);
         ++checks;
-        int npend = kkt_pass<float, double, LW>(A.S32, p, k, sm, st.w, nsup, st.lam_used - margin,
+        int npend = kkt_pass<float, double, LW>(A.S32, p, p, k, sm, st.w, nsup, st.lam_used - margin,
                                                false, 0.0, nullptr, nullptr);
         if (npend == 0) break;
         if (rounds >= A.max_rounds) {

@@ -313,4 +313,25 @@ void launch_standardize_split(const double *X, int64_t n, int64_t p, int64_t ldx
                        hi, lo, npad);
 }
 
+__global__ __launch_bounds__(256) void k_pack_columns(const double *__restrict__ X, int64_t n, int64_t p,
+                                                      int64_t ldx, const double *__restrict__ Y, int64_t m,
+                                                      int64_t ldy, double *__restrict__ Xa)
+{
+    const int64_t pa = p + m;
+    const int64_t total = n * pa;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t i = e / pa, j = e - i * pa;
+        Xa[e] = j < p ? X[i * ldx + j] : Y[i * ldy + (j - p)];
+    }
+}
+
+void launch_pack_columns(const double *X, int64_t n, int64_t p, int64_t ldx, const double *Y, int64_t m,
+                         int64_t ldy, double *Xa, hipStream_t s)
+{
+    int64_t blocks = (n * (p + m) + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_pack_columns, dim3((unsigned)blocks), dim3(256), 0, s, X, n, p, ldx, Y, m, ldy, Xa);
+}
+
 } // namespace spmesl

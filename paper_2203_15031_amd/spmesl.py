@@ -106,6 +106,11 @@ def load():
     lib.spmesl_solve_batch.restype = C.c_int
     lib.spmesl_covariance.argtypes = [vp, C.POINTER(Problem), C.c_int, vp, vp, vp]
     lib.spmesl_covariance.restype = C.c_int
+    lib.spmesl_scaled_lasso.argtypes = [vp, C.POINTER(Problem), vp, i64, i64, C.POINTER(Options), vp, vp, vp,
+                                        C.POINTER(Stats)]
+    lib.spmesl_scaled_lasso.restype = C.c_int
+    lib.spmesl_scaled_lasso_workspace_size.argtypes = [i64, i64, i64, C.POINTER(C.c_size_t)]
+    lib.spmesl_scaled_lasso_workspace_size.restype = C.c_int
     lib.spmesl_symmetrize.argtypes = [vp, i64, vp, vp]
     lib.spmesl_symmetrize.restype = C.c_int
     lib.spmesl_kernel_times.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double)]
@@ -346,6 +351,41 @@ class Context:
         if st != OK:
             raise SpmeslError(st, self._err())
         return S, mean, scale
+
+    def scaled_lasso(self, X, Y, lambda0, tol=1e-8, output_scale="original", max_outer=0, max_sweeps=0,
+                     max_rounds=0, check=True):
+        """Scaled lassos of the responses Y (n x m, or n) on the design X (n x p).
+
+        Returns (beta (p x m, or p), sigma (m, or a 0-d tensor), outer
+        (int32, sigma updates per response), status, stats)."""
+        _check_X(X)
+        vec = Y.dim() == 1
+        Y2 = Y.unsqueeze(1) if vec else Y
+        if Y2.dtype != torch.float64 or Y2.device != X.device or Y2.dim() != 2 or Y2.stride(1) != 1:
+            raise ValueError("Y must be a float64 tensor on the device of X, 1-D or 2-D row-major")
+        if Y2.shape[0] != X.shape[0]:
+            raise ValueError("Y must have as many rows as X")
+        n, p = X.shape
+        m = Y2.shape[1]
+        beta = torch.empty((p, m), dtype=torch.float64, device=X.device)
+        sigma = torch.empty((m,), dtype=torch.float64, device=X.device)
+        outer = torch.empty((m,), dtype=torch.int32, device=X.device)
+        opt = self.options(lambda0, tol, "fp64", output_scale, max_outer, max_sweeps, max_rounds)
+        sz = C.c_size_t()
+        st = load().spmesl_scaled_lasso_workspace_size(n, p, m, C.byref(sz))
+        if st != OK:
+            raise SpmeslError(st, "scaled_lasso_workspace_size")
+        self._workspace(sz.value + 4096)
+        self._bind_stream()
+        stats = Stats()
+        prob = self.problem(X)
+        st = load().spmesl_scaled_lasso(self._h, C.byref(prob), _ptr(Y2), m, Y2.stride(0), C.byref(opt),
+                                        _ptr(beta), _ptr(sigma), _ptr(outer), C.byref(stats))
+        if st != OK and (check or st != ENOCONV):
+            raise SpmeslError(st, self._err())
+        if vec:
+            return beta[:, 0], sigma[0], outer[0], st, stats.as_dict()
+        return beta, sigma, outer, st, stats.as_dict()
 
     def kernel_times(self):
         """[(name, ms)] of each launch step of the last solve run with timing=True."""

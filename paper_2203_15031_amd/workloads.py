@@ -38,7 +38,7 @@ __all__ = [
     "Workload", "WORKLOADS", "workload", "generate", "generate_batch",
     "ar_cov", "block_ar_cov", "erdos_renyi_precision", "hub_precision",
     "sample_from_cov", "sample_from_precision", "scale_free_tree_sample",
-    "paper_network", "orthogonal_pairs_design",
+    "paper_network", "orthogonal_pairs_design", "sparse_regression",
 ]
 
 
@@ -329,6 +329,23 @@ def orthogonal_pairs_design(n: int, rs, rng) -> np.ndarray:
 # --------------------------------------------------------------------------
 # the named workloads
 # --------------------------------------------------------------------------
+
+def sparse_regression(n: int = 250, p: int = 500, sigmas=(3.0, 5.0), seed: int = 5):
+    """The regression example of Section 3 (the one behind Fig. 2): y = X beta
+    + sigma eps with beta = (2 x 5, -1 x 5, 0 x (p - 10)), eps ~ N(0, I), one
+    response per noise level sigma, all on one design.  The paper does not
+    say how X is drawn; here its entries are iid N(0, 1).
+
+    Returns X (n x p), Y (n x len(sigmas)) and beta (p)."""
+    rng = _rng(seed)
+    beta = np.zeros(p)
+    beta[:5] = 2.0
+    beta[5:10] = -1.0
+    X = rng.standard_normal((n, p))
+    E = rng.standard_normal((n, len(sigmas)))
+    Y = (X @ beta)[:, None] + E * np.asarray(sigmas, dtype=np.float64)[None, :]
+    return X, np.ascontiguousarray(Y), beta
+
 
 @dataclass(frozen=True)
 class Workload:

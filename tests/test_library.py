@@ -27,7 +27,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("spmesl_create", "spmesl_destroy", "spmesl_solve", "spmesl_solve_batch",
               "spmesl_workspace_size", "spmesl_set_workspace", "spmesl_covariance",
-              "spmesl_symmetrize", "spmesl_lambda_pb"):
+              "spmesl_symmetrize", "spmesl_lambda_pb", "spmesl_scaled_lasso"):
         assert f in names
 
 

@@ -185,6 +185,28 @@ def test_scaled_lasso_y_scale_equivariance():
         assert abs(s2 - abs(a) * s1) < 1e-10 * abs(a)
 
 
+def test_scaled_lasso_sigma_settles_within_ten_updates():
+    # Section 3, the regression example of Fig. 2 (p = 500, n = 250, beta =
+    # (2 x 5, -1 x 5, 0 x 490), sigma = 3 and 5, lambda0 = sqrt(2 log p / n),
+    # start (0, 1)): the sigma iterates of Algorithm 1 settle in fewer than
+    # ten updates.  Read as: the ninth iterate is within 1e-4 of the limit,
+    # and the iterates rise monotonically from 1 towards it.
+    X, Y, _ = W.sparse_regression()
+    n, p = X.shape
+    Xs, _, _ = oracle.standardize(X)
+    lam0 = math.sqrt(2 * math.log(p) / n)
+    for r in range(Y.shape[1]):
+        y = Y[:, r] - Y[:, r].mean()
+        _, s_lim, _, _, st = oracle.scaled_lasso(Xs, y, lam0, tol=1e-12)
+        assert st == 0
+        prev = 1.0
+        for k in range(1, 10):
+            _, s_k, _, _, _ = oracle.scaled_lasso(Xs, y, lam0, tol=1e-12, max_outer=k)
+            assert prev < s_k <= s_lim * (1 + 1e-12)
+            prev = s_k
+        assert abs(prev / s_lim - 1) < 1e-4
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_spmesl_matches_enumeration_original_scale(seed):
     X = tiny_problem(seed)
