@@ -359,8 +359,7 @@ static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p
 // the columns it flagged.  When one row of S does not fit in LDS the first
 // solves run their own in-wave KKT passes instead.  With k0 > 0 only the
 // columns k0 .. p-1 are solved, each on the predictors 0 .. k0-1 (the scaled
-// lassos of responses appended to a design): no screen lists, in-wave KKT
-// passes.
+// lassos of responses appended to a design), with in-wave KKT passes.
 template <typename T, typename F>
 static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt,
                            double tol, double band, int max_outer, int max_sweeps, int max_rounds,
@@ -398,7 +397,7 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.flags = &dctl->flags;
     // first solves (their screen lists were written with S)
     a.mode = 0;
-    a.screened = k0 > 0 ? 0 : 1;
+    a.screened = 1;
     a.defer_kkt = rj > 0;
     a.esc_cnt = &dctl->esc_a;
     a.esc_list = (int *)(ws + L.esclist);
@@ -1075,7 +1074,15 @@ int spmesl_scaled_lasso(spmesl_ctx *ctx, const spmesl_problem *prob, const doubl
     launch_colstats(Xa, n, pa, pa, (double *)(ws + L.partial), L.rchunks, mean, scale, &dctl->flags,
                     (int *)(ws + L.pendcnt), s);
     launch_standardize_f64(Xa, n, pa, pa, mean, scale, (double *)(ws + L.xs), s);
-    launch_syrk_f64((const double *)(ws + L.xs), n, pa, (double *)(ws + L.S), Screen{}, s);
+    // the first working sets from the screen taken with S, as in spmesl_solve,
+    // with the design columns j < p as the only candidates
+    Screen sc;
+    sc.thr64 = kScreenFactor * opt->lambda0 + opt->tol;
+    sc.thr32 = 0.0f;
+    sc.cnt = (int *)(ws + L.pendcnt);
+    sc.idx = (int *)(ws + L.pendidx);
+    sc.pv = px;
+    launch_syrk_f64((const double *)(ws + L.xs), n, pa, (double *)(ws + L.S), sc, s);
     v = enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s,
                                 nullptr, [] { return (int)SPMESL_OK; }, px);
     if (v != SPMESL_OK) return v;

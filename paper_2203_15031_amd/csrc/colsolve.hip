@@ -158,8 +158,12 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
             wave_sync();
             if (writer && lane == 0) A.pend_cnt[k] = 0;
         } else if (nc >= 0) {
-            // the screen taken with S: W = its candidates
-            if (lane < nc) sm.pend[lane] = cfirst;
+            // the screen taken with S: W = its candidates (those that are
+            // predictors: j < pv)
+            const bool keep = lane < nc && cfirst < A.pv;
+            const unsigned long long km = __ballot(keep);
+            if (keep) sm.pend[lanes_below(km)] = cfirst;
+            nc = (int)__popcll(km);
             wave_sync();
             if (writer && lane == 0) A.pend_cnt[k] = 0;
             int np = nc > 0 ? sort_unique_small(sm.pend, nc) : 0;

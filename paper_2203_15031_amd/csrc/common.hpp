@@ -164,10 +164,11 @@ void launch_standardize_split(const double *X, int64_t n, int64_t p, int64_t ldx
 // KKT test at beta = 0) are appended to cnt[k] / idx[k * kPendMax + ...]
 // (cnt counts past kPendMax; cnt zeroed beforehand).  cnt == nullptr: none.
 struct Screen {
-    double thr64;
-    float thr32;
-    int *cnt;
-    int *idx;
+    double thr64 = 0.0;
+    float thr32 = 0.0f;
+    int *cnt = nullptr;
+    int *idx = nullptr;
+    int64_t pv = 0;  // candidates j < pv only (0: all; the bf16-split kernel takes all)
 };
 void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, const Screen &sc, hipStream_t s);
 void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, const Screen &sc, hipStream_t s);

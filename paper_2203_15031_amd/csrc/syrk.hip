@@ -55,10 +55,13 @@ struct ScreenLds {
     int jk[2 * N];
 };
 
+// Entry s_jk = v makes j a candidate of column k when |v| > thr and j < pv
+// (pv: the candidate variables; p for SPMESL).
 template <typename L, typename T>
-__device__ __forceinline__ void screen_entry(L &lst, int *cnt, int *idx, T thr, int64_t j, int64_t k, T v)
+__device__ __forceinline__ void screen_entry(L &lst, int *cnt, int *idx, T thr, int64_t pv, int64_t j, int64_t k,
+                                             T v)
 {
-    const bool hit = cnt && j != k && (v < T(0) ? -v : v) > thr;
+    const bool hit = cnt && j != k && j < pv && (v < T(0) ? -v : v) > thr;
     if (!__ballot(hit)) return;  // the common case: one wave-uniform branch
     if (hit) {
         const int q = atomicAdd(&lst.n, 1);
@@ -209,7 +212,7 @@ constexpr int kSyrkKC = 32;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int64_t n, int64_t p,
-                                                   T *__restrict__ S, int Tt, T invn, T thr,
+                                                   T *__restrict__ S, int Tt, T invn, T thr, int64_t pv,
                                                    int *__restrict__ scnt, int *__restrict__ sidx)
 {
     typedef typename Acc<T>::type AccT;
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
         if (j < p && k < p) {
             const T v = (j == k) ? T(1) : ((diag && rr > cc) ? sm.out[cc][rr] : sm.out[rr][cc]);
             S[j * p + k] = v;
-            screen_entry(scr, scnt, sidx, thr, j, k, v);
+            screen_entry(scr, scnt, sidx, thr, pv, j, k, v);
         }
     }
     if (bj != bk) {
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
             if (j < p && k < p) {
                 const T v = sm.out[cc][rr];
                 S[k * p + j] = v;
-                screen_entry(scr, scnt, sidx, thr, k, j, v);
+                screen_entry(scr, scnt, sidx, thr, pv, k, j, v);
             }
         }
     }
@@ -317,7 +320,7 @@ static void launch_syrk_t(const T *Xs, int64_t n, int64_t p, T *S, T thr, const 
     int Tt = (int)((p + 63) / 64);
     int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
     hipLaunchKernelGGL(k_syrk_mfma<T>, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
-                       (T)(1.0 / (double)n), thr, sc.cnt, sc.idx);
+                       (T)(1.0 / (double)n), thr, sc.pv > 0 ? sc.pv : p, sc.cnt, sc.idx);
 }
 
 void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, const Screen &sc, hipStream_t s)

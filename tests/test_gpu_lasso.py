@@ -136,6 +136,23 @@ def test_many_responses_ragged(ctx, n, p, m, k):
         check(beta[:, r], sig[r], refs[r], lam0, "original")
 
 
+def test_many_responses_sharing_one_signal(ctx):
+    # 96 responses of Section 3's example (sigma from 1 to 8): the responses
+    # correlate strongly with one another, and none may enter another's
+    # working set; every eighth response is checked against the oracle
+    X, Y, _ = W.sparse_regression(sigmas=np.linspace(1.0, 8.0, 96))
+    n, p = X.shape
+    lam0 = math.sqrt(2 * math.log(p) / n)
+    beta, sig, outer, st, stats = ctx.scaled_lasso(gpu(X), gpu(Y), lam0, tol=1e-8)
+    assert st == 0
+    assert stats["max_working_set"] <= 32
+    pick = list(range(0, 96, 8))
+    refs = reference(X, Y[:, pick], lam0)
+    beta, sig = beta.cpu().numpy(), sig.cpu().numpy()
+    for i, r in enumerate(pick):
+        check(beta[:, r], sig[r], refs[i], lam0, "original")
+
+
 def test_wide_working_set_escalates(ctx):
     # 48 strong coefficients: the working set outgrows 32 coordinates and
     # the response is finished by the 128-coordinate tier
