@@ -295,9 +295,16 @@ void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
         hipLaunchKernelGGL((k_colsolve<T, 32, 1, 4, 2, sizeof(T) == 4 ? 3 : 1>), dim3((unsigned)(a.p - a.k0)),
                            dim3(kWave), 0, s, a, 0);
     } else {
-        // one wave per block walking the (short) escalation queue
+        // the (short) escalation queue, one column per block.  Float: two
+        // waves per block share each column's in-wave KKT passes, which
+        // stream (|supp| + 1) rows of S and dominate these columns at large
+        // p (two 128-coordinate working sets fit the LDS of a block; double
+        // ones do not)
         unsigned blocks = (unsigned)(a.p < 256 ? a.p : 256);
-        hipLaunchKernelGGL((k_colsolve<T, kWMax, 1, 4, 2>), dim3(blocks), dim3(kWave), 0, s, a, 1);
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_colsolve<T, kWMax, 2, 4, 2>), dim3(blocks), dim3(kWave * 2), 0, s, a, 1);
+        else
+            hipLaunchKernelGGL((k_colsolve<T, kWMax, 1, 4, 2>), dim3(blocks), dim3(kWave), 0, s, a, 1);
     }
 }
 
