@@ -519,6 +519,8 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     }
     sc.cnt = (int *)(ws + L.pendcnt);  // zeroed by the column statistics
     sc.idx = (int *)(ws + L.pendidx);
+    // the covariance kernel's span starts here, after the fork and phase events
+    mark(mk, s, nullptr);
     if (L.prec == SPMESL_FP64)
         launch_syrk_f64((const double *)(ws + L.xs), n, p, (double *)(ws + L.S), sc, s);
     else if (L.prec == SPMESL_FP32)
