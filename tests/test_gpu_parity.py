@@ -255,12 +255,22 @@ def test_solve_batch_matches_single_solves(ctx):
             one = ctx.solve(Xd, lam, tol=1e-8, precision=prec, eager=True)
             assert torch.equal(r.Omega, one.Omega) and torch.equal(r.B, one.B)
         first = [(r.B.clone(), r.Omega.clone()) for r in res]
-        # the same call again replays the batch's graph into the same outputs
-        for o in outs:
-            o["B"].fill_(7.0)
-            o["Omega"].fill_(7.0)
-        res2 = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec, outs=outs)
-        for (B1, O1), r in zip(first, res2):
+        # the same call again replays the batch's graph (its data sets on
+        # several streams) into the same outputs; three replays with other
+        # work between them, each checked
+        for rep in range(3):
+            for o in outs:
+                o["B"].fill_(7.0)
+                o["Omega"].fill_(7.0)
+            res2 = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec, outs=outs)
+            for (B1, O1), r in zip(first, res2):
+                assert r.status == 0
+                assert torch.equal(r.B, B1) and torch.equal(r.Omega, O1)
+            torch.cuda.synchronize()
+            (Xg[0] * 2.0).sum().item()
+        # kernel by kernel (no graph), on the same streams
+        res3 = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec, eager=True)
+        for (B1, O1), r in zip(first, res3):
             assert r.status == 0
             assert torch.equal(r.B, B1) and torch.equal(r.Omega, O1)
     # and against the oracle on two of them
