@@ -35,7 +35,9 @@ def kernel_costs(n, p, prec):
 
     S = Xs^T Xs / n needs n p (p + 1) flops (the upper triangle, one
     multiply-add per sample and pair); the mixed form issues three bf16
-    products per term, and writes S (4 p^2 bytes).  The mixed form's
+    products per term.  Its bytes are S written once (4 or 8 p^2) and the
+    standardised data read once (the bf16 split: 4 npad p; double 8np,
+    float 4np).  The mixed form's
     standardisation reads X once and writes Xt (double) and the bf16 split
     (8np + 8np + 4 npad p bytes).  The row-tiled KKT pass reads S once; the
     zero fill writes one dense p x p double output.  The column solves and
@@ -45,9 +47,9 @@ def kernel_costs(n, p, prec):
     tsz = 8 if prec == "fp64" else 4
     fl = float(n) * p * (p + 1)
     npad = (n + 63) // 64 * 64
-    syrk = {"fp64": ("syrk_f64", (8.0 * p * p, fl, "fp64")),
-            "fp32": ("syrk_f32", (4.0 * p * p, fl, "fp32")),
-            "mixed": ("syrk_bf16x3", (4.0 * p * p, 3 * fl, "bf16"))}[prec]
+    syrk = {"fp64": ("syrk_f64", (8.0 * p * p + 8.0 * n * p, fl, "fp64")),
+            "fp32": ("syrk_f32", (4.0 * p * p + 4.0 * n * p, fl, "fp32")),
+            "mixed": ("syrk_bf16x3", (4.0 * p * p + 4.0 * npad * p, 3 * fl, "bf16"))}[prec]
     costs = {
         syrk[0]: syrk[1],
         "kkt_rows": (float(tsz) * p * p, 0.0, None),
