@@ -273,6 +273,64 @@ def bench_lasso(args, torch, spmesl, workloads):
     print(json.dumps(line), flush=True)
 
 
+# The paper's Table 2: PCD-GPU seconds per fit (GTX 1080 Ti, double precision
+# through R, lambda0 = sqrt(4 log p / n), mean of 10 data sets), by network,
+# n and p.  Context only: other hardware, the paper's own generators.
+TABLE2_PCD_GPU_S = {
+    ("ar1", 250): (1.9528, 4.4149, 12.0651, 60.1581), ("ar1", 500): (1.7117, 4.2744, 12.8309, 64.4670),
+    ("ar1", 1000): (1.7364, 4.9784, 15.8946, 85.5756),
+    ("ar4", 250): (0.8794, 1.7679, 4.9945, 20.9527), ("ar4", 500): (0.9950, 2.2517, 6.2053, 26.2313),
+    ("ar4", 1000): (1.5552, 4.1366, 12.1282, 57.1606),
+    ("sf", 250): (1.1620, 2.9021, 6.8921, 35.0760), ("sf", 500): (1.1572, 2.9931, 8.3851, 44.9643),
+    ("sf", 1000): (1.2210, 3.6376, 11.1231, 63.4638),
+    ("hub", 250): (2.3266, 6.9508, 11.6372, 35.8963), ("hub", 500): (2.3915, 7.6092, 15.7290, 53.2606),
+    ("hub", 1000): (2.6366, 9.6065, 21.4761, 77.6366),
+}
+TABLE2_P = (500, 1000, 2000, 5000)
+
+
+def bench_table2(args, torch, spmesl, workloads):
+    """The settings of the paper's timing table (Table 2): its four networks
+    (Section 4.1), p in {500, 1000, 2000, 5000}, n in {250, 500, 1000},
+    lambda0 = lambda_ub = sqrt(4 log p / n), one seeded data set per setting
+    (the paper averages ten).  Each fit is one full solve (X resident, B,
+    sigma and Omega written), timed one call at a time (median of --steps
+    calls after --warmup), in both forms, beside the paper's seconds."""
+    import numpy as np
+    ctx = spmesl.Context(0)
+    rows = []
+    for kind in ("ar1", "ar4", "sf", "hub"):
+        for pi, p in enumerate(TABLE2_P):
+            om = workloads.paper_network(kind, p, np.random.default_rng(100 + pi))
+            for n in (250, 500, 1000):
+                X = torch.from_numpy(workloads.sample_from_precision(n, om, np.random.default_rng(n + p))).to(
+                    "cuda:0")
+                lam = spmesl.lambda_ub(n, p)
+                row = {"network": kind, "n": n, "p": p, "lambda0": round(lam, 6),
+                       "paper_pcd_gpu_s": TABLE2_PCD_GPU_S[(kind, n)][pi]}
+                out = dict(B=torch.empty((p, p), dtype=torch.float64, device="cuda:0"),
+                           sigma=torch.empty((p,), dtype=torch.float64, device="cuda:0"),
+                           Omega=torch.empty((p, p), dtype=torch.float64, device="cuda:0"))
+                for prec in ("mixed", "fp64"):
+                    st = 0
+                    for _ in range(args.warmup):
+                        st = ctx.solve(X, lam, 1e-8, prec, out=out, check=False).status
+                    per = []
+                    for _ in range(args.steps):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        st = ctx.solve(X, lam, 1e-8, prec, out=out, check=False).status
+                        per.append((time.perf_counter() - t0) * 1000)
+                    per.sort()
+                    row[f"{prec}_ms"] = round(per[len(per) // 2], 4)
+                    row[f"{prec}_status"] = st
+                rows.append(row)
+                print(f"[bench] table2 {kind} n={n} p={p}: mixed {row['mixed_ms']:.3f} ms, fp64 "
+                      f"{row['fp64_ms']:.3f} ms (paper {row['paper_pcd_gpu_s']} s)", file=sys.stderr, flush=True)
+    print(json.dumps({"table": "paper Table 2 settings", "unit": "ms per fit", "tol": 1e-8,
+                      "timing": "host clock around spmesl_solve, median", "rows": rows}), flush=True)
+
+
 def copy_calibration(torch):
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiler run."""
@@ -292,6 +350,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--table2", action="store_true",
+                    help="time the settings of the paper's timing table (four networks, p up to 5000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB device to device five times (profiler calibration)")
     ap.add_argument("--workload", default=WORKLOAD,
@@ -309,6 +369,8 @@ def main():
         return copy_calibration(torch)
     from paper_2203_15031_amd import spmesl, workloads
 
+    if args.table2:
+        return bench_table2(args, torch, spmesl, workloads)
     if args.workload == "hub_batch64":
         return bench_batch(args, torch, spmesl, workloads)
     if args.workload == "lasso_n250_p500_m256":
