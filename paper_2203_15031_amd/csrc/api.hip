@@ -395,21 +395,27 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.colinfo = (int *)(ws + L.colinfo);
     a.counters = dctl->counters;
     a.flags = &dctl->flags;
-    // first solves (their screen lists were written with S)
+    // first solves (their screen lists were written with S).  With the
+    // row-tiled pass, the columns they hand to the wide tier join the
+    // re-solves' queue: one wide launch after the re-solves finishes both (an
+    // escalated column is final after it, and the row-tiled pass examines
+    // deferred columns only), which saves a launch that usually finds no work.
     a.mode = 0;
     a.screened = 1;
     a.defer_kkt = rj > 0;
-    a.esc_cnt = &dctl->esc_a;
-    a.esc_list = (int *)(ws + L.esclist);
+    a.esc_cnt = rj > 0 ? &dctl->esc_c : &dctl->esc_a;
+    a.esc_list = (int *)(ws + (rj > 0 ? L.esclist2 : L.esclist));
     launch_colsolve(a, 0, s);
     mark(mk, s, "colsolve_first");
-    a.mode = 1;
-    a.screened = 0;
-    a.work_list = (const int *)(ws + L.esclist);
-    a.work_cnt = &dctl->esc_a;
-    launch_colsolve(a, 1, s);
-    mark(mk, s, "colsolve_first_wide");
-    if (rj == 0) return after_kkt();
+    if (rj == 0) {
+        a.mode = 1;
+        a.screened = 0;
+        a.work_list = (const int *)(ws + L.esclist);
+        a.work_cnt = &dctl->esc_a;
+        launch_colsolve(a, 1, s);
+        mark(mk, s, "colsolve_first_wide");
+        return after_kkt();
+    }
     KktArgs<T> k{};
     k.S = a.S;
     k.p = p;
@@ -434,6 +440,8 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     const int v = after_kkt();
     if (v != SPMESL_OK) return v;
     // re-solve the flagged columns
+    a.mode = 1;
+    a.screened = 0;
     a.work_list = (const int *)(ws + L.dirtylist);
     a.work_cnt = &dctl->dirty;
     a.esc_cnt = &dctl->esc_c;
