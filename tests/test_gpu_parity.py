@@ -199,6 +199,28 @@ def test_errors(ctx, sp):
     ctx.solve(gpu(X), 0.3)
 
 
+def test_working_set_overflow_and_degenerate_fit(ctx, sp):
+    # a column that is the sum of 150 others: at lambda0 = 0.03 its lasso
+    # support has 175 coordinates (the oracle's), beyond the 128 a working
+    # set holds; the caps keep every column's work bounded
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((600, 200))
+    X[:, 0] = X[:, 1:151].sum(1) + 0.01 * rng.standard_normal(600)
+    with pytest.raises(sp.SpmeslError) as e:
+        ctx.solve(gpu(X), 0.03, tol=1e-8, precision="fp64", max_outer=50, max_sweeps=5000)
+    assert e.value.code == sp.EWORKSET
+    # an exact linear relation (x0 = x1 + x2): the scaled lasso's noise level
+    # falls to zero (the oracle's sigma is about 1e-9)
+    Y = rng.standard_normal((60, 10))
+    Y[:, 0] = Y[:, 1] + Y[:, 2]
+    with pytest.raises(sp.SpmeslError) as e:
+        ctx.solve(gpu(Y), 0.05, tol=1e-8, precision="fp64", max_outer=200, max_sweeps=20000)
+    assert e.value.code == sp.EDEGENERATE
+    # and the library still works
+    r = ctx.solve(gpu(Y[:, 1:]), 0.05, tol=1e-8, precision="fp64")
+    assert r.status == 0
+
+
 def test_strided_input_and_skipped_outputs(ctx):
     X = W.generate("ar1_n100_p200", n=60, p=40)
     big = np.zeros((60, 57))
