@@ -781,7 +781,8 @@ int spmesl_workspace_size(const spmesl_problem *prob, const spmesl_options *opt,
     if (!bytes) return SPMESL_EINVAL;
     int v = validate(nullptr, prob, opt);
     if (v != SPMESL_OK) return v;
-    *bytes = make_plan(prob->n, prob->p, opt->precision).total;
+    // the plan, then the control block spmesl_solve places after it
+    *bytes = align_up(make_plan(prob->n, prob->p, opt->precision).total, 256) + sizeof(Ctl);
     return SPMESL_OK;
 }
 

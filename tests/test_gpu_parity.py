@@ -199,6 +199,35 @@ def test_errors(ctx, sp):
     ctx.solve(gpu(X), 0.3)
 
 
+def test_caller_workspace_of_the_reported_size(sp):
+    # spmesl_workspace_size reports what a solve needs: a caller workspace of
+    # exactly that size works, one 256 bytes short is refused (SPMESL_ENOMEM)
+    import ctypes as C
+    lib = sp.load()
+    X = gpu(W.generate("ar1_n100_p200", n=50, p=40))
+    c = sp.Context(0)
+    try:
+        for prec in ("fp64", "mixed"):
+            opt = c.options(0.3, 1e-8, prec)
+            need = c.workspace_size(X, opt)
+            buf = torch.empty(need + 256, dtype=torch.uint8, device=DEV)
+            base = buf.data_ptr() + (-buf.data_ptr()) % 256
+            B = torch.empty((40, 40), dtype=torch.float64, device=DEV)
+            res = sp.Result(B.data_ptr(), None, None, None)
+            prob = c.problem(X)
+            c._bind_stream()
+            assert lib.spmesl_set_workspace(c._h, C.c_void_p(base), need - 256) == sp.OK
+            assert lib.spmesl_solve(c._h, C.byref(prob), C.byref(opt), C.byref(res)) == sp.ENOMEM
+            assert lib.spmesl_set_workspace(c._h, C.c_void_p(base), need) == sp.OK
+            assert lib.spmesl_solve(c._h, C.byref(prob), C.byref(opt), C.byref(res)) == sp.OK
+            ref = c.solve(X, 0.3, tol=1e-8, precision=prec, eager=True)
+            torch.cuda.synchronize()
+            assert torch.equal(B, ref.B)
+            assert lib.spmesl_set_workspace(c._h, None, 0) == sp.OK
+    finally:
+        c.close()
+
+
 def test_working_set_overflow_and_degenerate_fit(ctx, sp):
     # a column that is the sum of 150 others: at lambda0 = 0.03 its lasso
     # support has 175 coordinates (the oracle's), beyond the 128 a working
