@@ -6,6 +6,6 @@ the arithmetic lives in ``spmesl_oracle.c`` (plain C, compiled with gcc) and
 this package only builds and calls it.
 """
 from .api import (  # noqa: F401
-    build, lib_path, standardize, scaled_lasso, spmesl, spmesl_columns,
+    build, lib_path, standardize, scaled_lasso, spmesl, spmesl_columns, spmesl_subset,
     symmetrize, lambda_ub, lambda_univ, lambda_pb,
 )

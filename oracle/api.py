@@ -52,6 +52,8 @@ def _setup(lib):
                                           C.c_double, C.c_int, C.c_int, C.c_int64, _lp,
                                           _dp, _dp, _dp, _dp, _ip, _ip, _ip, C.c_int]
     lib.oracle_spmesl_columns.restype = C.c_int
+    lib.oracle_omega_subset.argtypes = [C.c_int64, C.c_int64, _lp, _dp, _dp, _dp, _dp]
+    lib.oracle_omega_subset.restype = None
     for f in ("oracle_lambda_ub", "oracle_lambda_univ"):
         getattr(lib, f).argtypes = [C.c_double, C.c_double]
         getattr(lib, f).restype = C.c_double
@@ -180,6 +182,32 @@ def spmesl_columns(X, lambda0, cols, tol=1e-8, max_outer=1000, max_sweeps=100000
     return dict(B=Bc[:m].T.copy(), sigma=sg[:m].copy(), mean=mean, c=c,
                 n_outer=no[:m].copy(), n_sweeps=ns[:m].copy(), col_status=cs[:m].copy(),
                 status=st)
+
+
+def spmesl_subset(X, lambda0, cols, tol=1e-8, original_scale=False, max_outer=1000,
+                  max_sweeps=1000000, nthreads=0, lib=None):
+    """Algorithm 1 for the listed columns (ascending, distinct) and the
+    symmetrised estimate on the pairs inside the set.
+
+    Returns spmesl_columns' dict (standardised B and sigma of the listed
+    columns) plus Omega_sub (m x m): the block of Omega for the pairs of
+    listed columns, on the data's scale when original_scale."""
+    lib = lib or load()
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    if cols.size > 1 and not np.all(np.diff(cols) > 0):
+        raise ValueError("cols must be ascending and distinct")
+    r = spmesl_columns(X, lambda0, cols, tol=tol, max_outer=max_outer,
+                       max_sweeps=max_sweeps, nthreads=nthreads, lib=lib)
+    p = X.shape[1]
+    m = cols.size
+    Bc = np.ascontiguousarray(r["B"].T)  # (m, p) C-order == column-major (p, m)
+    sg = np.ascontiguousarray(r["sigma"])
+    Om = np.empty((max(m, 1), max(m, 1)))
+    cc = np.ascontiguousarray(r["c"]) if original_scale else None
+    lib.oracle_omega_subset(p, m, cols.ctypes.data_as(_lp), _p(Bc), _p(sg),
+                            _p(cc) if cc is not None else None, Om.ctypes.data_as(_dp))
+    r["Omega_sub"] = Om[:m, :m].T.copy()
+    return r
 
 
 def symmetrize(W, lib=None):

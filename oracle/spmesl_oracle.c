@@ -442,6 +442,32 @@ int oracle_spmesl_columns(int64_t n, int64_t p, const double *X, double lambda0,
     return ret;
 }
 
+/*
+ * Algorithm 2's estimate restricted to a set of response columns.  For
+ * cols[m] (ascending, distinct) with their Algorithm 1 results Bcols [p*m]
+ * (column i = beta_{-cols[i]}, standardised scale) and sigma_cols [m], writes
+ * the m x m principal block of Omega (column-major, Om[a + b*m] = omega of
+ * the pair (cols[a], cols[b])): the diagonal sigma^{-2} first (reading R3),
+ * then omega_jk = -beta_jk sigma_k^{-2} (Eq. (eq:relation)), then the
+ * min-magnitude symmetrisation of Eq. (eq:symm).  An entry of the symmetrised
+ * estimate depends only on the two columns of its pair, so the block equals
+ * that of the full estimate.  c (length p, or NULL) maps the block back to
+ * the data's scale by Proposition 1 (omega^o_jk = c_j c_k omega_jk).
+ */
+void oracle_omega_subset(int64_t p, int64_t m, const int64_t *cols, const double *Bcols,
+                         const double *sigma_cols, const double *c, double *Om)
+{
+    for (int64_t b = 0; b < m; ++b) {
+        const double dk = 1.0 / (sigma_cols[b] * sigma_cols[b]);
+        for (int64_t a = 0; a < m; ++a)
+            Om[a + b * m] = (a == b) ? dk : -Bcols[cols[a] + b * p] * dk;
+    }
+    oracle_symmetrize(m, Om);
+    if (c)
+        for (int64_t b = 0; b < m; ++b)
+            for (int64_t a = 0; a < m; ++a) Om[a + b * m] *= c[cols[a]] * c[cols[b]];
+}
+
 /* ---- penalty levels (Section 2.2) ------------------------------------- */
 
 /* lambda_ub = sqrt(4 log p / n): the union bound over p scaled lassos. */

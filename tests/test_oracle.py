@@ -367,6 +367,26 @@ def test_columns_subset_matches_full():
     np.testing.assert_array_equal(sub["sigma"], full["sigma"][cols])
 
 
+@pytest.mark.parametrize("seed", [0, 3])
+@pytest.mark.parametrize("original", [False, True])
+def test_omega_subset_matches_enumeration(seed, original):
+    # the block of Omega on the pairs of a column subset: pinned by the exact
+    # enumeration (tiny p), and equal bit for bit to the block of the full
+    # estimate on a larger problem
+    X = tiny_problem(seed)
+    lam0 = 0.3
+    _, _, Om = spmesl_enumerate(X, lam0, original_scale=original)
+    cols = np.array([0, 2, 3, 5])
+    sub = oracle.spmesl_subset(X, lam0, cols, tol=1e-13, original_scale=original)
+    np.testing.assert_allclose(sub["Omega_sub"], Om[np.ix_(cols, cols)], rtol=1e-9, atol=1e-10)
+    X2 = W.generate("ar1_n100_p200", n=60, p=40)
+    full = oracle.spmesl(X2, 0.25, tol=1e-10, original_scale=original)
+    cols2 = np.array([1, 2, 3, 17, 30, 31])
+    sub2 = oracle.spmesl_subset(X2, 0.25, cols2, tol=1e-10, original_scale=original)
+    np.testing.assert_array_equal(sub2["Omega_sub"], full["Omega"][np.ix_(cols2, cols2)])
+    assert np.count_nonzero(sub2["Omega_sub"] - np.diag(np.diag(sub2["Omega_sub"]))) > 0
+
+
 # ---------------------------------------------------------------------------
 # the pins catch planted mistakes
 # ---------------------------------------------------------------------------
