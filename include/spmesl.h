@@ -180,6 +180,29 @@ int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob,
 int spmesl_solve_async(spmesl_ctx *ctx, const spmesl_problem *prob,
                        const spmesl_options *opt, spmesl_result *res, int *status_dev);
 
+/* Size of the device array spmesl_solve_noalloc works in (64 MiB). */
+#define SPMESL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * spmesl_solve_async, enqueued kernel by kernel, with every intermediate
+ * buffer in one fixed device array of SPMESL_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU until the process ends.  The call allocates
+ * nothing (no hipMalloc, no pinned host memory, no graph instantiation); the
+ * caller passes X, the outputs and the device int `status_dev`, which
+ * receives the status code when the solve completes on the stream, as for
+ * spmesl_solve_async.  A problem whose workspace (spmesl_workspace_size) does
+ * not fit the array is refused with SPMESL_ENOMEM before anything is
+ * enqueued (64 MiB holds, for example, n = 1024, p = 2048 in every
+ * precision).  Every call on one GPU, from any context, uses that GPU's one
+ * array: calls whose stream work overlaps on the same GPU race and give
+ * undefined results, so order them on one stream (or synchronise between
+ * them).  SPMESL_FLAG_TIMING and SPMESL_FLAG_EAGER are ignored; no stats are
+ * reported.  SPMESL_EHIP if the array's device address could not be found
+ * when the context was created. */
+int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob,
+                         const spmesl_options *opt, spmesl_result *res, int *status_dev);
+
 /* Solve `count` independent problems (uneven n, p) with the same options,
  * except that problem i uses lambda0s[i] when lambda0s (HOST array of count
  * doubles) is not NULL.  status[i] (host) receives each problem's code; the

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -144,6 +145,46 @@ struct DevGuard {
 
 } // namespace
 
+// Device memory of spmesl_solve_noalloc: one array per GPU, part of the
+// library's code object, held until the process ends.  Host code never uses
+// this name as an address (on the host it is only a handle of the symbol):
+// the array's device address is looked up once per device with
+// hipGetSymbolAddress when the first context on that device is created,
+// and kernels receive that address.
+static __device__ __align__(256) unsigned char scratch[SPMESL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Address of `scratch` on `device`, which must be the current device;
+// nullptr (and the HIP error in *err) when it cannot be found.
+char *scratch_address(int device, hipError_t *err)
+{
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ptr = nullptr;
+        }
+        g_scratch_addr[device] = (char *)ptr;
+        g_scratch_err[device] = e;
+        g_scratch_done[device] = true;
+    }
+    *err = g_scratch_err[device];
+    return g_scratch_addr[device];
+}
+} // namespace
+
 struct spmesl_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -177,6 +218,10 @@ struct spmesl_ctx {
     };
     static constexpr size_t kMaxGraphs = 4;
     std::vector<CachedGraph> graphs;  // most recently used first
+    // device address of this device's no-allocation scratch array (nullptr
+    // if the lookup failed; scratch_err then holds the HIP error)
+    char *scratch_dev = nullptr;
+    hipError_t scratch_err = hipSuccess;
     std::string err;
 };
 
@@ -730,6 +775,8 @@ int spmesl_create(spmesl_ctx **out, int device, void *hip_stream)
     bool kok = ok;
     for (int i = 0; i < spmesl_ctx::kMaxMarks && kok; ++i) kok = hipEventCreate(&ctx->kev[i]) == hipSuccess;
     ctx->kev_ok = kok;
+    // the no-allocation entry point's scratch address, with this device current
+    ctx->scratch_dev = scratch_address(device, &ctx->scratch_err);
     if (!ok || ensure_pinned(ctx, 1) != SPMESL_OK) {
         spmesl_destroy(ctx);
         return SPMESL_EHIP;
@@ -898,6 +945,35 @@ int spmesl_solve_async(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl
     key_problem(k, *prob, *res);
     key_options(k, *opt);
     return run_graph(ctx, std::move(k.b), body);
+}
+
+int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
+                         spmesl_result *res, int *status_dev)
+{
+    if (!ctx || !res || !status_dev) return SPMESL_EINVAL;
+    int v = validate(ctx, prob, opt);
+    if (v != SPMESL_OK) return v;
+    if (!ctx->scratch_dev)
+        return fail(ctx, SPMESL_EHIP,
+                    std::string("no device address for the scratch array: ") + hipGetErrorString(ctx->scratch_err));
+    const Plan L = make_plan(prob->n, prob->p, opt->precision);
+    const size_t ctl_off = align_up(L.total, 256);
+    if (ctl_off + sizeof(Ctl) > (size_t)SPMESL_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, SPMESL_ENOMEM,
+                    "this solve needs " + std::to_string(ctl_off + sizeof(Ctl)) +
+                        " bytes of scratch; spmesl_solve_noalloc holds " +
+                        std::to_string((size_t)SPMESL_NOALLOC_SCRATCH_BYTES));
+    DevGuard g(ctx->device);
+    char *base = ctx->scratch_dev;
+    Ctl *dctl = (Ctl *)(base + ctl_off);
+    ctx->nmarks = 0;
+    // kernel by kernel (a graph instantiation may allocate); the control
+    // block is zeroed by the solve's first kernel
+    v = enqueue_solve(ctx, prob, opt, res, L, base, dctl, nullptr);
+    if (v != SPMESL_OK) return v;
+    hipLaunchKernelGGL(k_decode_status, dim3(1), dim3(1), 0, ctx->stream, dctl, status_dev);
+    HIPTRY(ctx, hipGetLastError());
+    return SPMESL_OK;
 }
 
 int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,

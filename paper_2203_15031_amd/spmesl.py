@@ -31,6 +31,7 @@ SCALE_ORIGINAL, SCALE_STANDARDIZED = 0, 1
 FLAG_TIMING = 1
 FLAG_EAGER = 2
 MAX_WORKING_SET = 128
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _PRECISION = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
 _SCALE = {"original": SCALE_ORIGINAL, "standardized": SCALE_STANDARDIZED}
@@ -103,6 +104,8 @@ def load():
                                        C.POINTER(C.c_double), C.POINTER(Result), C.POINTER(C.c_int)]
     lib.spmesl_solve_async.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result), vp]
     lib.spmesl_solve_async.restype = C.c_int
+    lib.spmesl_solve_noalloc.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result), vp]
+    lib.spmesl_solve_noalloc.restype = C.c_int
     lib.spmesl_solve_batch.restype = C.c_int
     lib.spmesl_covariance.argtypes = [vp, C.POINTER(Problem), C.c_int, vp, vp, vp]
     lib.spmesl_covariance.restype = C.c_int
@@ -275,6 +278,29 @@ class Context:
         prob, res, out, _ = self._prepare(X, opt, want, out)
         st = load().spmesl_solve_async(self._h, C.byref(prob), C.byref(opt), C.byref(res),
                                        C.c_void_p(status.data_ptr()))
+        if st != OK:
+            raise SpmeslError(st, self._err())
+        return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), OK, {})
+
+    def solve_noalloc(self, X, lambda0, status, out, tol=1e-8, precision="fp64",
+                      output_scale="original"):
+        """spmesl_solve_noalloc: the solve of solve_async in the library's fixed
+        scratch array (no allocation by the library).  `out` holds the
+        caller's B / sigma / Omega tensors (any may be None); `status` a
+        one-element int32 CUDA tensor that receives the status code."""
+        if status.dtype != torch.int32 or status.device != X.device or status.numel() < 1:
+            raise ValueError("status must be an int32 tensor on the device of X")
+        opt = self.options(lambda0, tol, precision, output_scale)
+        prob = self.problem(X)
+        for name in ("B", "sigma", "Omega"):
+            t = out.get(name)
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or t.device != X.device):
+                raise ValueError(f"{name} must be a contiguous float64 tensor on {X.device}")
+        res = Result(_ptr(out.get("B")).value, _ptr(out.get("sigma")).value,
+                     _ptr(out.get("Omega")).value, None)
+        self._bind_stream()
+        st = load().spmesl_solve_noalloc(self._h, C.byref(prob), C.byref(opt), C.byref(res),
+                                         C.c_void_p(status.data_ptr()))
         if st != OK:
             raise SpmeslError(st, self._err())
         return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), OK, {})
