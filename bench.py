@@ -113,6 +113,53 @@ def roofline_of(name, ms, cost):
             "ms_per_launch": round(ms, 5)}
 
 
+def whole_solve_roofline(n, p, prec, stats, ms):
+    """T_roof / T_measured of one whole solve.
+
+    T_roof sums, over the solve's phases, max(algorithmic bytes / HBM peak,
+    algorithmic flops / matrix-core peak of the phase's precision):
+      standardisation  X read, the standardised copies written
+      covariance       S written once, the standardised data read once;
+                       n p (p + 1) flops (three bf16 products per term in
+                       the mixed form)
+      KKT pass         S read once (the row-tiled pass over every column)
+      active-set sweeps 16 B (float) or 32 B (double) per coordinate per
+                       sweep (read and write of gradient and coefficient),
+                       with the device counters' sweeps times the mean
+                       final working set
+      double polish    (mixed) the rows of the standardised data on each
+                       column's working set plus its own: 8 n (|W| + 1)
+      outputs          B and Omega written dense (16 p^2), sigma (8 p)
+    The in-wave KKT passes of re-solved columns and the scatter of the
+    nonzeros are left out (they only lower T_roof)."""
+    tsz = 8 if prec == "fp64" else 4
+    npad = (n + 63) // 64 * 64
+    mean_w = stats["sum_working_set"] / p
+    fl = float(n) * p * (p + 1)
+    ph = {}
+    if prec == "mixed":
+        ph["standardize"] = (16.0 * n * p + 4.0 * npad * p, 0.0, None)
+        ph["covariance"] = (4.0 * p * p + 4.0 * npad * p, 3 * fl, "bf16")
+    else:
+        ph["standardize"] = (8.0 * n * p + tsz * n * p, 0.0, None)
+        ph["covariance"] = (tsz * p * p + tsz * n * p, fl, "fp64" if prec == "fp64" else "fp32")
+    ph["kkt_pass"] = (float(tsz) * p * p, 0.0, None)
+    ph["active_set_sweeps"] = (2.0 * 2 * tsz * stats["total_sweeps"] * mean_w, 0.0, None)
+    if prec == "mixed":
+        ph["polish"] = (8.0 * n * p * (mean_w + 1.0), 0.0, None)
+    ph["outputs"] = (16.0 * p * p + 8.0 * p, 0.0, None)
+    out, tot, nbytes, nflops = {}, 0.0, 0.0, 0.0
+    for k, (b, f, dt) in ph.items():
+        t = max(b / (PEAK_HBM_GBS * 1e9), f / (PEAK_TFLOPS[dt] * 1e12) if dt else 0.0)
+        out[k] = {"bytes": b, "flops": f, "t_roof_us": round(t * 1e6, 3)}
+        tot += t
+        nbytes += b
+        nflops += f
+    return {"t_roof_ms": round(tot * 1e3, 5), "t_measured_ms": round(ms, 5), "frac": round(tot * 1e3 / ms, 4),
+            "bytes": nbytes, "flops": nflops, "phases": out,
+            "note": "T_measured is the pipelined time per solve; peaks as in roofline"}
+
+
 def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
     p = X.shape[1]
     out = dict(B=torch.empty((p, p), dtype=torch.float64, device=X.device),
@@ -192,6 +239,49 @@ def cpu_baseline(X_np, lam0, tol, target_s=20.0):
             "sample": f"{m} of {p} response columns of the same workload (Algorithm 1 per column, "
                       f"tol {tol:g}), {wall:.2f} s wall on {cores} threads, scaled by p/{m}; "
                       f"Omega assembly excluded"}
+
+
+def cpu_baseline_single_thread(X_np, lam0, tol, target_s=10.0):
+    """The oracle as cpu_baseline, on one host thread."""
+    import numpy as np
+    import oracle
+    n, p = X_np.shape
+    rng = np.random.default_rng(321)
+    probe = rng.choice(p, size=4, replace=False)
+    t0 = time.perf_counter()
+    oracle.spmesl_columns(X_np, lam0, probe, tol=tol, nthreads=1)
+    per_col = (time.perf_counter() - t0) / len(probe)
+    m = int(min(p, max(len(probe), target_s / max(per_col, 1e-6))))
+    cols = rng.choice(p, size=m, replace=False)
+    t0 = time.perf_counter()
+    oracle.spmesl_columns(X_np, lam0, cols, tol=tol, nthreads=1)
+    wall = time.perf_counter() - t0
+    return {"value": round(m / (wall * p), 7), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} of {p} response columns of the same workload (Algorithm 1 per column, "
+                      f"tol {tol:g}), {wall:.2f} s on one thread, scaled by p/{m}; Omega assembly excluded"}
+
+
+def errors_vs_oracle(X_np, lam0, results, m=32):
+    """Per-result error of each form against the oracle's exact minimiser
+    (tol 1e-12) on m sampled response columns: max |B_gpu - B_orc| /
+    max |B_orc| over each sampled column of B, and the relative error of
+    sigma, on the data's scale (Proposition 1 applied to the oracle)."""
+    import numpy as np
+    import oracle
+    p = X_np.shape[1]
+    cols = np.sort(np.random.default_rng(7).choice(p, size=m, replace=False))
+    ref = oracle.spmesl_columns(X_np, lam0, cols, tol=1e-12, nthreads=0)
+    c = ref["c"]
+    Bo = ref["B"] * c[:, None] / c[cols][None, :]
+    so = ref["sigma"] / c[cols]
+    out = {"columns": m, "reference": "oracle, tol 1e-12"}
+    for prec, (B, sig) in results.items():
+        Bc = B[:, cols]
+        eb = max(float(np.abs(Bc[:, i] - Bo[:, i]).max() / np.abs(Bo[:, i]).max()) if np.abs(Bo[:, i]).max() > 0
+                 else float(np.abs(Bc[:, i]).max()) for i in range(m))
+        es = float(np.max(np.abs(sig[cols] - so) / so))
+        out[prec] = {"B_columns": eb, "sigma": es}
+    return out
 
 
 def bench_batch(args, torch, spmesl, workloads):
@@ -382,9 +472,11 @@ def main():
     ctx = spmesl.Context(0)
     forms = args.forms.split(",")
     res = {}
+    outs = {}
     for prec in forms:
         ms, ms_sync, ph, kern, r = time_form(ctx, X, lam0, tol, prec, args.steps, args.warmup, torch)
         res[prec] = (ms, ms_sync, ph, kern, r)
+        outs[prec] = (r.B.cpu().numpy(), r.sigma.cpu().numpy())
         print(f"[bench] {prec}: {ms:.3f} ms/solve pipelined, {ms_sync['median']:.3f} median one call at a time; phases " +
               " ".join(f"{k}={v:.4f}" for k, v in ph.items()), file=sys.stderr, flush=True)
         print(f"[bench] {prec} kernels: " +
@@ -427,10 +519,12 @@ def main():
                    "tol": tol, "precision": head},
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
         "roofline": roof,
+        "whole_solve": whole_solve_roofline(w.n, w.p, head, r.stats, ms),
         "kernels": kernels,
         "stats": {k: r.stats[k] for k in ("total_outer", "max_outer", "total_sweeps",
                                           "total_updates", "total_rounds", "max_working_set",
-                                          "columns_noconv", "polish_kkt_checks", "polish_added")},
+                                          "columns_noconv", "polish_kkt_checks", "polish_added",
+                                          "sum_working_set")},
     }
     for prec in forms[1:]:
         ms2, ms2_sync, ph2, kern2, r2 = res[prec]
@@ -438,9 +532,12 @@ def main():
                       "ms_per_solve_one_call_at_a_time": {k: round(v, 4) for k, v in ms2_sync.items()},
                       "phases_ms": {k: round(v, 4) for k, v in ph2.items()},
                       "kernels_ms": {k: round(v["ms_per_solve"], 5) for k, v in kern2.items()}}
+        line[prec]["whole_solve"] = whole_solve_roofline(w.n, w.p, prec, r2.stats, ms2)
         line["speedup_vs_" + prec] = round(ms2 / ms, 3)
     if not args.no_cpu:
+        line["errors_vs_oracle"] = errors_vs_oracle(X_np, lam0, outs)
         line["cpu_baseline"] = cpu_baseline(X_np, lam0, tol)
+        line["cpu_baseline_single_thread"] = cpu_baseline_single_thread(X_np, lam0, tol)
     print(json.dumps(line), flush=True)
 
 

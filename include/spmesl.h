@@ -96,6 +96,20 @@ typedef struct {
     int64_t n;       /* samples, >= 2 */
     int64_t p;       /* variables, >= 2 */
     int64_t ldx;     /* >= p */
+    /* Optional warm start of Algorithm 1 (NULL: the paper's start, beta = 0
+     * and sigma = 1 for every column).  Device arrays in the scale of the
+     * outputs (options.output_scale), so a result can be passed back in:
+     * B0 is p x p row-major like the output B (column k = the coefficients
+     * of response k; its diagonal is ignored, and at most
+     * SPMESL_MAX_WORKING_SET nonzeros per column are used, the first in row
+     * order), sigma0 has p entries (an entry that is not a positive finite
+     * number starts that column at sigma = 1).  The minimiser is unique, so
+     * a warm start changes the work, not the result: it resumes a solve that
+     * stopped at an iteration cap (SPMESL_ENOCONV), or follows a path of
+     * penalties.  Ignored by spmesl_covariance; spmesl_scaled_lasso refuses
+     * it (SPMESL_EINVAL). */
+    const double *B0;
+    const double *sigma0;
 } spmesl_problem;
 
 typedef struct {
@@ -108,7 +122,8 @@ typedef struct {
     int32_t max_rounds;  /* cap on working-set growth rounds (<= 0: 64) */
     int32_t precision;   /* SPMESL_FP64 | SPMESL_FP32 | SPMESL_MIXED */
     int32_t output_scale;/* SPMESL_SCALE_ORIGINAL | SPMESL_SCALE_STANDARDIZED */
-    int32_t flags;       /* SPMESL_FLAG_TIMING | SPMESL_FLAG_EAGER */
+    int32_t flags;       /* SPMESL_FLAG_TIMING | SPMESL_FLAG_EAGER |
+                            SPMESL_FLAG_FULL_KKT */
 } spmesl_options;
 
 #define SPMESL_FLAG_TIMING 1
@@ -116,6 +131,12 @@ typedef struct {
  * HIP graph of the call (the default for calls that repeat the pointers,
  * sizes and options of the previous call; timed calls are always eager). */
 #define SPMESL_FLAG_EAGER 2
+/* Mixed form: the double polish proves every column by a full pass over S
+ * (every j with |g_j| within the float error bound of lambda joins the
+ * double working set, which is then re-solved), instead of accepting a
+ * column when the change of its gradient since the float solve is provably
+ * smaller than the float near-threshold band.  Slower; the same minimiser. */
+#define SPMESL_FLAG_FULL_KKT 4
 
 typedef struct {
     /* host-side counters filled by a solve */
@@ -130,6 +151,8 @@ typedef struct {
     int64_t columns_noconv;   /* columns that hit a cap */
     int64_t polish_kkt_checks;/* double-precision KKT checks (mixed form) */
     int64_t polish_added;     /* variables the polish added (mixed form) */
+    int64_t sum_working_set;  /* sum over columns of the final working-set
+                                 sizes (in the mixed form, the polish's) */
     /* phase times in milliseconds (only with SPMESL_FLAG_TIMING) */
     double ms_standardize, ms_covariance, ms_solve, ms_polish, ms_output, ms_total;
 } spmesl_stats;

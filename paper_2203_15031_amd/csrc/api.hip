@@ -272,6 +272,8 @@ static void key_problem(KeyBuf &k, const spmesl_problem &pr, const spmesl_result
     k.add(pr.n);
     k.add(pr.p);
     k.add(pr.ldx);
+    k.add(pr.B0);
+    k.add(pr.sigma0);
     k.add(r.B);
     k.add(r.sigma);
     k.add(r.Omega);
@@ -286,6 +288,7 @@ static void key_options(KeyBuf &k, const spmesl_options &o)
     k.add(o.max_rounds);
     k.add(o.precision);
     k.add(o.output_scale);
+    k.add(o.flags & SPMESL_FLAG_FULL_KKT);
 }
 
 // Records the per-launch events of a timed solve; a null Marker records
@@ -408,7 +411,7 @@ static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p
 template <typename T, typename F>
 static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt,
                            double tol, double band, int max_outer, int max_sweeps, int max_rounds,
-                           hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0)
+                           hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0, bool warm = false)
 {
     const int64_t p = L.p;
     const int rj = k0 > 0 ? 0 : kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
@@ -440,6 +443,7 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.colinfo = (int *)(ws + L.colinfo);
     a.counters = dctl->counters;
     a.flags = &dctl->flags;
+    a.warm = warm ? 1 : 0;
     // first solves (their screen lists were written with S).  With the
     // row-tiled pass, the columns they hand to the wide tier join the
     // re-solves' queue: one wide launch after the re-solves finishes both (an
@@ -587,13 +591,27 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
 
     const bool fill = res->B || res->Omega;
     auto fork = [&] { return fill_early ? (int)SPMESL_OK : fork_output_fill(ctx, res, p, s, mk); };
+    // a warm start: the columns' stored state from B0 and sigma0 (in the
+    // scale of the outputs), which the first solves resume from
+    const bool warm = prob->B0 || prob->sigma0;
+    if (warm) {
+        if (L.prec == SPMESL_FP64)
+            launch_warm_start<double>(prob->B0, prob->sigma0, p, scale, original, opt->lambda0,
+                                      (int *)(ws + L.wcnt), (int *)(ws + L.widx), (double *)(ws + L.wbeta),
+                                      (double *)(ws + L.sigma), (double *)(ws + L.lam), (int *)(ws + L.cstat), s);
+        else
+            launch_warm_start<float>(prob->B0, prob->sigma0, p, scale, original, opt->lambda0,
+                                     (int *)(ws + L.wcnt), (int *)(ws + L.widx), (float *)(ws + L.wbeta),
+                                     (double *)(ws + L.sigma), (double *)(ws + L.lam), (int *)(ws + L.cstat), s);
+        mark(mk, s, "warm_start");
+    }
     int vc;
     if (L.prec == SPMESL_FP64)
         vc = enqueue_columns<double>(L, ws, dctl, opt, tol_cols, 0.0, max_outer, max_sweeps, max_rounds, s,
-                                     mk, fork);
+                                     mk, fork, 0, warm);
     else
         vc = enqueue_columns<float>(L, ws, dctl, opt, tol_cols, L.prec == SPMESL_MIXED ? kMixedBand : 0.0,
-                                    max_outer, max_sweeps, max_rounds, s, mk, fork);
+                                    max_outer, max_sweeps, max_rounds, s, mk, fork, 0, warm);
     if (vc != SPMESL_OK) return vc;
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
 
@@ -630,6 +648,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         q.col_status = (int *)(ws + L.cstat64);
         q.polinfo = (int *)(ws + L.polinfo);
         q.flags = &dctl->flags;
+        q.full_kkt = (opt->flags & SPMESL_FLAG_FULL_KKT) ? 1 : 0;
         launch_polish(q, s);
         mark(mk, s, "polish");
     }
@@ -736,6 +755,7 @@ static int decode(const Ctl &c, int64_t p, spmesl_stats *st)
         st->columns_noconv = (int64_t)c.counters[kCntNoconv];
         st->polish_kkt_checks = (int64_t)c.counters[kCntPolishChecks];
         st->polish_added = (int64_t)c.counters[kCntPolishAdded];
+        st->sum_working_set = (int64_t)c.counters[kCntSumW];
     }
     if (c.flags & 1) return SPMESL_ENONFINITE;
     if (c.flags & 2) return SPMESL_EZEROVAR;
@@ -1131,6 +1151,8 @@ int spmesl_scaled_lasso(spmesl_ctx *ctx, const spmesl_problem *prob, const doubl
     if (prob->p > ((int64_t)1 << 30) - m) return fail(ctx, SPMESL_EINVAL, "p + m too large");
     if (opt->precision != SPMESL_FP64)
         return fail(ctx, SPMESL_EINVAL, "the scaled lasso entry runs in SPMESL_FP64 only");
+    if (prob->B0 || prob->sigma0)
+        return fail(ctx, SPMESL_EINVAL, "the scaled lasso entry takes no warm start");
     // the design and the responses as one problem of p + m variables
     spmesl_problem aug = *prob;
     aug.p = prob->p + m;

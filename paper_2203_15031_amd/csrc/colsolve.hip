@@ -93,12 +93,15 @@ __device__ void record_info(const ColArgs<T> &A, int64_t k, const SolveCounts &c
     }
 }
 
+// `unsolved`: the stored state is a warm start no solve has run on yet (the
+// wide kernel then solves it even with no pending candidates)
 template <typename T, int LW>
 __device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const WaveSm<T, LW> &sm,
-                         const ColState<T, LW> &st, int np, const SolveCounts &cnt, int rounds)
+                         const ColState<T, LW> &st, int np, const SolveCounts &cnt, int rounds,
+                         bool unsolved = false)
 {
     const int lane = lane_id();
-    store_column(A, k, sm, st, kColOk, false);
+    store_column(A, k, sm, st, unsolved ? (int)kColWarm : (int)kColOk, false);
     if (lane == 0) record_info(A, k, cnt, rounds);
     for (int i = lane; i < np; i += kWave) A.pend_idx[k * kPendMax + i] = sm.pend[i];
     if (lane == 0) {
@@ -148,10 +151,43 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         // per column) the candidates, in one round of loads
         int nc = A.screened ? A.pend_cnt[k] : -1;
         const int cfirst = A.screened ? A.pend_idx[k * kPendMax + lane] : 0;
+        if (A.warm) {
+            // a warm start: W, beta and sigma from the stored state (the
+            // screen's candidates are merged into W below)
+            const int wc = A.w_cnt[k];
+            if (wc > LW) {
+                // more than this tier holds: the wide kernel resumes the
+                // stored state, with the screen (when its list holds it) as
+                // the pending candidates; its in-wave KKT passes find the rest
+                if (writer && lane == 0) {
+                    if (!(nc >= 0 && nc <= kPendMax)) A.pend_cnt[k] = 0;
+                    A.colinfo[k * 4 + 0] = A.colinfo[k * 4 + 1] = 0;
+                    A.colinfo[k * 4 + 2] = A.colinfo[k * 4 + 3] = 0;
+                    int pos = atomicAdd(A.esc_cnt, 1);
+                    A.esc_list[pos] = (int)k;
+                    atomicAdd(&A.counters[kCntEscalated], 1ull);
+                }
+                return;
+            }
+            for (int q = lane; q < wc; q += kWave) {
+                sm.widx[q] = A.w_idx[k * kWMax + q];
+                sm.wbeta[q] = A.w_beta[k * kWMax + q];
+            }
+            st.w = wc;
+#pragma unroll
+            for (int s = 0; s < ColState<T, LW>::NS; ++s) {
+                int q = s * kWave + lane;
+                st.b[s] = q < wc ? A.w_beta[k * kWMax + q] : T(0);
+            }
+            st.sigma = (T)A.sigma[k];
+            st.lam_used = (T)A.lam_used[k];
+            wave_sync();
+        }
         if (FIRST && !(nc >= 0 && nc <= kPendMax)) {
             // too many candidates for the list: the wide kernel screens in
-            // the wave (resumed from W = {} with no pending candidates)
-            if (writer) escalate(A, k, sm, st, 0, cnt, rounds);
+            // the wave (resumed from W = {}, or the warm start, with no
+            // pending candidates)
+            if (writer) escalate(A, k, sm, st, 0, cnt, rounds, A.warm != 0);
             return;
         } else if (nc > kPendMax) {
             // too many candidates for the list: screen in the wave below
@@ -167,16 +203,16 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
             wave_sync();
             if (writer && lane == 0) A.pend_cnt[k] = 0;
             int np = nc > 0 ? sort_unique_small(sm.pend, nc) : 0;
-            if (np > LW) {
+            if (st.w + np > LW) {
                 if (tier == 0) {
-                    if (writer) escalate(A, k, sm, st, np, cnt, rounds);
+                    if (writer) escalate(A, k, sm, st, np, cnt, rounds, A.warm != 0);
                     return;
                 }
-                np = LW;
+                np = LW - st.w;
             }
-            if (np > 0) {
+            if (np > 0 || st.w > 0) {
                 ++rounds;
-                merge_pending(sm, st, np);
+                if (np > 0) merge_pending(sm, st, np);
                 load_working_set(A.S, p, k, sm, st, rlo, rhi);
                 status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
                 if (A.defer_kkt && status == kColOk) deferred = true;
@@ -201,6 +237,8 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         }
         st.sigma = (T)A.sigma[k];
         st.lam_used = (T)A.lam_used[k];
+        // a warm start handed over unsolved (read with the rest of the state)
+        const bool unsolved = A.warm && A.col_status[k] == kColWarm;
         int np = A.pend_cnt[k];
         np = np < 0 ? 0 : (np > kPendMax ? kPendMax : np);
         for (int i = lane; i < np; i += kWave) sm.pend[i] = A.pend_idx[k * kPendMax + i];
@@ -228,6 +266,9 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
             }
         } else {
             load_working_set(A.S, p, k, sm, st, rlo, rhi);
+            // a warm start handed over unsolved: solve it before the KKT passes
+            if (unsolved)
+                status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         }
     }
 

@@ -32,11 +32,13 @@ enum Counter : int {
     kCntPolishChecks,
     kCntPolishAdded,
     kCntBandOverflow,
+    kCntSumW,
     kNumCounters
 };
 
 // Column status codes written by the kernels (mirror the public codes).
 enum ColStatus : int {
+    kColWarm = 2,       // state set by a warm start, not yet solved
     kColDeferred = 1,   // first solve done, KKT check left to the row-tiled pass
     kColOk = 0,
     kColDegenerate = -4,
@@ -191,6 +193,7 @@ struct ColArgs {
                          // last columns are responses only, not predictors)
     int defer_kkt;       // fresh mode: stop after the first solve (the row-tiled pass checks)
     int screened;        // fresh mode: pend_cnt / pend_idx hold the screen (see Screen)
+    int warm;            // the stored state holds a warm start (launch_warm_start)
     const int *work_list;// resume mode: columns work_list[0 .. *work_cnt)
     const int *work_cnt;
     int *w_cnt;          // [p]
@@ -215,6 +218,19 @@ struct ColArgs {
 // tier: 0 = 32-wide working sets (escalating), 1 = 128-wide
 template <typename T>
 void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s);
+
+// Warm start of the column solves from a caller's B0 (p x p row-major,
+// column k = beta of response k) and sigma0 (p), on the standardised scale or
+// (original != 0) on the data's scale, mapped by Proposition 1 with scale
+// c: b_jk = b0_jk c_k / c_j, sigma_k = sigma0_k c_k.  Writes each column's
+// stored state: the nonzeros of column k of B0 off the diagonal in ascending
+// j (at most kWMax), sigma (1 where sigma0 is null or not a positive finite
+// number), lambda = sigma lambda0, and the status kColWarm.  Either pointer
+// may be null.
+template <typename T>
+void launch_warm_start(const double *B0, const double *sigma0, int64_t p, const double *scale,
+                       int original, double lambda0, int *w_cnt, int *w_idx, T *w_beta, double *sigma,
+                       double *lam_used, int *col_status, hipStream_t s);
 
 // Row-tiled KKT pass over every column: stage rows of S in LDS once, check
 // g_jk = s_jk - sum_l S_jl beta_lk for all (j, k) (see kkt.hip).
@@ -265,6 +281,7 @@ struct PolishArgs {
     int *col_status;
     int *polinfo;           // [p * 8] per column: sigma updates, sweeps, updates, checks, added
     const int *flags;
+    int full_kkt;           // 1: every column takes the full KKT pass (no band bound)
 };
 void launch_polish(const PolishArgs &a, hipStream_t s);
 

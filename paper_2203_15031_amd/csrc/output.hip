@@ -43,8 +43,9 @@ __global__ __launch_bounds__(1024) void k_reduce_stats(int64_t p, const int *__r
 {
     typedef int i4 __attribute__((ext_vector_type(4)));
     constexpr int U = 4;
-    // outer, sweeps, updates, rounds, polish checks, polish added, noconv
-    double sum[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // outer, sweeps, updates, rounds, polish checks, polish added, noconv,
+    // final working-set sizes
+    double sum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int maxw = 0, maxo = 0, bits = 0;
     const int64_t nt = blockDim.x;
     for (int64_t k0 = threadIdx.x; k0 < p; k0 += U * nt) {
@@ -72,22 +73,23 @@ __global__ __launch_bounds__(1024) void k_reduce_stats(int64_t p, const int *__r
             const int o = ci[u].x + pa[u].x;
             maxo = o > maxo ? o : maxo;
             maxw = wc[u] > maxw ? wc[u] : maxw;
+            sum[7] += (double)(wc[u] > 0 ? wc[u] : 0);
             if (cs[u] < 0) {
                 sum[6] += 1.0;
                 bits |= cs[u] == kColWorkset ? 4 : (cs[u] == kColDegenerate ? 2 : 1);
             }
         }
     }
-    __shared__ double red[7][32];
+    __shared__ double red[8][32];
     __shared__ int redi[3][32];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) sum[i] = wave_sum(sum[i]);
+    for (int i = 0; i < 8; ++i) sum[i] = wave_sum(sum[i]);
     // maxima below 2^24 are exact in float
     const int wmaxw = (int)wave_max((float)maxw), wmaxo = (int)wave_max((float)maxo);
     const int wbits = (__ballot(bits & 1) ? 1 : 0) | (__ballot(bits & 2) ? 2 : 0) | (__ballot(bits & 4) ? 4 : 0);
     if (lane == 0) {
-        for (int i = 0; i < 7; ++i) red[i][wv] = sum[i];
+        for (int i = 0; i < 8; ++i) red[i][wv] = sum[i];
         redi[0][wv] = wmaxw;
         redi[1][wv] = wmaxo;
         redi[2][wv] = wbits;
@@ -95,10 +97,10 @@ __global__ __launch_bounds__(1024) void k_reduce_stats(int64_t p, const int *__r
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = (int)(blockDim.x / kWave);
-        double t[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int mw = 0, mo = 0, bb = 0;
         for (int w = 0; w < nw; ++w) {
-            for (int i = 0; i < 7; ++i) t[i] += red[i][w];
+            for (int i = 0; i < 8; ++i) t[i] += red[i][w];
             mw = redi[0][w] > mw ? redi[0][w] : mw;
             mo = redi[1][w] > mo ? redi[1][w] : mo;
             bb |= redi[2][w];
@@ -110,6 +112,7 @@ __global__ __launch_bounds__(1024) void k_reduce_stats(int64_t p, const int *__r
         counters[kCntPolishChecks] = (unsigned long long)t[4];
         counters[kCntPolishAdded] = (unsigned long long)t[5];
         counters[kCntNoconv] = (unsigned long long)t[6];
+        counters[kCntSumW] = (unsigned long long)t[7];
         counters[kCntMaxW] = (unsigned long long)mw;
         counters[kCntMaxOuter] = (unsigned long long)mo;
         *status_bits = bb;

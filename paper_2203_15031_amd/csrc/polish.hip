@@ -335,7 +335,18 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     // --- W' = float support U float band --------------------------------
     w32 = w32 < 0 ? 0 : (w32 > kWMax ? kWMax : w32);
     nb = nb < 0 ? 0 : nb;
-    bool full = nb > kBandMax || (st32 != kColOk && st32 != kColDeferred);
+    bool full = A.full_kkt || nb > kBandMax || (st32 != kColOk && st32 != kColDeferred);
+    if constexpr (LW < kWMax) {
+        // the full pass is the wide kernel's: hand a column that will need it
+        // over at once
+        if (A.full_kkt) {
+            if (lane == 0) {
+                int pos = atomicAdd(A.esc_cnt, 1);
+                A.esc_list[pos] = (int)k;
+            }
+            return;
+        }
+    }
     nb = nb < kBandMax ? nb : kBandMax;
     double norm32 = 0.0;
     int ns = 0;

@@ -30,6 +30,7 @@ FP64, FP32, MIXED = 0, 1, 2
 SCALE_ORIGINAL, SCALE_STANDARDIZED = 0, 1
 FLAG_TIMING = 1
 FLAG_EAGER = 2
+FLAG_FULL_KKT = 4
 MAX_WORKING_SET = 128
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -47,7 +48,8 @@ class SpmeslError(RuntimeError):
 
 
 class Problem(C.Structure):
-    _fields_ = [("X", C.c_void_p), ("n", C.c_int64), ("p", C.c_int64), ("ldx", C.c_int64)]
+    _fields_ = [("X", C.c_void_p), ("n", C.c_int64), ("p", C.c_int64), ("ldx", C.c_int64),
+                ("B0", C.c_void_p), ("sigma0", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -59,7 +61,8 @@ class Options(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in (
         "columns", "total_outer", "max_outer", "total_sweeps", "total_updates", "total_rounds",
-        "max_working_set", "nnz_B", "columns_noconv", "polish_kkt_checks", "polish_added")] + \
+        "max_working_set", "nnz_B", "columns_noconv", "polish_kkt_checks", "polish_added",
+        "sum_working_set")] + \
         [(f, C.c_double) for f in (
             "ms_standardize", "ms_covariance", "ms_solve", "ms_polish", "ms_output", "ms_total")]
 
@@ -225,11 +228,12 @@ class Context:
 
     @staticmethod
     def options(lambda0, tol=1e-8, precision="fp64", output_scale="original", max_outer=0,
-                max_sweeps=0, max_rounds=0, timing=False, eager=False):
+                max_sweeps=0, max_rounds=0, timing=False, eager=False, full_kkt=False):
         return Options(float(lambda0), float(tol), int(max_outer), int(max_sweeps),
                        int(max_rounds), _PRECISION[precision] if isinstance(precision, str) else int(precision),
                        _SCALE[output_scale] if isinstance(output_scale, str) else int(output_scale),
-                       (FLAG_TIMING if timing else 0) | (FLAG_EAGER if eager else 0))
+                       (FLAG_TIMING if timing else 0) | (FLAG_EAGER if eager else 0)
+                       | (FLAG_FULL_KKT if full_kkt else 0))
 
     @staticmethod
     def problem(X):
@@ -248,17 +252,22 @@ class Context:
     # -- entry points -------------------------------------------------------
     def solve(self, X, lambda0, tol=1e-8, precision="fp64", output_scale="original",
               want=("B", "sigma", "Omega"), out=None, max_outer=0, max_sweeps=0, max_rounds=0,
-              timing=False, check=True, eager=False) -> SolveResult:
+              timing=False, check=True, eager=False, full_kkt=False, B0=None, sigma0=None) -> SolveResult:
         """Full SPMESL of X (n x p float64 CUDA tensor).
 
         Returns B (p x p, column k = beta of response k), sigma (p) and the
         symmetrised Omega (p x p).  `out` may hold preallocated output
         tensors.  Raises SpmeslError on any code other than OK and (when
         check is False) ENOCONV.  eager=True enqueues kernel by kernel
-        instead of replaying the context's graph of a repeated call."""
+        instead of replaying the context's graph of a repeated call.
+        full_kkt=True (mixed form) makes the double polish prove every column
+        with a full KKT pass over S.  B0 (p x p) and sigma0 (p), float64 CUDA
+        tensors in the scale of the outputs, warm-start the column solves
+        (either may be None)."""
         opt = self.options(lambda0, tol, precision, output_scale, max_outer, max_sweeps,
-                           max_rounds, timing, eager)
+                           max_rounds, timing, eager, full_kkt)
         prob, res, out, stats = self._prepare(X, opt, want, out)
+        self._warm(prob, X, B0, sigma0)
         st = load().spmesl_solve(self._h, C.byref(prob), C.byref(opt), C.byref(res))
         if st != OK and (check or st != ENOCONV):
             raise SpmeslError(st, self._err())
@@ -304,6 +313,16 @@ class Context:
         if st != OK:
             raise SpmeslError(st, self._err())
         return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), OK, {})
+
+    @staticmethod
+    def _warm(prob, X, B0, sigma0):
+        p = prob.p
+        for name, t, shape in (("B0", B0, (p, p)), ("sigma0", sigma0, (p,))):
+            if t is None:
+                continue
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != X.device or tuple(t.shape) != shape:
+                raise ValueError(f"{name} must be a contiguous float64 tensor of shape {shape} on {X.device}")
+            setattr(prob, name, t.data_ptr())
 
     def _prepare(self, X, opt, want, out):
         prob = self.problem(X)

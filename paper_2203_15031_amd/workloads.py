@@ -38,7 +38,8 @@ __all__ = [
     "Workload", "WORKLOADS", "workload", "generate", "generate_batch",
     "ar_cov", "block_ar_cov", "erdos_renyi_precision", "hub_precision",
     "sample_from_cov", "sample_from_precision", "scale_free_tree_sample",
-    "paper_network", "orthogonal_pairs_design", "sparse_regression",
+    "paper_network", "orthogonal_pairs_design", "exact_covariance_design", "star_band_design",
+    "sparse_regression",
 ]
 
 
@@ -324,6 +325,45 @@ def orthogonal_pairs_design(n: int, rs, rng) -> np.ndarray:
         X[:, 2 * i] = q1 * math.sqrt(n)
         X[:, 2 * i + 1] = (r * q1 + math.sqrt(1 - r * r) * q2) * math.sqrt(n)
     return X
+
+
+def exact_covariance_design(n: int, S: np.ndarray, rng) -> np.ndarray:
+    """X (n x p) with centred columns whose sample covariance X^T X / n is S exactly.
+
+    S must be symmetric positive definite.  X = sqrt(n) Q L^T with S = L L^T
+    and Q an orthonormal basis of n-vectors orthogonal to the all-ones
+    vector (so the columns are centred).  Requires n > p.
+    """
+    p = S.shape[0]
+    if n <= p:
+        raise ValueError("need n > p")
+    Z = rng.standard_normal((n, p))
+    Z -= Z.mean(axis=0, keepdims=True)
+    Q, _ = np.linalg.qr(Z)
+    L = np.linalg.cholesky(S)
+    return math.sqrt(n) * (Q @ L.T)
+
+
+def star_band_design(n: int = 200, arms: int = 40, lambda0: float = 0.15, gap: float = 3e-5,
+                     pairs=(0.6, -0.5, 0.7, 0.4, -0.65), seed: int = 6) -> np.ndarray:
+    """A design whose first variable has `arms` exactly uncorrelated partners,
+    each at sample correlation lambda0 - gap, followed by independent pairs
+    with the given correlations.
+
+    At penalty lambda0 the first column's regression stays at beta = 0 and
+    sigma = 1, with all `arms` gradients |s_j1| = lambda0 - gap just below its
+    threshold.  Requires arms (lambda0 - gap)^2 < 1 (positive definite).
+    """
+    r = lambda0 - gap
+    m = 1 + arms
+    p = m + 2 * len(pairs)
+    S = np.eye(p)
+    S[0, 1:m] = r
+    S[1:m, 0] = r
+    for i, c in enumerate(pairs):
+        a = m + 2 * i
+        S[a, a + 1] = S[a + 1, a] = c
+    return exact_covariance_design(n, S, _rng(seed))
 
 
 # --------------------------------------------------------------------------

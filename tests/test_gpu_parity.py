@@ -1,8 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
 Inputs are the seeded workloads; the oracle runs in its exact mode
-(tol 1e-12) as the reference minimiser.  Full-size workloads are checked on
-sampled columns the oracle computes one by one.
+(tol 1e-12) as the reference minimiser.  The full-size workloads are in
+test_gpu_fullsize.py.
 """
 import math
 
@@ -92,12 +92,12 @@ def test_symmetrize_matches_oracle_with_ties(ctx):
 # full solves against the oracle
 # ---------------------------------------------------------------------------
 
-def _check_full(ctx, X, lam0, prec, bar, tol=1e-8):
+def _check_full(ctx, X, lam0, prec, bar, tol=1e-8, **kw):
     ref = oracle.spmesl(X, lam0, tol=1e-12, original_scale=True)
     ref_std = oracle.spmesl(X, lam0, tol=1e-12, original_scale=False)
     Xg = gpu(X)
-    r = ctx.solve(Xg, lam0, tol=tol, precision=prec)
-    rs = ctx.solve(Xg, lam0, tol=tol, precision=prec, output_scale="standardized")
+    r = ctx.solve(Xg, lam0, tol=tol, precision=prec, **kw)
+    rs = ctx.solve(Xg, lam0, tol=tol, precision=prec, output_scale="standardized", **kw)
     B, sig, Om = host(r.B), host(r.sigma), host(r.Omega)
     errs = dict(B=rel_err(B, ref["B"]), sigma=rel_err(sig, ref["sigma"]), Omega=rel_err(Om, ref["Omega"]))
     assert max(errs.values()) <= bar, errs
@@ -137,6 +137,32 @@ def test_solve_er_n200_p1000_fp64_and_mixed(ctx):
     X = W.generate(w.name)
     _check_full(ctx, X, w.lambda0, "fp64", 1e-6)
     _check_full(ctx, X, w.lambda0, "mixed", 1e-4)
+
+
+def test_mixed_polish_full_pass_on_band_overflow(ctx):
+    # Column 0 of this design has 40 exactly uncorrelated partners whose
+    # gradients sit 3e-5 below its threshold: its float near-threshold band
+    # overflows (more than 32 entries), so the double polish cannot use its
+    # band bound and takes the full KKT pass over S, which adds every
+    # coordinate within its error margin of lambda and re-solves in double:
+    # the band list holds 32 of the 40, the pass adds the other 8, and the
+    # column's double working set ends with all 40.
+    lam0 = 0.15
+    X = W.star_band_design(lambda0=lam0, gap=3e-5)
+    errs, st = _check_full(ctx, X, lam0, "mixed", 1e-4)
+    assert st["polish_kkt_checks"] > 0 and st["polish_added"] >= 8, st
+    assert st["max_working_set"] == 40, st
+
+
+def test_mixed_full_kkt_option(ctx):
+    # SPMESL_FLAG_FULL_KKT: every column's double polish proves its KKT
+    # conditions by the full pass instead of the band bound
+    w = W.workload("er_n200_p1000")
+    X = W.generate(w.name)
+    errs, st = _check_full(ctx, X, w.lambda0, "mixed", 1e-4, full_kkt=True)
+    assert st["polish_kkt_checks"] >= w.p, st
+    base = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision="mixed")
+    assert base.stats["polish_kkt_checks"] < st["polish_kkt_checks"]
 
 
 @pytest.mark.parametrize("n,p,lam", [(23, 67, 0.35), (64, 129, 0.25), (200, 65, 0.2), (5, 2, 0.1)])
@@ -263,34 +289,7 @@ def test_strided_input_and_skipped_outputs(ctx):
 
 
 # ---------------------------------------------------------------------------
-# the p = 5000 workload, sampled columns
-# ---------------------------------------------------------------------------
-
-@pytest.mark.parametrize("prec,bar", [("mixed", 1e-4), ("fp64", 1e-6)])
-def test_blockar_p5000_sampled_columns(ctx, prec, bar):
-    w = W.workload("blockar_n400_p5000")
-    X = W.generate(w.name)
-    r = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision=prec, output_scale="standardized")
-    B = host(r.B)
-    sig = host(r.sigma)
-    rng = np.random.default_rng(0)
-    cols = np.sort(rng.choice(w.p, size=24, replace=False))
-    ref = oracle.spmesl_columns(X, w.lambda0, cols, tol=1e-12, nthreads=0)
-    assert ref["status"] == 0
-    Bref = ref["B"]
-    for i, k in enumerate(cols):
-        assert rel_err(B[:, k], Bref[:, i]) <= bar
-        assert abs(sig[k] - ref["sigma"][i]) <= bar * ref["sigma"][i]
-        nz_ref = np.abs(Bref[:, i]) > bar
-        assert np.all(B[nz_ref, k] != 0)
-    # Omega invariants hold on the whole matrix
-    rO = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision=prec, want=("Omega",))
-    Om = host(rO.Omega)
-    assert np.array_equal(Om, Om.T)
-
-
-# ---------------------------------------------------------------------------
-# batched data sets and the p = 20000 workload
+# batched data sets (the full-size workloads are in test_gpu_fullsize.py)
 # ---------------------------------------------------------------------------
 
 def test_solve_batch_matches_single_solves(ctx):
@@ -329,24 +328,6 @@ def test_solve_batch_matches_single_solves(ctx):
         ref = oracle.spmesl(Xs[i], lams[i], tol=1e-12)
         r = ctx.solve(Xg[i], lams[i], tol=1e-8, precision="mixed")
         assert rel_err(host(r.Omega), ref["Omega"]) <= 1e-4
-
-
-@pytest.mark.parametrize("prec,bar", [("mixed", 1e-4), ("fp64", 1e-6)])
-def test_scale_free_p20000_sampled_columns(ctx, prec, bar):
-    w = W.workload("sf_n1000_p20000")
-    X = W.generate(w.name)
-    r = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision=prec, output_scale="standardized",
-                  want=("B", "sigma"))
-    assert r.status == 0
-    rng = np.random.default_rng(1)
-    cols = np.sort(rng.choice(w.p, size=12, replace=False))
-    ref = oracle.spmesl_columns(X, w.lambda0, cols, tol=1e-12, nthreads=0)
-    assert ref["status"] == 0
-    B = r.B[:, torch.from_numpy(cols).to(DEV)].cpu().numpy()
-    sig = host(r.sigma)[cols]
-    for i in range(len(cols)):
-        assert rel_err(B[:, i], ref["B"][:, i]) <= bar
-        assert abs(sig[i] - ref["sigma"][i]) <= bar * ref["sigma"][i]
 
 
 # ---------------------------------------------------------------------------
@@ -407,3 +388,74 @@ def test_solve_async_status_and_outputs(ctx, sp):
     ctx.solve_async(Xz, lam, status, tol=1e-8, precision="fp64")
     torch.cuda.synchronize()
     assert int(status.item()) == sp.EZEROVAR
+
+
+# ---------------------------------------------------------------------------
+# warm starts (B0, sigma0)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_warm_start_resumes_a_capped_solve(ctx, sp, prec, bar):
+    # a solve stopped after one sigma update per column (SPMESL_ENOCONV)
+    # resumes from its own outputs to the cold result
+    w = W.workload("er_n200_p1000")
+    X = W.generate(w.name)
+    Xg = gpu(X)
+    cold = ctx.solve(Xg, w.lambda0, tol=w.tol, precision=prec)
+    capped = ctx.solve(Xg, w.lambda0, tol=w.tol, precision=prec, max_outer=1, check=False)
+    assert capped.status == sp.ENOCONV
+    warm = ctx.solve(Xg, w.lambda0, tol=w.tol, precision=prec, B0=capped.B.clone(), sigma0=capped.sigma.clone())
+    assert warm.status == 0
+    for t in ("B", "sigma", "Omega"):
+        assert rel_err(host(getattr(warm, t)), host(getattr(cold, t))) <= bar, t
+    ref = oracle.spmesl(X, w.lambda0, tol=1e-12)
+    assert rel_err(host(warm.Omega), ref["Omega"]) <= bar
+    omega_invariants(host(warm.Omega), host(warm.B))
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-6), ("mixed", 1e-4)])
+@pytest.mark.parametrize("scale", ["original", "standardized"])
+def test_warm_start_along_a_penalty_path(ctx, prec, bar, scale):
+    # lambda_ub -> lambda_univ: the second solve starts from the first one's
+    # result and reaches the cold solve at lambda_univ (support checked both
+    # ways against the oracle)
+    from paper_2203_15031_amd import spmesl as sp
+    X = W.generate("blockar_n400_p5000", n=300, p=600)
+    n, p = X.shape
+    lam_hi, lam_lo = sp.lambda_ub(n, p), sp.lambda_univ(n, p)
+    Xg = gpu(X)
+    first = ctx.solve(Xg, lam_hi, tol=1e-8, precision=prec, output_scale=scale)
+    warm = ctx.solve(Xg, lam_lo, tol=1e-8, precision=prec, output_scale=scale, B0=first.B, sigma0=first.sigma)
+    cold = ctx.solve(Xg, lam_lo, tol=1e-8, precision=prec, output_scale=scale)
+    assert warm.status == 0
+    for t in ("B", "sigma", "Omega"):
+        assert rel_err(host(getattr(warm, t)), host(getattr(cold, t))) <= bar, t
+    ref = oracle.spmesl(X, lam_lo, tol=1e-12, original_scale=(scale == "original"))
+    assert rel_err(host(warm.Omega), ref["Omega"]) <= bar
+    if scale == "standardized":
+        mism, excl = support_mismatch(host(warm.B), ref["B"], standardized_cov(X), ref["sigma"], lam_lo, bar)
+        assert mism == 0, (mism, excl)
+
+
+def test_warm_start_from_the_solution_and_wide_columns(ctx):
+    # from its own solution a solve takes one sigma update per column; a
+    # start whose columns hold more than 32 coordinates goes to the wide tier
+    rng = np.random.default_rng(5)
+    n, p = 300, 120
+    X = W.sample_from_cov(n, W.ar_cov(p, 0.9), rng) + 0.3 * rng.standard_normal((n, p))
+    lam = 0.03
+    Xg = gpu(X)
+    cold = ctx.solve(Xg, lam, tol=1e-8, precision="fp64", output_scale="standardized")
+    assert cold.stats["max_working_set"] > 32
+    warm = ctx.solve(Xg, lam, tol=1e-8, precision="fp64", output_scale="standardized",
+                     B0=cold.B, sigma0=cold.sigma)
+    assert warm.status == 0
+    assert warm.stats["total_outer"] < cold.stats["total_outer"]
+    assert rel_err(host(warm.Omega), host(cold.Omega)) <= 1e-6
+    ref = oracle.spmesl(X, lam, tol=1e-12, original_scale=False)
+    assert rel_err(host(warm.B), ref["B"]) <= 1e-6
+    # sigma0 alone (no B0), and a sigma0 with an invalid entry
+    s0 = cold.sigma.clone()
+    s0[3] = -1.0
+    r = ctx.solve(Xg, lam, tol=1e-8, precision="fp64", output_scale="standardized", sigma0=s0)
+    assert r.status == 0 and rel_err(host(r.Omega), host(cold.Omega)) <= 1e-6

@@ -33,3 +33,15 @@ def test_named_workloads_are_seeded_with_their_shapes():
         assert X1.shape == (w.n, w.p)
         assert np.array_equal(X1, X2)
         assert np.all(np.isfinite(X1))
+
+
+def test_exact_covariance_designs():
+    # the designs with a prescribed sample covariance hold it to rounding
+    X = W.star_band_design(n=200, arms=40, lambda0=0.15, gap=3e-5)
+    n, p = X.shape
+    S = X.T @ X / n
+    assert np.abs(X.mean(0)).max() < 1e-12
+    np.testing.assert_allclose(np.diag(S), 1.0, atol=1e-12)
+    np.testing.assert_allclose(S[0, 1:41], 0.15 - 3e-5, atol=1e-12)
+    assert np.abs(S[1:41, 1:41] - np.eye(40)).max() < 1e-12
+    assert abs(S[41, 42] - 0.6) < 1e-12
