@@ -63,10 +63,15 @@ extern "C" {
 #define SPMESL_EHIP (-6)        /* HIP runtime error */
 #define SPMESL_ENOMEM (-7)      /* workspace allocation failed or the caller's
                                    workspace is too small */
-#define SPMESL_EWORKSET (-8)    /* a column's working set exceeded
-                                   SPMESL_MAX_WORKING_SET variables */
+#define SPMESL_EWORKSET (-8)    /* the dense tier ran out of room: the long
+                                   supports of one solve together exceeded
+                                   32p + 65536 entries, or (mixed form) the
+                                   double stage of a group of wide columns
+                                   needed more than 1024 variables */
 
-/* Largest working set (candidate variables of one regression) supported. */
+/* Largest working set one LDS tier holds.  Columns whose working sets grow
+ * beyond it are finished by the dense tier, which has no such bound (the
+ * union of a group's working sets may reach p). */
 #define SPMESL_MAX_WORKING_SET 128
 
 /* ---- enums -------------------------------------------------------------- */
@@ -226,7 +231,9 @@ int spmesl_solve_async(spmesl_ctx *ctx, const spmesl_problem *prob,
 int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob,
                          const spmesl_options *opt, spmesl_result *res, int *status_dev);
 
-/* Solve `count` independent problems (uneven n, p) with the same options,
+/* The batched form (the paper's simulation study solves many independent
+ * data sets per setting: Section 4.1, Tables 1-4).
+ * Solve `count` independent problems (uneven n, p) with the same options,
  * except that problem i uses lambda0s[i] when lambda0s (HOST array of count
  * doubles) is not NULL.  status[i] (host) receives each problem's code; the
  * return value is the first non-OK code, or SPMESL_OK.  The problems run one

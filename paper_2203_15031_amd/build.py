@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspmesl.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["standardize.hip", "syrk.hip", "colsolve.hip", "kkt.hip", "polish.hip", "output.hip", "warm.hip",
+SOURCES = ["standardize.hip", "syrk.hip", "colsolve.hip", "kkt.hip", "polish.hip", "output.hip", "warm.hip", "dense.hip",
            "api.hip", "penalty.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPMESL_ARCH", "gfx950")

@@ -34,6 +34,10 @@ struct Ctl {
     int dirty;        // columns the row-tiled KKT pass flagged
     int esc_c;        // escalations of the flagged columns' re-solves
     int esc_polish;   // escalations of the polish
+    int dense;        // columns handed to the dense tier
+    int dense64;      // columns handed to the dense tier by the polish
+    int pool;         // pool entries taken by the dense tier's results
+    int pool64;
     int pad[1];
 };
 static_assert(sizeof(Ctl) % 4 == 0, "Ctl is zeroed as 32-bit words");
@@ -49,6 +53,10 @@ constexpr double kMixedFloatTol = 3e-5;
 // instead of 5.3 coordinates per first working set; at 0.7 up to 93% of the
 // columns of a scale-free p = 20000 workload would outgrow 32 coordinates.
 constexpr double kScreenFactor = 0.8;
+// Rows per block of the dense tier's delayed update, and the largest V whose
+// S[V, V] the double dense tier of the mixed form keeps (8 MB).
+constexpr int kDenseBlock = 32;
+constexpr int64_t kDenseDataMax = 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -59,6 +67,9 @@ struct Plan {
     size_t wcnt, widx, wbeta, sigma, lam, cstat, esclist, bandcnt, bandidx;
     size_t suppcnt, suppidx, suppval, pendcnt, pendidx, dirtylist, esclist2, colinfo, polinfo;
     size_t wcnt64, widx64, wbeta64, sigma64, lam64, cstat64, esclist64;
+    // the dense tier: queues, result offsets into the pools, workspace
+    size_t dq, dq64, woff, woff64, dmark, dv, dvold, dr, dbd, dbp, dsk, dsvv, de;
+    int64_t pool_cap = 0, svv_cap = 0;
     size_t total = 0;
 };
 
@@ -95,9 +106,23 @@ Plan make_plan(int64_t n, int64_t p, int prec)
         L.lo = b.take(2 * (size_t)L.npad * P);
     }
     L.S = b.take(tsz * P * P);
+    // per-column lists hold kWMax entries each; the dense tier's longer
+    // results go to a pool after them
+    L.pool_cap = std::min<int64_t>(p * p, 32 * p + 65536);
+    const size_t lists = P * kWMax + (size_t)L.pool_cap;
     L.wcnt = b.take(4 * P);
-    L.widx = b.take(4 * P * kWMax);
-    L.wbeta = b.take(tsz * P * kWMax);
+    L.widx = b.take(4 * lists);
+    L.wbeta = b.take(tsz * lists);
+    L.woff = b.take(4 * P);
+    L.dq = b.take(4 * P);
+    L.dmark = b.take(4 * P);
+    L.dv = b.take(4 * P);
+    L.dvold = b.take(4 * P);
+    L.dr = b.take(8 * 16 * P);
+    L.dbd = b.take(8 * 16 * P);
+    L.dbp = b.take(8 * 16 * P);
+    L.dsk = b.take(8 * 16 * P);
+    L.dq64 = L.woff64 = L.dsvv = L.de = 0;
     L.sigma = b.take(8 * P);
     L.lam = b.take(8 * P);
     L.cstat = b.take(4 * P);
@@ -117,8 +142,14 @@ Plan make_plan(int64_t n, int64_t p, int prec)
         L.bandcnt = b.take(4 * P);
         L.bandidx = b.take(4 * P * kBandMax);
         L.wcnt64 = b.take(4 * P);
-        L.widx64 = b.take(4 * P * kWMax);
-        L.wbeta64 = b.take(8 * P * kWMax);
+        L.widx64 = b.take(4 * lists);
+        L.wbeta64 = b.take(8 * lists);
+        L.woff64 = b.take(4 * P);
+        L.dq64 = b.take(4 * P);
+        // S[V, V] of the double dense tier (formed from the data)
+        L.svv_cap = p < kDenseDataMax ? p : kDenseDataMax;
+        L.dsvv = b.take(8 * (size_t)L.svv_cap * (size_t)L.svv_cap);
+        L.de = b.take(8 * 16 * N);
         L.sigma64 = b.take(8 * P);
         L.lam64 = b.take(8 * P);
         L.cstat64 = b.take(4 * P);
@@ -402,6 +433,59 @@ static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p
     return SPMESL_OK;
 }
 
+// The dense tier (dense.hip) for the columns the 128-coordinate tier handed
+// over, reading S and writing the columns' results in place.
+template <typename T>
+static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &a, hipStream_t s, Marker *mk)
+{
+    DenseArgs<T> d{};
+    d.S = a.S;
+    d.Xt = nullptr;
+    d.n = L.n;
+    d.p = L.p;
+    d.pv = a.pv;
+    d.lambda0 = a.lambda0;
+    d.tol = a.tol;
+    d.kkt_tol = a.kkt_tol;
+    d.max_outer = a.max_outer;
+    d.max_sweeps = a.max_sweeps;
+    d.max_rounds = a.max_rounds;
+    d.block = kDenseBlock;
+    d.queue = a.dense_list;
+    d.qcnt = a.dense_cnt;
+    d.w_cnt = a.w_cnt;
+    d.w_idx = a.w_idx;
+    d.w_beta = a.w_beta;
+    d.w_off = (int *)(ws + L.woff);
+    d.sigma = a.sigma;
+    d.lam_used = a.lam_used;
+    d.col_status = a.col_status;
+    d.pool_cnt = &dctl->pool;
+    d.pool_cap = L.pool_cap;
+    d.band_cnt = a.band_cnt;
+    d.info = a.colinfo;
+    d.info_stride = 4;
+    d.mark = (int *)(ws + L.dmark);
+    d.V = (int *)(ws + L.dv);
+    d.Vold = (int *)(ws + L.dvold);
+    d.R = (T *)(ws + L.dr);
+    d.Bd = (T *)(ws + L.dbd);
+    d.Bp = (T *)(ws + L.dbp);
+    d.sk = (T *)(ws + L.dsk);
+    d.counters = a.counters;
+    d.flags = a.flags;
+    DenseSrc<T> src{};
+    src.cnt = a.w_cnt;
+    src.idx = a.w_idx;
+    src.beta = a.w_beta;
+    src.off = d.w_off;
+    src.sigma = a.sigma;
+    src.pend_cnt = a.pend_cnt;
+    src.pend_idx = a.pend_idx;
+    launch_dense<T, T>(d, src, s);
+    mark(mk, s, "dense");
+}
+
 // The p regressions: first solves (screen + one working-set solve), the
 // escalations, the row-tiled KKT pass over every column, and the re-solves of
 // the columns it flagged.  When one row of S does not fit in LDS the first
@@ -444,6 +528,8 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.counters = dctl->counters;
     a.flags = &dctl->flags;
     a.warm = warm ? 1 : 0;
+    a.dense_cnt = &dctl->dense;
+    a.dense_list = (int *)(ws + L.dq);
     // first solves (their screen lists were written with S).  With the
     // row-tiled pass, the columns they hand to the wide tier join the
     // re-solves' queue: one wide launch after the re-solves finishes both (an
@@ -463,6 +549,7 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
         a.work_cnt = &dctl->esc_a;
         launch_colsolve(a, 1, s);
         mark(mk, s, "colsolve_first_wide");
+        enqueue_dense<T>(L, ws, dctl, a, s, mk);
         return after_kkt();
     }
     KktArgs<T> k{};
@@ -501,6 +588,7 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.work_cnt = &dctl->esc_c;
     launch_colsolve(a, 1, s);
     mark(mk, s, "colsolve_resume_wide");
+    enqueue_dense<T>(L, ws, dctl, a, s, mk);
     return SPMESL_OK;
 }
 
@@ -649,8 +737,60 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         q.polinfo = (int *)(ws + L.polinfo);
         q.flags = &dctl->flags;
         q.full_kkt = (opt->flags & SPMESL_FLAG_FULL_KKT) ? 1 : 0;
+        q.dense_cnt = &dctl->dense64;
+        q.dense_list = (int *)(ws + L.dq64);
         launch_polish(q, s);
         mark(mk, s, "polish");
+        // the columns whose double working sets outgrow the polish's: the
+        // dense tier in double, from the float solution, with S[V, V] and the
+        // gradients taken from the standardised data
+        DenseArgs<double> d{};
+        d.S = nullptr;
+        d.Xt = q.Xt;
+        d.n = n;
+        d.p = p;
+        d.pv = p;
+        d.lambda0 = opt->lambda0;
+        d.tol = opt->tol;
+        d.kkt_tol = opt->tol;
+        d.max_outer = max_outer;
+        d.max_sweeps = max_sweeps;
+        d.max_rounds = max_rounds;
+        d.block = kDenseBlock;
+        d.queue = q.dense_list;
+        d.qcnt = q.dense_cnt;
+        d.w_cnt = q.w_cnt;
+        d.w_idx = q.w_idx;
+        d.w_beta = q.w_beta;
+        d.w_off = (int *)(ws + L.woff64);
+        d.sigma = q.sigma;
+        d.lam_used = q.lam_used;
+        d.col_status = q.col_status;
+        d.pool_cnt = &dctl->pool64;
+        d.pool_cap = L.pool_cap;
+        d.band_cnt = nullptr;
+        d.info = q.polinfo;
+        d.info_stride = 8;
+        d.mark = (int *)(ws + L.dmark);
+        d.V = (int *)(ws + L.dv);
+        d.Vold = (int *)(ws + L.dvold);
+        d.R = (double *)(ws + L.dr);
+        d.Bd = (double *)(ws + L.dbd);
+        d.Bp = (double *)(ws + L.dbp);
+        d.sk = (double *)(ws + L.dsk);
+        d.Svv = (double *)(ws + L.dsvv);
+        d.svv_cap = L.svv_cap;
+        d.E = (double *)(ws + L.de);
+        d.counters = dctl->counters;
+        d.flags = &dctl->flags;
+        DenseSrc<float> src{};
+        src.cnt = q.w_cnt32;
+        src.idx = q.w_idx32;
+        src.beta = q.w_beta32;
+        src.off = (const int *)(ws + L.woff);
+        src.sigma = q.sigma32;
+        launch_dense<double, float>(d, src, s);
+        mark(mk, s, "dense_polish");
     }
     {
         // the statistics reduction reads only the column results: it runs on
@@ -674,17 +814,17 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     mark(mk, s, "wait_fill");
     if (L.prec == SPMESL_FP64)
         launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
-                                       (const double *)(ws + L.wbeta), (const double *)(ws + L.sigma),
+                                       (const double *)(ws + L.wbeta), (const int *)(ws + L.woff), (const double *)(ws + L.sigma),
                                        scale, original, res->B, res->sigma, res->Omega,
                                        &dctl->flags, s);
     else if (L.prec == SPMESL_FP32)
         launch_scatter_outputs<float>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
-                                      (const float *)(ws + L.wbeta), (const double *)(ws + L.sigma),
+                                      (const float *)(ws + L.wbeta), (const int *)(ws + L.woff), (const double *)(ws + L.sigma),
                                       scale, original, res->B, res->sigma, res->Omega,
                                        &dctl->flags, s);
     else
         launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt64), (const int *)(ws + L.widx64),
-                                       (const double *)(ws + L.wbeta64),
+                                       (const double *)(ws + L.wbeta64), (const int *)(ws + L.woff64),
                                        (const double *)(ws + L.sigma64), scale, original, res->B,
                                        res->sigma, res->Omega, &dctl->flags, s);
     mark(mk, s, "scatter");
@@ -931,7 +1071,7 @@ int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_optio
     }
     if (st == SPMESL_ENONFINITE) ctx->err = "X holds a NaN or Inf";
     else if (st == SPMESL_EZEROVAR) ctx->err = "a column of X has zero variance";
-    else if (st == SPMESL_EWORKSET) ctx->err = "a working set exceeded SPMESL_MAX_WORKING_SET";
+    else if (st == SPMESL_EWORKSET) ctx->err = "the dense tier ran out of room for the long working sets";
     else if (st == SPMESL_EDEGENERATE) ctx->err = "a residual variance fell to zero";
     else if (st == SPMESL_ENOCONV) ctx->err = "an iteration cap was reached";
     return st;
@@ -1199,7 +1339,8 @@ int spmesl_scaled_lasso(spmesl_ctx *ctx, const spmesl_problem *prob, const doubl
                         (const int *)(ws + L.cstat) + px, dctl->counters, &dctl->status1, s);
     launch_fill_zero(beta, px * m, s);
     launch_scatter_lasso<double>(px, m, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
-                                 (const double *)(ws + L.wbeta), (const double *)(ws + L.sigma), scale,
+                                 (const double *)(ws + L.wbeta), (const int *)(ws + L.woff),
+                                 (const double *)(ws + L.sigma), scale,
                                  opt->output_scale == SPMESL_SCALE_ORIGINAL, (const int *)(ws + L.colinfo),
                                  beta, sigma, outer, &dctl->flags, s);
     HIPTRY(ctx, hipGetLastError());
@@ -1209,7 +1350,7 @@ int spmesl_scaled_lasso(spmesl_ctx *ctx, const spmesl_problem *prob, const doubl
     if (stats) stats->nnz_B = -1;
     if (st == SPMESL_ENONFINITE) ctx->err = "X or Y holds a NaN or Inf";
     else if (st == SPMESL_EZEROVAR) ctx->err = "a column of X or Y has zero variance";
-    else if (st == SPMESL_EWORKSET) ctx->err = "a working set exceeded SPMESL_MAX_WORKING_SET";
+    else if (st == SPMESL_EWORKSET) ctx->err = "the dense tier ran out of room for the long working sets";
     else if (st == SPMESL_EDEGENERATE) ctx->err = "a residual variance fell to zero";
     else if (st == SPMESL_ENOCONV) ctx->err = "an iteration cap was reached";
     return st;

@@ -32,8 +32,8 @@
 //            their violators from the pending list, re-solve, and finish with
 //            in-wave KKT passes (rows of S streamed per column).
 // Two tiers: 32-coordinate working sets (four columns per workgroup) and
-// 128-coordinate ones (one per workgroup).  Beyond 128 the column reports
-// SPMESL_EWORKSET.
+// 128-coordinate ones (one per workgroup).  Beyond 128 the column goes to
+// the dense tier (dense.hip), which has no bound on the working set.
 #include "colsolve_dev.hpp"
 
 namespace spmesl {
@@ -93,6 +93,9 @@ __device__ void record_info(const ColArgs<T> &A, int64_t k, const SolveCounts &c
     }
 }
 
+// Hand column k to the next tier: its state (W, beta, sigma) and its np
+// pending candidates are stored, and k joins the 128-coordinate tier's queue
+// (from the 32-coordinate tier) or the dense tier's (from the 128 one).
 // `unsolved`: the stored state is a warm start no solve has run on yet (the
 // wide kernel then solves it even with no pending candidates)
 template <typename T, int LW>
@@ -101,13 +104,14 @@ __device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const W
                          bool unsolved = false)
 {
     const int lane = lane_id();
+    const bool dense = LW >= kWMax;
     store_column(A, k, sm, st, unsolved ? (int)kColWarm : (int)kColOk, false);
     if (lane == 0) record_info(A, k, cnt, rounds);
     for (int i = lane; i < np; i += kWave) A.pend_idx[k * kPendMax + i] = sm.pend[i];
     if (lane == 0) {
         A.pend_cnt[k] = np;
-        int pos = atomicAdd(A.esc_cnt, 1);
-        A.esc_list[pos] = (int)k;
+        int pos = atomicAdd(dense ? A.dense_cnt : A.esc_cnt, 1);
+        (dense ? A.dense_list : A.esc_list)[pos] = (int)k;
         atomicAdd(&A.counters[kCntEscalated], 1ull);
     }
 }
@@ -204,11 +208,8 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
             if (writer && lane == 0) A.pend_cnt[k] = 0;
             int np = nc > 0 ? sort_unique_small(sm.pend, nc) : 0;
             if (st.w + np > LW) {
-                if (tier == 0) {
-                    if (writer) escalate(A, k, sm, st, np, cnt, rounds, A.warm != 0);
-                    return;
-                }
-                np = LW - st.w;
+                if (writer) escalate(A, k, sm, st, np, cnt, rounds, A.warm != 0);
+                return;
             }
             if (np > 0 || st.w > 0) {
                 ++rounds;
@@ -250,20 +251,13 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         if (np > 0) {
             np = sort_unique_small(sm.pend, np);
             if (st.w + np > LW) {
-                if (tier == 0) {
-                    if (writer) escalate(A, k, sm, st, np, cnt, rounds);
-                    return;
-                }
-                np = LW - st.w;
+                if (writer) escalate(A, k, sm, st, np, cnt, rounds, unsolved);
+                return;
             }
-            if (np > 0) {
-                ++rounds;
-                merge_pending(sm, st, np);
-                load_working_set(A.S, p, k, sm, st, rlo, rhi);
-                status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
-            } else {
-                status = kColWorkset;
-            }
+            ++rounds;
+            merge_pending(sm, st, np);
+            load_working_set(A.S, p, k, sm, st, rlo, rhi);
+            status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         } else {
             load_working_set(A.S, p, k, sm, st, rlo, rhi);
             // a warm start handed over unsolved: solve it before the KKT passes
@@ -284,15 +278,8 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         }
         int np = npend < kPendMax ? npend : kPendMax;
         if (st.w + np > LW) {
-            if (tier == 0) {
-                if (writer) escalate(A, k, sm, st, np, cnt, rounds);
-                return;
-            }
-            np = LW - st.w;
-            if (np <= 0) {
-                status = kColWorkset;
-                break;
-            }
+            if (writer) escalate(A, k, sm, st, np, cnt, rounds);
+            return;
         }
         ++rounds;
         merge_pending(sm, st, np);

@@ -33,6 +33,7 @@ enum Counter : int {
     kCntPolishAdded,
     kCntBandOverflow,
     kCntSumW,
+    kCntDense,
     kNumCounters
 };
 
@@ -117,6 +118,14 @@ template <typename T>
 __device__ __forceinline__ T wave_max(T v)
 {
     return wave_reduce(v, -__builtin_huge_valf(), [](T a, T b) { return b > a ? b : a; });
+}
+
+// Start of column k's list of `cnt` entries in the per-column list arrays:
+// slot k * kWMax, or (more than kWMax entries, from the dense tier) the pool
+// after the p slots, at w_off[k].
+__device__ __forceinline__ int64_t list_base(const int *w_off, int64_t p, int64_t k, int cnt)
+{
+    return cnt > kWMax ? p * (int64_t)kWMax + w_off[k] : k * (int64_t)kWMax;
 }
 
 // Soft_lambda(a) = sign(a) (|a| - lambda)_+ ; 0 at |a| == lambda.
@@ -211,6 +220,8 @@ struct ColArgs {
     int *band_idx;       // [p * kBandMax] or null
     int *esc_cnt;        // escalation queue (32 -> 128 working set)
     int *esc_list;       // [p]
+    int *dense_cnt;      // escalation queue (128 -> the dense tier)
+    int *dense_list;     // [p]
     int *colinfo;        // [p * 4] per column: sigma updates, sweeps, updates, rounds
     unsigned long long *counters;
     const int *flags;    // nonzero: bad input, every wave exits at once
@@ -218,6 +229,51 @@ struct ColArgs {
 // tier: 0 = 32-wide working sets (escalating), 1 = 128-wide
 template <typename T>
 void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s);
+
+// Columns whose working sets outgrow the 128-coordinate LDS tier (see
+// dense.hip): where their start comes from ...
+template <typename TS>
+struct DenseSrc {
+    const int *cnt;       // [p] start-list lengths (> kWMax: the list is in the pool at off[k])
+    const int *idx;       // lists: column k at k * kWMax, or at p * kWMax + off[k]
+    const TS *beta;
+    const int *off;       // [p] pool offsets (read only for lists longer than kWMax)
+    const double *sigma;  // [p] start sigma
+    const int *pend_cnt;  // [p] extra candidates (kPendMax per column), or null
+    const int *pend_idx;
+};
+// ... and what the tier needs and writes.
+template <typename T>
+struct DenseArgs {
+    const T *S;           // p x p covariance (S source), or null with ...
+    const double *Xt;     // ... p x n standardised data (data source; T = double)
+    int64_t n, p;
+    int64_t pv;           // candidate variables j < pv (p for SPMESL)
+    T lambda0, tol, kkt_tol;
+    int max_outer, max_sweeps, max_rounds;
+    int block;            // b: rows per block of the delayed update (16 .. 64)
+    const int *queue;     // columns queue[0 .. *qcnt)
+    const int *qcnt;
+    int *w_cnt, *w_idx;   // results: nonzeros in ascending order, at k * kWMax,
+    T *w_beta;            // or (more than kWMax) at p * kWMax + w_off[k] in the pool
+    int *w_off;
+    double *sigma, *lam_used;
+    int *col_status;
+    int *pool_cnt;        // entries of the pool taken
+    int64_t pool_cap;
+    int *band_cnt;        // null, or set to kBandMax + 1 (the polish takes its full pass)
+    int *info;            // per-column counters (stride 4: outer, sweeps, updates,
+    int info_stride;      // KKT passes; stride 8 adds the rows added), accumulated
+    int *mark, *V, *Vold; // [p] workspace
+    T *R, *Bd, *Bp, *sk;  // [p * 16] workspace
+    double *Svv;          // [svv_cap^2] workspace of the data source
+    int64_t svv_cap;
+    double *E;            // [16 * n] workspace of the data source
+    unsigned long long *counters;
+    const int *flags;
+};
+template <typename T, typename TS>
+void launch_dense(const DenseArgs<T> &a, const DenseSrc<TS> &src, hipStream_t s);
 
 // Warm start of the column solves from a caller's B0 (p x p row-major,
 // column k = beta of response k) and sigma0 (p), on the standardised scale or
@@ -273,6 +329,8 @@ struct PolishArgs {
     double eps;             // bound on |g32 - g64| per unit of (1 + ||beta||_1)
     int *esc_cnt;           // escalation queue (32 -> 128 working set)
     int *esc_list;
+    int *dense_cnt;         // escalation queue (128 -> the dense tier)
+    int *dense_list;
     int *w_cnt;             // double solution (output)
     int *w_idx;
     double *w_beta;
@@ -298,14 +356,14 @@ void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s);
 // Outputs.
 void launch_fill_zero(double *A, int64_t count, hipStream_t s);
 template <typename T>
-void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta,
+void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta, const int *w_off,
                             const double *sigma, const double *scale, int original_scale,
                             double *B, double *sig_out, double *Omega, const int *flags,
                             hipStream_t s);
 void launch_symmetrize_dense(int64_t p, const double *Om1, double *Om, hipStream_t s);
 template <typename T>
 void launch_scatter_lasso(int64_t k0, int64_t m, const int *w_cnt, const int *w_idx, const T *w_beta,
-                          const double *sigma, const double *scale, int original_scale,
+                          const int *w_off, const double *sigma, const double *scale, int original_scale,
                           const int *colinfo, double *beta, double *sig_out, int *outer,
                           const int *flags, hipStream_t s);
 

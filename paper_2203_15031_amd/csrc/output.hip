@@ -166,6 +166,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_scatter(int64_t p, const int *__restrict__ w_cnt,
                                                  const int *__restrict__ w_idx,
                                                  const T *__restrict__ w_beta,
+                                                 const int *__restrict__ w_off,
                                                  const double *__restrict__ sigma,
                                                  const double *__restrict__ scale, int original,
                                                  double *__restrict__ B,
@@ -177,21 +178,23 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t p, const int *__restric
     const int lane = threadIdx.x & 63;
     if (k >= p || *flags) return;
     int wk = w_cnt[k];
-    wk = wk < 0 ? 0 : (wk > kWMax ? kWMax : wk);
+    wk = wk < 0 ? 0 : wk;
+    const int64_t bk = list_base(w_off, p, k, wk);
     const double sk = sigma[k];
     const double ck = original ? scale[k] : 1.0;
     const double dk = 1.0 / (sk * sk);
     for (int q = lane; q < wk; q += kWave) {
-        const int j = w_idx[k * kWMax + q];
-        const double b = (double)w_beta[k * kWMax + q];
+        const int j = w_idx[bk + q];
+        const double b = (double)w_beta[bk + q];
         if (b == 0.0 || j < 0 || (int64_t)j >= p) continue;
         const double cj = original ? scale[j] : 1.0;
         if (B) B[(int64_t)j * p + k] = b * (cj / ck);
         if (Om && j < k) {
             // the pair (j, k) belongs to its larger index k
-            const int *lj = w_idx + (int64_t)j * kWMax;
             int wj = w_cnt[j];
-            wj = wj < 0 ? 0 : (wj > kWMax ? kWMax : wj);
+            wj = wj < 0 ? 0 : wj;
+            const int64_t bj = list_base(w_off, p, j, wj);
+            const int *lj = w_idx + bj;
             int lo = 0, hi = wj;
             while (lo < hi) {
                 int mid = (lo + hi) >> 1;
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t p, const int *__restric
                 else hi = mid;
             }
             if (lo < wj && lj[lo] == (int)k) {
-                const double bkj = (double)w_beta[(int64_t)j * kWMax + lo];
+                const double bkj = (double)w_beta[bj + lo];
                 if (bkj != 0.0) {
                     const double sj = sigma[j];
                     const double ojk = -b * dk;               // omega_jk,1 (column k)
@@ -219,19 +222,19 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t p, const int *__restric
 }
 
 template <typename T>
-void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta,
+void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta, const int *w_off,
                             const double *sigma, const double *scale, int original_scale,
                             double *B, double *sig_out, double *Omega, const int *flags,
                             hipStream_t s)
 {
     hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((p + 3) / 4)), dim3(256), 0, s, p, w_cnt,
-                       w_idx, w_beta, sigma, scale, original_scale, B, sig_out, Omega, flags);
+                       w_idx, w_beta, w_off, sigma, scale, original_scale, B, sig_out, Omega, flags);
 }
 
-template void launch_scatter_outputs<double>(int64_t, const int *, const int *, const double *,
+template void launch_scatter_outputs<double>(int64_t, const int *, const int *, const double *, const int *,
                                              const double *, const double *, int, double *,
                                              double *, double *, const int *, hipStream_t);
-template void launch_scatter_outputs<float>(int64_t, const int *, const int *, const float *,
+template void launch_scatter_outputs<float>(int64_t, const int *, const int *, const float *, const int *,
                                             const double *, const double *, int, double *,
                                             double *, double *, const int *, hipStream_t);
 
@@ -245,6 +248,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_scatter_lasso(int64_t k0, int64_t m, const int *__restrict__ w_cnt,
                                                        const int *__restrict__ w_idx,
                                                        const T *__restrict__ w_beta,
+                                                       const int *__restrict__ w_off,
                                                        const double *__restrict__ sigma,
                                                        const double *__restrict__ scale, int original,
                                                        const int *__restrict__ colinfo,
@@ -257,11 +261,12 @@ __global__ __launch_bounds__(256) void k_scatter_lasso(int64_t k0, int64_t m, co
     if (r >= m || *flags) return;
     const int64_t k = k0 + r;
     int wk = w_cnt[k];
-    wk = wk < 0 ? 0 : (wk > kWMax ? kWMax : wk);
+    wk = wk < 0 ? 0 : wk;
+    const int64_t bk = list_base(w_off, k0 + m, k, wk);
     const double ck = original ? scale[k] : 1.0;
     for (int q = lane; q < wk; q += kWave) {
-        const int j = w_idx[k * kWMax + q];
-        const double b = (double)w_beta[k * kWMax + q];
+        const int j = w_idx[bk + q];
+        const double b = (double)w_beta[bk + q];
         if (b == 0.0 || j < 0 || (int64_t)j >= k0) continue;
         const double cj = original ? scale[j] : 1.0;
         beta[(int64_t)j * m + r] = b * (cj / ck);
@@ -274,17 +279,17 @@ __global__ __launch_bounds__(256) void k_scatter_lasso(int64_t k0, int64_t m, co
 
 template <typename T>
 void launch_scatter_lasso(int64_t k0, int64_t m, const int *w_cnt, const int *w_idx, const T *w_beta,
-                          const double *sigma, const double *scale, int original_scale,
+                          const int *w_off, const double *sigma, const double *scale, int original_scale,
                           const int *colinfo, double *beta, double *sig_out, int *outer,
                           const int *flags, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scatter_lasso<T>, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, k0, m, w_cnt,
-                       w_idx, w_beta, sigma, scale, original_scale, colinfo, beta, sig_out, outer, flags);
+                       w_idx, w_beta, w_off, sigma, scale, original_scale, colinfo, beta, sig_out, outer, flags);
 }
 
 template void launch_scatter_lasso<double>(int64_t, int64_t, const int *, const int *, const double *,
-                                           const double *, const double *, int, const int *, double *,
-                                           double *, int *, const int *, hipStream_t);
+                                           const int *, const double *, const double *, int, const int *,
+                                           double *, double *, int *, const int *, hipStream_t);
 
 // Dense symmetrisation of a given Omega_1 (32 x 32 tiles; the partner tile
 // is read transposed through LDS so both reads are coalesced).

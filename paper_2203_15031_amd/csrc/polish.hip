@@ -332,8 +332,17 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     SolveCounts cnt = {0, 0, 0};
     int status = kColOk, rounds = 0, checks = 0, added = 0;
 
+    // a float list longer than a tier holds (from the dense tier): the dense
+    // tier solves the column in double
+    if (w32 > kWMax) {
+        if (lane == 0) {
+            int pos = atomicAdd(A.dense_cnt, 1);
+            A.dense_list[pos] = (int)k;
+        }
+        return;
+    }
     // --- W' = float support U float band --------------------------------
-    w32 = w32 < 0 ? 0 : (w32 > kWMax ? kWMax : w32);
+    w32 = w32 < 0 ? 0 : w32;
     nb = nb < 0 ? 0 : nb;
     bool full = A.full_kkt || nb > kBandMax || (st32 != kColOk && st32 != kColDeferred);
     if constexpr (LW < kWMax) {
@@ -368,16 +377,12 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     wave_sync();
     nb = sort_unique_small(sm.pend, nb);  // the row-tiled pass appends in any order
     if (ns + nb > LW) {
-        if (!tier2) {
-            if (lane == 0) {
-                int pos = atomicAdd(A.esc_cnt, 1);
-                A.esc_list[pos] = (int)k;
-            }
-            return;
+        // to the wide kernel, or from it to the dense tier
+        if (lane == 0) {
+            int pos = atomicAdd(tier2 ? A.dense_cnt : A.esc_cnt, 1);
+            (tier2 ? A.dense_list : A.esc_list)[pos] = (int)k;
         }
-        status = kColWorkset;
-        nb = ns < LW ? (LW - ns < nb ? LW - ns : nb) : 0;
-        ns = ns < LW ? ns : LW;
+        return;
     }
     st.w = ns;
 #pragma unroll
@@ -458,18 +463,11 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
         ++rounds;
         int np = npend < kPendMax ? npend : kPendMax;
         if (st.w + np > LW) {
-            if (!tier2) {
-                if (lane == 0) {
-                    int pos = atomicAdd(A.esc_cnt, 1);
-                    A.esc_list[pos] = (int)k;
-                }
-                return;
+            if (lane == 0) {
+                int pos = atomicAdd(tier2 ? A.dense_cnt : A.esc_cnt, 1);
+                (tier2 ? A.dense_list : A.esc_list)[pos] = (int)k;
             }
-            np = LW - st.w;
-            if (np <= 0) {
-                status = kColWorkset;
-                break;
-            }
+            return;
         }
         // keep the double coefficients across the merge
 #pragma unroll
