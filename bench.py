@@ -439,14 +439,17 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default launch shapes instead of the autotuner's")
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--table2", action="store_true",
                     help="time the settings of the paper's timing table (four networks, p up to 5000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB device to device five times (profiler calibration)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    help="blockar_n400_p5000 (headline), sf_n1000_p20000, hub_batch64, or "
-                         "lasso_n250_p500_m256 (the scaled lasso on its own)")
+                    help="blockar_n400_p5000 (headline), sf_n1000_p20000, dense_n1500_p300 (every "
+                         "column in the dense tier), hub_batch64, or lasso_n250_p500_m256 (the scaled "
+                         "lasso on its own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -457,7 +460,7 @@ def main():
     import torch
     if args.copy_calibration:
         return copy_calibration(torch)
-    from paper_2203_15031_amd import spmesl, workloads
+    from paper_2203_15031_amd import spmesl, tuning, workloads
 
     if args.table2:
         return bench_table2(args, torch, spmesl, workloads)
@@ -473,7 +476,18 @@ def main():
     forms = args.forms.split(",")
     res = {}
     outs = {}
+    tunes = {}
     for prec in forms:
+        if not args.no_tune:
+            # launch shapes for this problem from the autotuner (cached per
+            # device, precision and shape; the tuning runs before the timed
+            # region, like any one-time set-up)
+            t, tms, hit = tuning.tuned(ctx, X, lam0, tol, prec, reps=20)
+            tunes[prec] = {"shapes": t, "ms_per_solve_when_tuned": round(tms, 5), "from_cache": hit}
+            print(f"[bench] {prec}: tuned launch shapes {t} ({'cache' if hit else 'tuned here'})",
+                  file=sys.stderr, flush=True)
+        else:
+            ctx.set_tuning(None)
         ms, ms_sync, ph, kern, r = time_form(ctx, X, lam0, tol, prec, args.steps, args.warmup, torch)
         res[prec] = (ms, ms_sync, ph, kern, r)
         outs[prec] = (r.B.cpu().numpy(), r.sigma.cpu().numpy())
@@ -520,6 +534,7 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
         "roofline": roof,
         "whole_solve": whole_solve_roofline(w.n, w.p, head, r.stats, ms),
+        "tuning": tunes or None,
         "kernels": kernels,
         "stats": {k: r.stats[k] for k in ("total_outer", "max_outer", "total_sweeps",
                                           "total_updates", "total_rounds", "max_working_set",

@@ -243,6 +243,42 @@ int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                        const spmesl_options *opt, const double *lambda0s,
                        spmesl_result *res, int *status);
 
+/* ---- launch shapes and the autotuner ------------------------------------ */
+
+/* Launch shapes a context applies to its solves.  None of them changes the
+ * minimiser; they change how the work is laid out (and, for the screen and
+ * the dense tier's block size, which path the iterates take).  0 in a field
+ * selects the default. */
+typedef struct {
+    int32_t dense_block;      /* b, rows per block of the dense tier's delayed
+                                 rank-b update (Proposition 2 blocked): 16, 32
+                                 or 64 (default 32) */
+    int32_t fill_blocks;      /* workgroups of the dense outputs' zero fill,
+                                 which runs beside the covariance kernel
+                                 (default 64) */
+    int32_t kkt_rows;         /* rows of S per tile of the row-tiled KKT pass:
+                                 1, 2 or 4 (default: the most that fit LDS) */
+    int32_t screen_permille;  /* first working sets {j : |s_jk| > f lambda0 +
+                                 tol}, f in thousandths (default 800) */
+} spmesl_tuning;
+
+/* Set (NULL: reset to the defaults) or read the context's launch shapes. */
+int spmesl_set_tuning(spmesl_ctx *ctx, const spmesl_tuning *t);
+int spmesl_get_tuning(const spmesl_ctx *ctx, spmesl_tuning *t);
+
+/* Autotuner: times solves of this problem (graph replays, the fastest of
+ * three runs of `reps` per candidate, HIP events on the context's stream;
+ * a candidate must be at least 1% faster to be kept) over the candidate values
+ * of each field in turn (coordinate search from the current shapes: screen
+ * 700/800/900/1000, KKT rows 4/2/1 as they fit, fill 32/64/128/256
+ * workgroups, dense block 16/32/64 when the problem reaches the dense tier),
+ * keeps the fastest, sets it on the context and writes it to *best (host,
+ * may be NULL) with its time per solve in *ms_best (host, may be NULL).  The
+ * outputs in `res` hold the last solve's result.  Allocates (workspace,
+ * graphs, a status word).  Returns SPMESL_OK or the first error of a solve. */
+int spmesl_autotune(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
+                    spmesl_result *res, int reps, spmesl_tuning *best, double *ms_best);
+
 /* Kernel times of the last spmesl_solve run with SPMESL_FLAG_TIMING: one
  * entry per launch step in enqueue order, `names[i]` a static string naming
  * the kernel(s) and `ms[i]` its duration in milliseconds, from HIP events

@@ -52,11 +52,32 @@ constexpr double kMixedFloatTol = 3e-5;
 // flagged columns fall from 12% to 4% of p against a factor of 1, for 10.6
 // instead of 5.3 coordinates per first working set; at 0.7 up to 93% of the
 // columns of a scale-free p = 20000 workload would outgrow 32 coordinates.
-constexpr double kScreenFactor = 0.8;
+constexpr int kScreenPermille = 800;
 // Rows per block of the dense tier's delayed update, and the largest V whose
 // S[V, V] the double dense tier of the mixed form keeps (8 MB).
 constexpr int kDenseBlock = 32;
 constexpr int64_t kDenseDataMax = 1024;
+// Workgroups of the zero fill of the dense outputs (64 blocks of
+// nontemporal 16-byte stores write about 5 TB/s beside the covariance kernel).
+constexpr int kFillBlocks = 64;
+
+// The launch shapes of a solve: the context's spmesl_tuning with its zero
+// fields replaced by the defaults.
+struct Tune {
+    int dense_block = kDenseBlock;
+    int fill_blocks = kFillBlocks;
+    int kkt_rows = 0;  // 0: the most that fit
+    int screen_permille = kScreenPermille;
+};
+Tune resolve_tune(const spmesl_tuning &t)
+{
+    Tune u;
+    if (t.dense_block > 0) u.dense_block = t.dense_block;
+    if (t.fill_blocks > 0) u.fill_blocks = t.fill_blocks;
+    if (t.kkt_rows > 0) u.kkt_rows = t.kkt_rows;
+    if (t.screen_permille > 0) u.screen_permille = t.screen_permille;
+    return u;
+}
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -253,6 +274,8 @@ struct spmesl_ctx {
     // if the lookup failed; scratch_err then holds the HIP error)
     char *scratch_dev = nullptr;
     hipError_t scratch_err = hipSuccess;
+    spmesl_tuning tune = {};     // launch shapes (zero fields: defaults)
+    int *tune_status = nullptr;  // device status word of the autotuner's solves
     std::string err;
 };
 
@@ -308,6 +331,14 @@ static void key_problem(KeyBuf &k, const spmesl_problem &pr, const spmesl_result
     k.add(r.B);
     k.add(r.sigma);
     k.add(r.Omega);
+}
+
+static void key_tuning(KeyBuf &k, const spmesl_tuning &t)
+{
+    k.add(t.dense_block);
+    k.add(t.fill_blocks);
+    k.add(t.kkt_rows);
+    k.add(t.screen_permille);
 }
 
 static void key_options(KeyBuf &k, const spmesl_options &o)
@@ -417,16 +448,17 @@ static int validate(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
 // for it.
 static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p, hipStream_t s, Marker *mk)
 {
+    const int fb = resolve_tune(ctx->tune).fill_blocks;
     if (!res->B && !res->Omega) return SPMESL_OK;
     HIPTRY(ctx, hipEventRecord(ctx->fork, s));
     HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork, 0));
     mark(mk, ctx->side, nullptr);
     if (res->B) {
-        launch_fill_zero(res->B, p * p, ctx->side);
+        launch_fill_zero(res->B, p * p, ctx->side, fb);
         mark(mk, ctx->side, "fill_B");
     }
     if (res->Omega) {
-        launch_fill_zero(res->Omega, p * p, ctx->side);
+        launch_fill_zero(res->Omega, p * p, ctx->side, fb);
         mark(mk, ctx->side, "fill_Omega");
     }
     HIPTRY(ctx, hipEventRecord(ctx->join, ctx->side));
@@ -436,7 +468,8 @@ static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p
 // The dense tier (dense.hip) for the columns the 128-coordinate tier handed
 // over, reading S and writing the columns' results in place.
 template <typename T>
-static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &a, hipStream_t s, Marker *mk)
+static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &a, const Tune &tu, hipStream_t s,
+                          Marker *mk)
 {
     DenseArgs<T> d{};
     d.S = a.S;
@@ -450,7 +483,7 @@ static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &
     d.max_outer = a.max_outer;
     d.max_sweeps = a.max_sweeps;
     d.max_rounds = a.max_rounds;
-    d.block = kDenseBlock;
+    d.block = tu.dense_block;
     d.queue = a.dense_list;
     d.qcnt = a.dense_cnt;
     d.w_cnt = a.w_cnt;
@@ -493,12 +526,13 @@ static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &
 // columns k0 .. p-1 are solved, each on the predictors 0 .. k0-1 (the scaled
 // lassos of responses appended to a design), with in-wave KKT passes.
 template <typename T, typename F>
-static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt,
+static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt, const Tune &tu,
                            double tol, double band, int max_outer, int max_sweeps, int max_rounds,
                            hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0, bool warm = false)
 {
     const int64_t p = L.p;
-    const int rj = k0 > 0 ? 0 : kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
+    int rj = k0 > 0 ? 0 : kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
+    if (rj > 0 && tu.kkt_rows > 0 && tu.kkt_rows < rj) rj = tu.kkt_rows >= 2 ? 2 : 1;
     ColArgs<T> a{};
     a.S = (const T *)(ws + L.S);
     a.p = p;
@@ -549,7 +583,7 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
         a.work_cnt = &dctl->esc_a;
         launch_colsolve(a, 1, s);
         mark(mk, s, "colsolve_first_wide");
-        enqueue_dense<T>(L, ws, dctl, a, s, mk);
+        if (band == 0.0) enqueue_dense<T>(L, ws, dctl, a, tu, s, mk);
         return after_kkt();
     }
     KktArgs<T> k{};
@@ -588,7 +622,9 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.work_cnt = &dctl->esc_c;
     launch_colsolve(a, 1, s);
     mark(mk, s, "colsolve_resume_wide");
-    enqueue_dense<T>(L, ws, dctl, a, s, mk);
+    // the dense tier; in the mixed form (band > 0) its columns go to the
+    // double polish's dense tier instead
+    if (band == 0.0) enqueue_dense<T>(L, ws, dctl, a, tu, s, mk);
     return SPMESL_OK;
 }
 
@@ -606,6 +642,8 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     double *mean = (double *)(ws + L.mean);
     double *scale = (double *)(ws + L.scale);
     const int original = opt->output_scale == SPMESL_SCALE_ORIGINAL;
+    const Tune tu = resolve_tune(ctx->tune);
+    const double screen = tu.screen_permille * 1e-3;
 
     if (ev) HIPTRY(ctx, hipEventRecord(ev[0], s));
     Marker marker(ctx);
@@ -646,7 +684,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
 
-    // the first solves' working sets, {j : |s_jk| > kScreenFactor lambda0 +
+    // the first solves' working sets, {j : |s_jk| > f lambda0 +
     // tol}, are taken where S is written.  At beta = 0 the KKT test is
     // |s_jk| > lambda0 + tol; the final lambda is sigma lambda0 with sigma < 1,
     // so the lower factor starts most columns on their final support (a
@@ -657,9 +695,9 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                                 : std::max(opt->tol, L.prec == SPMESL_MIXED ? kMixedFloatTol
                                                                             : (double)SPMESL_FP32_TOL_FLOOR);
     Screen sc;
-    sc.thr64 = kScreenFactor * opt->lambda0 + tol_cols;
+    sc.thr64 = screen * opt->lambda0 + tol_cols;
     {
-        volatile float a = (float)(kScreenFactor * opt->lambda0), b = (float)tol_cols;
+        volatile float a = (float)(screen * opt->lambda0), b = (float)tol_cols;
         sc.thr32 = a + b;
     }
     sc.cnt = (int *)(ws + L.pendcnt);  // zeroed by the column statistics
@@ -695,10 +733,10 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     }
     int vc;
     if (L.prec == SPMESL_FP64)
-        vc = enqueue_columns<double>(L, ws, dctl, opt, tol_cols, 0.0, max_outer, max_sweeps, max_rounds, s,
+        vc = enqueue_columns<double>(L, ws, dctl, opt, tu, tol_cols, 0.0, max_outer, max_sweeps, max_rounds, s,
                                      mk, fork, 0, warm);
     else
-        vc = enqueue_columns<float>(L, ws, dctl, opt, tol_cols, L.prec == SPMESL_MIXED ? kMixedBand : 0.0,
+        vc = enqueue_columns<float>(L, ws, dctl, opt, tu, tol_cols, L.prec == SPMESL_MIXED ? kMixedBand : 0.0,
                                     max_outer, max_sweeps, max_rounds, s, mk, fork, 0, warm);
     if (vc != SPMESL_OK) return vc;
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
@@ -756,7 +794,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         d.max_outer = max_outer;
         d.max_sweeps = max_sweeps;
         d.max_rounds = max_rounds;
-        d.block = kDenseBlock;
+        d.block = tu.dense_block;
         d.queue = q.dense_list;
         d.qcnt = q.dense_cnt;
         d.w_cnt = q.w_cnt;
@@ -789,6 +827,8 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         src.beta = q.w_beta32;
         src.off = (const int *)(ws + L.woff);
         src.sigma = q.sigma32;
+        src.pend_cnt = (const int *)(ws + L.pendcnt);
+        src.pend_idx = (const int *)(ws + L.pendidx);
         launch_dense<double, float>(d, src, s);
         mark(mk, s, "dense_polish");
     }
@@ -967,6 +1007,7 @@ void spmesl_destroy(spmesl_ctx *ctx)
         if (ctx->fork2) (void)hipEventDestroy(ctx->fork2);
         if (ctx->join2) (void)hipEventDestroy(ctx->join2);
         if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
+        if (ctx->tune_status) (void)hipFree(ctx->tune_status);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         for (int i = 0; i < 6; ++i)
             if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
@@ -1038,6 +1079,7 @@ int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_optio
         k.add(ctx->ws);
         key_problem(k, *prob, *res);
         key_options(k, *opt);
+        key_tuning(k, ctx->tune);
         v = run_graph(ctx, std::move(k.b),
                       [&] { return enqueue_solve(ctx, prob, opt, res, L, ctx->ws, dctl, nullptr); });
     }
@@ -1104,6 +1146,7 @@ int spmesl_solve_async(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl
     k.add(status_dev);
     key_problem(k, *prob, *res);
     key_options(k, *opt);
+    key_tuning(k, ctx->tune);
     return run_graph(ctx, std::move(k.b), body);
 }
 
@@ -1133,6 +1176,128 @@ int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     if (v != SPMESL_OK) return v;
     hipLaunchKernelGGL(k_decode_status, dim3(1), dim3(1), 0, ctx->stream, dctl, status_dev);
     HIPTRY(ctx, hipGetLastError());
+    return SPMESL_OK;
+}
+
+int spmesl_set_tuning(spmesl_ctx *ctx, const spmesl_tuning *t)
+{
+    if (!ctx) return SPMESL_EINVAL;
+    if (!t) {
+        ctx->tune = spmesl_tuning{};
+        return SPMESL_OK;
+    }
+    if (t->dense_block < 0 || (t->dense_block > 0 && t->dense_block != 16 && t->dense_block != 32 &&
+                               t->dense_block != 64))
+        return fail(ctx, SPMESL_EINVAL, "dense_block must be 0, 16, 32 or 64");
+    if (t->fill_blocks < 0 || t->fill_blocks > 4096)
+        return fail(ctx, SPMESL_EINVAL, "fill_blocks must be in 0 .. 4096");
+    if (t->kkt_rows < 0 || t->kkt_rows > 4) return fail(ctx, SPMESL_EINVAL, "kkt_rows must be in 0 .. 4");
+    if (t->screen_permille < 0 || t->screen_permille > 4000)
+        return fail(ctx, SPMESL_EINVAL, "screen_permille must be in 0 .. 4000");
+    ctx->tune = *t;
+    return SPMESL_OK;
+}
+
+int spmesl_get_tuning(const spmesl_ctx *ctx, spmesl_tuning *t)
+{
+    if (!ctx || !t) return SPMESL_EINVAL;
+    *t = ctx->tune;
+    return SPMESL_OK;
+}
+
+// Milliseconds per solve: the fastest of three runs of `reps` asynchronous
+// solves back to back (graph replays; the first call captures the graph, is
+// checked and is not timed).  The minimum over runs keeps other work on the
+// device out of the comparison.
+static int time_solves(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
+                       spmesl_result *res, int reps, double *ms)
+{
+    spmesl_options o = *opt;
+    o.flags &= ~(SPMESL_FLAG_TIMING | SPMESL_FLAG_EAGER);
+    int v = spmesl_solve(ctx, prob, &o, res);  // captures the graph, checks the status
+    if (v != SPMESL_OK) return v;
+    DevGuard g(ctx->device);
+    double best = 0.0;
+    for (int run = 0; run < 3; ++run) {
+        HIPTRY(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+        for (int r = 0; r < reps; ++r) {
+            v = spmesl_solve_async(ctx, prob, &o, res, ctx->tune_status);
+            if (v != SPMESL_OK) return v;
+        }
+        HIPTRY(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+        HIPTRY(ctx, hipEventSynchronize(ctx->ev[1]));
+        float t = 0.f;
+        HIPTRY(ctx, hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+        const double m = (double)t / reps;
+        best = run == 0 || m < best ? m : best;
+    }
+    *ms = best;
+    return SPMESL_OK;
+}
+
+int spmesl_autotune(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
+                    spmesl_result *res, int reps, spmesl_tuning *best, double *ms_best)
+{
+    if (!ctx || !res || reps < 1) return SPMESL_EINVAL;
+    int v = validate(ctx, prob, opt);
+    if (v != SPMESL_OK) return v;
+    if (!ctx->have_events) return fail(ctx, SPMESL_EHIP, "the context has no timing events");
+    {
+        DevGuard g(ctx->device);
+        if (!ctx->tune_status) HIPTRY(ctx, hipMalloc((void **)&ctx->tune_status, sizeof(int)));
+    }
+    // explicit values for every field, starting from the current shapes
+    const Tune d = resolve_tune(ctx->tune);
+    spmesl_tuning cur{};
+    cur.dense_block = d.dense_block;
+    cur.fill_blocks = d.fill_blocks;
+    cur.screen_permille = d.screen_permille;
+    const size_t tsz = opt->precision == SPMESL_FP64 ? 8 : 4;
+    const int rj_max = kkt_rows_per_block(prob->p, tsz, (size_t)160 * 1024);
+    cur.kkt_rows = d.kkt_rows > 0 && d.kkt_rows < rj_max ? d.kkt_rows : rj_max;
+    ctx->tune = cur;
+    double tbest = 0.0;
+    v = time_solves(ctx, prob, opt, res, reps, &tbest);
+    if (v != SPMESL_OK) return v;
+    // does the problem reach the dense tier?  (its block size matters only then)
+    spmesl_stats st{};
+    spmesl_result rs = *res;
+    rs.stats = &st;
+    v = spmesl_solve(ctx, prob, opt, &rs);
+    if (v != SPMESL_OK) return v;
+    const bool dense = st.max_working_set > SPMESL_MAX_WORKING_SET || ctx->pinned[0].dense + ctx->pinned[0].dense64 > 0;
+    auto search = [&](int32_t spmesl_tuning::*field, std::vector<int> cands) -> int {
+        for (int c : cands) {
+            if (c == cur.*field) continue;
+            spmesl_tuning t = cur;
+            t.*field = c;
+            ctx->tune = t;
+            double ms = 0.0;
+            const int r = time_solves(ctx, prob, opt, res, reps, &ms);
+            if (r != SPMESL_OK) return r;
+            // a candidate replaces the current shapes only when clearly faster
+            if (ms < 0.99 * tbest) {
+                tbest = ms;
+                cur = t;
+            }
+        }
+        ctx->tune = cur;
+        return SPMESL_OK;
+    };
+    if ((v = search(&spmesl_tuning::screen_permille, {700, 800, 900, 1000})) != SPMESL_OK) return v;
+    if (rj_max > 0) {
+        std::vector<int> kr;
+        for (int r = rj_max; r >= 1; r >>= 1) kr.push_back(r);
+        if ((v = search(&spmesl_tuning::kkt_rows, kr)) != SPMESL_OK) return v;
+    }
+    if ((v = search(&spmesl_tuning::fill_blocks, {32, 64, 128, 256})) != SPMESL_OK) return v;
+    if (dense && (v = search(&spmesl_tuning::dense_block, {16, 32, 64})) != SPMESL_OK) return v;
+    ctx->tune = cur;
+    // the outputs hold a solve with the chosen shapes
+    v = spmesl_solve(ctx, prob, opt, res);
+    if (v != SPMESL_OK) return v;
+    if (best) *best = cur;
+    if (ms_best) *ms_best = tbest;
     return SPMESL_OK;
 }
 
@@ -1181,6 +1346,7 @@ int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
         for (int i = 0; i < count; ++i) {
             key_problem(k, probs[i], res[i]);
             key_options(k, opts[(size_t)i]);
+            key_tuning(k, ctx->tune);
         }
         v = run_graph(ctx, std::move(k.b), body);
     }
@@ -1326,13 +1492,14 @@ int spmesl_scaled_lasso(spmesl_ctx *ctx, const spmesl_problem *prob, const doubl
     // the first working sets from the screen taken with S, as in spmesl_solve,
     // with the design columns j < p as the only candidates
     Screen sc;
-    sc.thr64 = kScreenFactor * opt->lambda0 + opt->tol;
+    const Tune tu = resolve_tune(ctx->tune);
+    sc.thr64 = tu.screen_permille * 1e-3 * opt->lambda0 + opt->tol;
     sc.thr32 = 0.0f;
     sc.cnt = (int *)(ws + L.pendcnt);
     sc.idx = (int *)(ws + L.pendidx);
     sc.pv = px;
     launch_syrk_f64((const double *)(ws + L.xs), n, pa, (double *)(ws + L.S), sc, s);
-    v = enqueue_columns<double>(L, ws, dctl, opt, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s,
+    v = enqueue_columns<double>(L, ws, dctl, opt, tu, opt->tol, 0.0, max_outer, max_sweeps, max_rounds, s,
                                 nullptr, [] { return (int)SPMESL_OK; }, px);
     if (v != SPMESL_OK) return v;
     launch_reduce_stats(m, (const int *)(ws + L.colinfo) + 4 * px, nullptr, (const int *)(ws + L.wcnt) + px,

@@ -95,7 +95,9 @@ __device__ void record_info(const ColArgs<T> &A, int64_t k, const SolveCounts &c
 
 // Hand column k to the next tier: its state (W, beta, sigma) and its np
 // pending candidates are stored, and k joins the 128-coordinate tier's queue
-// (from the 32-coordinate tier) or the dense tier's (from the 128 one).
+// (from the 32-coordinate tier) or the dense tier's (from the 128 one, with
+// the status kColDenseQ; in the mixed form the double polish hands such a
+// column to the dense tier in double, so the float stage has no dense tier).
 // `unsolved`: the stored state is a warm start no solve has run on yet (the
 // wide kernel then solves it even with no pending candidates)
 template <typename T, int LW>
@@ -105,7 +107,7 @@ __device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const W
 {
     const int lane = lane_id();
     const bool dense = LW >= kWMax;
-    store_column(A, k, sm, st, unsolved ? (int)kColWarm : (int)kColOk, false);
+    store_column(A, k, sm, st, dense ? (int)kColDenseQ : (unsolved ? (int)kColWarm : (int)kColOk), false);
     if (lane == 0) record_info(A, k, cnt, rounds);
     for (int i = lane; i < np; i += kWave) A.pend_idx[k * kPendMax + i] = sm.pend[i];
     if (lane == 0) {

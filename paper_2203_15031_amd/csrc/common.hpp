@@ -39,6 +39,7 @@ enum Counter : int {
 
 // Column status codes written by the kernels (mirror the public codes).
 enum ColStatus : int {
+    kColDenseQ = 3,     // handed to the dense tier (working set beyond 128)
     kColWarm = 2,       // state set by a warm start, not yet solved
     kColDeferred = 1,   // first solve done, KKT check left to the row-tiled pass
     kColOk = 0,
@@ -354,7 +355,7 @@ void launch_reduce_stats(int64_t p, const int *colinfo, const int *polinfo, cons
 void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s);
 
 // Outputs.
-void launch_fill_zero(double *A, int64_t count, hipStream_t s);
+void launch_fill_zero(double *A, int64_t count, hipStream_t s, int max_blocks = 64);
 template <typename T>
 void launch_scatter_outputs(int64_t p, const int *w_cnt, const int *w_idx, const T *w_beta, const int *w_off,
                             const double *sigma, const double *scale, int original_scale,

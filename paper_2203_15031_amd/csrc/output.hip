@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ A, int64
     if (blockIdx.x == 0 && threadIdx.x == 0 && (count & 1)) A[count - 1] = 0.0;
 }
 
-void launch_fill_zero(double *A, int64_t count, hipStream_t s)
+void launch_fill_zero(double *A, int64_t count, hipStream_t s, int max_blocks)
 {
     if (count <= 0) return;
     if (((uintptr_t)A & 15u) != 0) {
@@ -156,7 +156,7 @@ void launch_fill_zero(double *A, int64_t count, hipStream_t s)
     // the second stream; 64 blocks of nontemporal 16-byte stores still write
     // about 5 TB/s, and leave the solves their wave slots (with 256 blocks
     // the re-solves of flagged columns took 90 us instead of 65 at p = 5000)
-    if (blocks > 64) blocks = 64;
+    if (blocks > max_blocks) blocks = max_blocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, A, count);
 }

@@ -332,9 +332,10 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     SolveCounts cnt = {0, 0, 0};
     int status = kColOk, rounds = 0, checks = 0, added = 0;
 
-    // a float list longer than a tier holds (from the dense tier): the dense
-    // tier solves the column in double
-    if (w32 > kWMax) {
+    // a column the float stage handed to the dense tier (its state is the
+    // 128-coordinate tier's last working set and pending candidates): the
+    // dense tier solves it in double
+    if (w32 > kWMax || st32 == kColDenseQ) {
         if (lane == 0) {
             int pos = atomicAdd(A.dense_cnt, 1);
             A.dense_list[pos] = (int)k;

@@ -70,6 +70,14 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("dense_block", C.c_int32), ("fill_blocks", C.c_int32), ("kkt_rows", C.c_int32),
+                ("screen_permille", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Result(C.Structure):
     _fields_ = [("B", C.c_void_p), ("sigma", C.c_void_p), ("Omega", C.c_void_p),
                 ("stats", C.POINTER(Stats))]
@@ -119,6 +127,13 @@ def load():
     lib.spmesl_scaled_lasso_workspace_size.restype = C.c_int
     lib.spmesl_symmetrize.argtypes = [vp, i64, vp, vp]
     lib.spmesl_symmetrize.restype = C.c_int
+    lib.spmesl_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    lib.spmesl_set_tuning.restype = C.c_int
+    lib.spmesl_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    lib.spmesl_get_tuning.restype = C.c_int
+    lib.spmesl_autotune.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result), C.c_int,
+                                    C.POINTER(Tuning), C.POINTER(C.c_double)]
+    lib.spmesl_autotune.restype = C.c_int
     lib.spmesl_kernel_times.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double)]
     lib.spmesl_kernel_times.restype = C.c_int
     for f in ("spmesl_lambda_univ", "spmesl_lambda_ub"):
@@ -431,6 +446,38 @@ class Context:
         if vec:
             return beta[:, 0], sigma[0], outer[0], st, stats.as_dict()
         return beta, sigma, outer, st, stats.as_dict()
+
+    # -- launch shapes and the autotuner ------------------------------------
+    def set_tuning(self, tuning=None):
+        """Set the context's launch shapes (a dict of spmesl_tuning fields;
+        None resets them to the defaults)."""
+        if tuning is None:
+            st = load().spmesl_set_tuning(self._h, None)
+        else:
+            t = Tuning(**{k: int(v) for k, v in tuning.items()})
+            st = load().spmesl_set_tuning(self._h, C.byref(t))
+        if st != OK:
+            raise SpmeslError(st, self._err())
+
+    def get_tuning(self):
+        t = Tuning()
+        st = load().spmesl_get_tuning(self._h, C.byref(t))
+        if st != OK:
+            raise SpmeslError(st, self._err())
+        return t.as_dict()
+
+    def autotune(self, X, lambda0, tol=1e-8, precision="fp64", output_scale="original", reps=5, out=None):
+        """spmesl_autotune on this problem: returns (tuning dict, ms per solve);
+        the context keeps the chosen shapes."""
+        opt = self.options(lambda0, tol, precision, output_scale)
+        prob, res, out, _ = self._prepare(X, opt, ("B", "sigma", "Omega"), out)
+        best = Tuning()
+        ms = C.c_double()
+        st = load().spmesl_autotune(self._h, C.byref(prob), C.byref(opt), C.byref(res), int(reps),
+                                    C.byref(best), C.byref(ms))
+        if st != OK:
+            raise SpmeslError(st, self._err())
+        return best.as_dict(), ms.value
 
     def kernel_times(self):
         """[(name, ms)] of each launch step of the last solve run with timing=True."""

@@ -23,9 +23,9 @@ Structures
   with 0.48 off-diagonals, AR(4) with 0.6^|i-j|, and scale-free and hub
   networks built from subnetworks of 100 nodes.
 
-The five named workloads (``WORKLOADS``) are the ones the tests and the
-benchmark use; their penalty is lambda0 = sqrt(2 log p / n) and their
-tolerance 1e-8.
+The named workloads (``WORKLOADS``) are the ones the tests and the
+benchmark use; their penalty is lambda0 = sqrt(2 log p / n) (one states its
+own) and their tolerance 1e-8.
 """
 from __future__ import annotations
 
@@ -400,7 +400,10 @@ class Workload:
 
     @property
     def lambda0(self) -> float:
-        """sqrt(2 log p / n), the penalty the workload is specified with."""
+        """sqrt(2 log p / n), the penalty the workload is specified with
+        (unless it states its own)."""
+        if "lambda0" in self.extra:
+            return float(self.extra["lambda0"])
         return math.sqrt(2.0 * math.log(self.p) / self.n)
 
 
@@ -415,6 +418,10 @@ WORKLOADS = {
                             batch=64),
     "sf_n1000_p20000": Workload("sf_n1000_p20000", 1000, 20000, 4,
                                 "Barabasi-Albert tree, +-U[0.2,0.4], diag dominant + 0.1"),
+    # every column's support has 130-190 coordinates at this small penalty:
+    # the case of working sets beyond the 128 an LDS tier holds
+    "dense_n1500_p300": Workload("dense_n1500_p300", 1500, 300, 9, "ar_cov(0.3), centred, lambda0 = 0.015",
+                                 extra={"lambda0": 0.015}),
 }
 
 
@@ -447,6 +454,8 @@ def generate(name: str, n: int | None = None, p: int | None = None) -> np.ndarra
     if name == "sf_n1000_p20000":
         X, *_ = scale_free_tree_sample(n, p, 0.2, 0.4, 0.1, rng)
         return X
+    if name == "dense_n1500_p300":
+        return sample_from_cov(n, ar_cov(p, 0.3), rng, centre=True)
     raise ValueError(f"{name} is a batch workload; use generate_batch")
 
 

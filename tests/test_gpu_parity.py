@@ -276,10 +276,9 @@ def test_dense_tier_takes_every_column(ctx, prec, bar):
     # n = 1500, p = 300, lambda0 = 0.015 on an AR(0.3) design: every
     # column's support has 130-190 coordinates, so all 300 columns go
     # through the dense tier (19 groups of up to 16 columns)
-    rng = np.random.default_rng(9)
-    n, p = 1500, 300
-    X = W.sample_from_cov(n, W.ar_cov(p, 0.3), rng)
-    errs, st = _check_full(ctx, X, 0.015, prec, bar, max_outer=200, max_sweeps=20000)
+    w = W.workload("dense_n1500_p300")
+    X = W.generate(w.name)
+    errs, st = _check_full(ctx, X, w.lambda0, prec, bar, max_outer=200, max_sweeps=20000)
     assert st["max_working_set"] > 128 and st["columns_noconv"] == 0, st
 
 
@@ -480,3 +479,45 @@ def test_warm_start_from_the_solution_and_wide_columns(ctx):
     s0[3] = -1.0
     r = ctx.solve(Xg, lam, tol=1e-8, precision="fp64", output_scale="standardized", sigma0=s0)
     assert r.status == 0 and rel_err(host(r.Omega), host(cold.Omega)) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# launch shapes and the autotuner
+# ---------------------------------------------------------------------------
+
+def test_autotune_and_tuning(ctx, sp):
+    w = W.workload("er_n200_p1000")
+    X = W.generate(w.name)
+    Xg = gpu(X)
+    ref = oracle.spmesl(X, w.lambda0, tol=1e-12)
+    try:
+        t, ms = ctx.autotune(Xg, w.lambda0, w.tol, "mixed", reps=3)
+        assert ms > 0
+        assert t["dense_block"] in (16, 32, 64) and t["kkt_rows"] in (1, 2, 4)
+        assert t["fill_blocks"] in (32, 64, 128, 256) and t["screen_permille"] in (700, 800, 900, 1000)
+        assert ctx.get_tuning() == t
+        # every candidate shape gives the same minimiser
+        for shapes in (t, dict(t, kkt_rows=1, screen_permille=1000, fill_blocks=32)):
+            ctx.set_tuning(shapes)
+            r = ctx.solve(Xg, w.lambda0, tol=w.tol, precision="mixed")
+            assert rel_err(host(r.Omega), ref["Omega"]) <= 1e-4
+        with pytest.raises(sp.SpmeslError) as e:
+            ctx.set_tuning(dict(t, dense_block=48))
+        assert e.value.code == sp.EINVAL
+    finally:
+        ctx.set_tuning(None)
+    assert ctx.get_tuning() == dict(dense_block=0, fill_blocks=0, kkt_rows=0, screen_permille=0)
+
+
+@pytest.mark.parametrize("b", [16, 64])
+def test_dense_tier_block_sizes(ctx, b):
+    # the dense tier's block size b changes when the gradients outside a
+    # block are brought up to date, not the minimiser
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((600, 200))
+    X[:, 0] = X[:, 1:151].sum(1) + 0.01 * rng.standard_normal(600)
+    try:
+        ctx.set_tuning(dict(dense_block=b))
+        _check_full(ctx, X, 0.03, "fp64", 1e-6, tol=1e-10, max_outer=200, max_sweeps=20000)
+    finally:
+        ctx.set_tuning(None)

@@ -92,3 +92,36 @@ def test_workspace_size_and_validation():
               spmesl.Options(0.2, 1e-8, 0, 0, 0, 3, 0, 0), spmesl.Options(0.2, 1e-8, 0, 0, 0, 0, 2, 0)):
         sz = ctypes.c_size_t()
         assert lib.spmesl_workspace_size(ctypes.byref(prob), ctypes.byref(o), ctypes.byref(sz)) == -1
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    # the autotuner's cache: stored entries come back, keyed by device,
+    # precision and shape, and a hit skips the tuning call
+    from paper_2203_15031_amd import tuning
+
+    class FakeCtx:
+        def __init__(self):
+            self.tuned = 0
+            self.set = None
+
+        def autotune(self, X, lam, tol, prec, reps=5):
+            self.tuned += 1
+            return {"dense_block": 16, "fill_blocks": 128, "kkt_rows": 2, "screen_permille": 900}, 0.25
+
+        def set_tuning(self, t):
+            self.set = dict(t)
+
+    class FakeX:
+        shape = (400, 5000)
+
+    path = str(tmp_path / "t.json")
+    c = FakeCtx()
+    t, ms, hit = tuning.tuned(c, FakeX(), 0.2, precision="mixed", path=path, device_name="gpu")
+    assert not hit and c.tuned == 1 and ms == 0.25 and t["fill_blocks"] == 128
+    t2, ms2, hit2 = tuning.tuned(c, FakeX(), 0.2, precision="mixed", path=path, device_name="gpu")
+    assert hit2 and c.tuned == 1 and t2 == t and c.set == t and ms2 == 0.25
+    # another precision or shape is another entry
+    tuning.tuned(c, FakeX(), 0.2, precision="fp64", path=path, device_name="gpu")
+    assert c.tuned == 2
+    data = tuning.load(path)
+    assert tuning.key("gpu", "mixed", 400, 5000) in data and len(data) == 2
