@@ -160,15 +160,21 @@ def whole_solve_roofline(n, p, prec, stats, ms):
             "note": "T_measured is the pipelined time per solve; peaks as in roofline"}
 
 
-def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
+# the forms a run can time: name -> (precision, data form)
+FORMS = {"mixed": ("mixed", False), "fp64": ("fp64", False), "fp32": ("fp32", False), "data": ("fp64", True)}
+DTYPES = {"mixed": "bf16x3-f32+f64", "fp64": "f64", "fp32": "f32", "data": "f64"}
+
+
+def time_form(ctx, X, lam0, tol, form, steps, warmup, torch):
+    prec, data = FORMS[form]
     p = X.shape[1]
     out = dict(B=torch.empty((p, p), dtype=torch.float64, device=X.device),
                sigma=torch.empty((p,), dtype=torch.float64, device=X.device),
                Omega=torch.empty((p, p), dtype=torch.float64, device=X.device))
     status = torch.full((1,), 99, dtype=torch.int32, device=X.device)
     for _ in range(warmup):
-        ctx.solve(X, lam0, tol, prec, out=out)
-        ctx.solve_async(X, lam0, status, tol, prec, out=out)
+        ctx.solve(X, lam0, tol, prec, out=out, data_form=data)
+        ctx.solve_async(X, lam0, status, tol, prec, out=out, data_form=data)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -179,7 +185,7 @@ def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
-        ctx.solve_async(X, lam0, status, tol, prec, out=out)
+        ctx.solve_async(X, lam0, status, tol, prec, out=out, data_form=data)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -191,7 +197,7 @@ def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
           for _ in range(steps)]
     for a, b in ev:
         a.record(stream)
-        r = ctx.solve(X, lam0, tol, prec, out=out)
+        r = ctx.solve(X, lam0, tol, prec, out=out, data_form=data)
         b.record(stream)
     torch.cuda.synchronize()
     per_call = sorted(a.elapsed_time(b) for a, b in ev)
@@ -203,7 +209,7 @@ def time_form(ctx, X, lam0, tol, prec, steps, warmup, torch):
     kern = {}
     reps = max(1, min(steps, 10))
     for _ in range(reps):
-        r = ctx.solve(X, lam0, tol, prec, out=out, timing=True)
+        r = ctx.solve(X, lam0, tol, prec, out=out, timing=True, data_form=data)
         for k in ph:
             ph[k] += r.stats["ms_" + k] / reps
         for name, kms in ctx.kernel_times():
@@ -441,7 +447,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch shapes instead of the autotuner's")
-    ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--forms", default="mixed,fp64",
+                    help="comma list of mixed, fp64, fp32, data (the double data form, no S)")
     ap.add_argument("--table2", action="store_true",
                     help="time the settings of the paper's timing table (four networks, p up to 5000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -478,11 +485,11 @@ def main():
     outs = {}
     tunes = {}
     for prec in forms:
-        if not args.no_tune:
+        if not args.no_tune and not FORMS[prec][1]:
             # launch shapes for this problem from the autotuner (cached per
             # device, precision and shape; the tuning runs before the timed
             # region, like any one-time set-up)
-            t, tms, hit = tuning.tuned(ctx, X, lam0, tol, prec, reps=20)
+            t, tms, hit = tuning.tuned(ctx, X, lam0, tol, FORMS[prec][0], reps=20)
             tunes[prec] = {"shapes": t, "ms_per_solve_when_tuned": round(tms, 5), "from_cache": hit}
             print(f"[bench] {prec}: tuned launch shapes {t} ({'cache' if hit else 'tuned here'})",
                   file=sys.stderr, flush=True)
@@ -498,7 +505,7 @@ def main():
 
     head = forms[0]
     ms, ms_sync, ph, kern, r = res[head]
-    costs = kernel_costs(w.n, w.p, head)
+    costs = kernel_costs(w.n, w.p, FORMS[head][0]) if not FORMS[head][1] else {}
     # the kernel step that takes longest per solve, among those on the
     # solver's stream (the output fill overlaps them on the second stream)
     main = {k: v for k, v in kern.items() if not k.startswith(("fill_", "wait_"))}
@@ -507,13 +514,13 @@ def main():
     if dom not in costs:
         roof["note"] = "latency-bound step with no algorithmic byte count; achieved is 0"
     on_traffic = args.workload == WORKLOAD
-    roof["traffic"] = measured_traffic(dom, head) if on_traffic else None
+    roof["traffic"] = measured_traffic(dom, FORMS[head][0]) if on_traffic else None
     kernels = {}
     for k, v in kern.items():
         kernels[k] = dict(ms_per_solve=round(v["ms_per_solve"], 5), launches=v["launches"])
         if k in costs:
             rk = roofline_of(k, v["ms_per_launch"], costs[k])
-            rk["traffic"] = measured_traffic(k, head) if on_traffic else None
+            rk["traffic"] = measured_traffic(k, FORMS[head][0]) if on_traffic else None
             kernels[k]["roofline"] = rk
     line = {
         "metric": "full SPMESL solves/s at p=5000 (mixed vs FP64), % MFMA/HBM roofline",
@@ -527,13 +534,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "bf16x3-f32+f64", "fp64": "f64", "fp32": "f32"}[head],
+        "dtype": DTYPES[head],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": w.n, "p": w.p, "lambda0": round(lam0, 6),
                    "tol": tol, "precision": head},
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
         "roofline": roof,
-        "whole_solve": whole_solve_roofline(w.n, w.p, head, r.stats, ms),
+        "whole_solve": whole_solve_roofline(w.n, w.p, head, r.stats, ms) if not FORMS[head][1] else None,
         "tuning": tunes or None,
         "kernels": kernels,
         "stats": {k: r.stats[k] for k in ("total_outer", "max_outer", "total_sweeps",
@@ -547,7 +554,8 @@ def main():
                       "ms_per_solve_one_call_at_a_time": {k: round(v, 4) for k, v in ms2_sync.items()},
                       "phases_ms": {k: round(v, 4) for k, v in ph2.items()},
                       "kernels_ms": {k: round(v["ms_per_solve"], 5) for k, v in kern2.items()}}
-        line[prec]["whole_solve"] = whole_solve_roofline(w.n, w.p, prec, r2.stats, ms2)
+        line[prec]["whole_solve"] = (whole_solve_roofline(w.n, w.p, prec, r2.stats, ms2)
+                                     if not FORMS[prec][1] else None)
         line["speedup_vs_" + prec] = round(ms2 / ms, 3)
     if not args.no_cpu:
         line["errors_vs_oracle"] = errors_vs_oracle(X_np, lam0, outs)

@@ -128,7 +128,7 @@ typedef struct {
     int32_t precision;   /* SPMESL_FP64 | SPMESL_FP32 | SPMESL_MIXED */
     int32_t output_scale;/* SPMESL_SCALE_ORIGINAL | SPMESL_SCALE_STANDARDIZED */
     int32_t flags;       /* SPMESL_FLAG_TIMING | SPMESL_FLAG_EAGER |
-                            SPMESL_FLAG_FULL_KKT */
+                            SPMESL_FLAG_FULL_KKT | SPMESL_FLAG_DATA_FORM */
 } spmesl_options;
 
 #define SPMESL_FLAG_TIMING 1
@@ -142,6 +142,14 @@ typedef struct {
  * column when the change of its gradient since the float solve is provably
  * smaller than the float near-threshold band.  Slower; the same minimiser. */
 #define SPMESL_FLAG_FULL_KKT 4
+/* The data form of Algorithm 3 (double precision only): no p x p S is
+ * formed.  Every column is solved by the dense tier with the standardised
+ * data as its source of S: groups of 16 columns, S restricted to the union V
+ * of the group's working sets formed from the data, blocked sweeps on V, and
+ * the full gradient X^T (x_k - X_V beta) / n for the KKT check.  Memory grows
+ * with n p, not p^2, so it serves p beyond what an S fits (and n << p).  A
+ * group whose V would exceed 256 variables fails with SPMESL_EWORKSET. */
+#define SPMESL_FLAG_DATA_FORM 8
 
 typedef struct {
     /* host-side counters filled by a solve */
@@ -260,6 +268,10 @@ typedef struct {
                                  1, 2 or 4 (default: the most that fit LDS) */
     int32_t screen_permille;  /* first working sets {j : |s_jk| > f lambda0 +
                                  tol}, f in thousandths (default 800) */
+    int32_t fill_split;       /* where the zero fill of the dense outputs runs:
+                                 0 both beside the covariance kernel (default),
+                                 1 Omega's after the row-tiled KKT pass, 2 both
+                                 after it */
 } spmesl_tuning;
 
 /* Set (NULL: reset to the defaults) or read the context's launch shapes. */
@@ -271,7 +283,8 @@ int spmesl_get_tuning(const spmesl_ctx *ctx, spmesl_tuning *t);
  * a candidate must be at least 1% faster to be kept) over the candidate values
  * of each field in turn (coordinate search from the current shapes: screen
  * 700/800/900/1000, KKT rows 4/2/1 as they fit, fill 32/64/128/256
- * workgroups, dense block 16/32/64 when the problem reaches the dense tier),
+ * workgroups, fill placement 0/1/2, dense block 16/32/64 when the problem
+ * reaches the dense tier),
  * keeps the fastest, sets it on the context and writes it to *best (host,
  * may be NULL) with its time per solve in *ms_best (host, may be NULL).  The
  * outputs in `res` hold the last solve's result.  Allocates (workspace,

@@ -68,6 +68,7 @@ struct Tune {
     int fill_blocks = kFillBlocks;
     int kkt_rows = 0;  // 0: the most that fit
     int screen_permille = kScreenPermille;
+    int fill_split = 0;
 };
 Tune resolve_tune(const spmesl_tuning &t)
 {
@@ -76,6 +77,7 @@ Tune resolve_tune(const spmesl_tuning &t)
     if (t.fill_blocks > 0) u.fill_blocks = t.fill_blocks;
     if (t.kkt_rows > 0) u.kkt_rows = t.kkt_rows;
     if (t.screen_permille > 0) u.screen_permille = t.screen_permille;
+    u.fill_split = t.fill_split;
     return u;
 }
 
@@ -91,6 +93,10 @@ struct Plan {
     // the dense tier: queues, result offsets into the pools, workspace
     size_t dq, dq64, woff, woff64, dmark, dv, dvold, dr, dbd, dbp, dsk, dsvv, de;
     int64_t pool_cap = 0, svv_cap = 0;
+    // the data form (no S): workgroups of its dense tier and rows of V each
+    bool data = false;
+    int dgroups = 1;
+    int64_t dvcap = 0;
     size_t total = 0;
 };
 
@@ -104,8 +110,61 @@ struct Bump {
     }
 };
 
-Plan make_plan(int64_t n, int64_t p, int prec)
+// The data form (SPMESL_FLAG_DATA_FORM, double): no S.  The standardised
+// data Xt, the per-column lists, and the dense tier's workspace for
+// kDataGroups workgroups whose V holds up to kDataVcap rows.
+constexpr int kDataGroups = 128;
+constexpr int64_t kDataVcap = 256;
+
+Plan make_plan_data(int64_t n, int64_t p)
 {
+    Plan L;
+    L.n = n;
+    L.p = p;
+    L.prec = SPMESL_FP64;
+    L.data = true;
+    L.rchunks = colstats_rchunks(n, p);
+    L.npad = (n + 63) / 64 * 64;
+    const size_t P = (size_t)p, N = (size_t)n;
+    const int64_t groups = (p + 15) / 16;
+    L.dgroups = (int)(groups < kDataGroups ? groups : kDataGroups);
+    L.dvcap = p < kDataVcap ? p : kDataVcap;
+    const size_t G = (size_t)L.dgroups, VC = (size_t)L.dvcap;
+    Bump b;
+    L.mean = b.take(8 * P);
+    L.scale = b.take(8 * P);
+    L.partial = b.take(16 * (size_t)L.rchunks * P);
+    L.xt = b.take(8 * N * P);
+    L.hi = b.take(2 * (size_t)L.npad * P);
+    L.lo = b.take(2 * (size_t)L.npad * P);
+    L.pool_cap = std::min<int64_t>(p * p, 32 * p + 65536);
+    const size_t lists = P * kWMax + (size_t)L.pool_cap;
+    L.wcnt = b.take(4 * P);
+    L.widx = b.take(4 * lists);
+    L.wbeta = b.take(8 * lists);
+    L.woff = b.take(4 * P);
+    L.sigma = b.take(8 * P);
+    L.lam = b.take(8 * P);
+    L.cstat = b.take(4 * P);
+    L.colinfo = b.take(16 * P);
+    L.pendcnt = b.take(4 * P);
+    L.dmark = b.take(4 * G * P);
+    L.dv = b.take(4 * G * VC);
+    L.dvold = b.take(4 * G * VC);
+    L.dr = b.take(8 * 16 * G * VC);
+    L.dbd = b.take(8 * 16 * G * VC);
+    L.dbp = b.take(8 * 16 * G * VC);
+    L.dsk = b.take(8 * 16 * G * VC);
+    L.svv_cap = L.dvcap;
+    L.dsvv = b.take(8 * G * VC * VC);
+    L.de = b.take(8 * 16 * N * G);
+    L.total = b.cur;
+    return L;
+}
+
+Plan make_plan(int64_t n, int64_t p, int prec, bool data = false)
+{
+    if (data) return make_plan_data(n, p);
     Plan L;
     L.n = n;
     L.p = p;
@@ -339,6 +398,7 @@ static void key_tuning(KeyBuf &k, const spmesl_tuning &t)
     k.add(t.fill_blocks);
     k.add(t.kkt_rows);
     k.add(t.screen_permille);
+    k.add(t.fill_split);
 }
 
 static void key_options(KeyBuf &k, const spmesl_options &o)
@@ -350,7 +410,7 @@ static void key_options(KeyBuf &k, const spmesl_options &o)
     k.add(o.max_rounds);
     k.add(o.precision);
     k.add(o.output_scale);
-    k.add(o.flags & SPMESL_FLAG_FULL_KKT);
+    k.add(o.flags & (SPMESL_FLAG_FULL_KKT | SPMESL_FLAG_DATA_FORM));
 }
 
 // Records the per-launch events of a timed solve; a null Marker records
@@ -439,6 +499,8 @@ static int validate(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
         return fail(ctx, SPMESL_EINVAL, "unknown precision");
     if (opt->output_scale != SPMESL_SCALE_ORIGINAL && opt->output_scale != SPMESL_SCALE_STANDARDIZED)
         return fail(ctx, SPMESL_EINVAL, "unknown output_scale");
+    if ((opt->flags & SPMESL_FLAG_DATA_FORM) && opt->precision != SPMESL_FP64)
+        return fail(ctx, SPMESL_EINVAL, "the data form runs in SPMESL_FP64 only");
     return SPMESL_OK;
 }
 
@@ -446,19 +508,24 @@ static int validate(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
 // forked onto the context's second stream at a point where the main stream
 // leaves HBM to it (chosen per form by the caller), and the scatter waits
 // for it.
-static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p, hipStream_t s, Marker *mk)
+// `which`: 1 fills B, 2 fills Omega (a solve may fork twice; the second
+// fork's join covers both, the second stream being in order).
+static int fork_output_fill(spmesl_ctx *ctx, const spmesl_result *res, int64_t p, hipStream_t s, Marker *mk,
+                            int which = 3)
 {
     const int fb = resolve_tune(ctx->tune).fill_blocks;
-    if (!res->B && !res->Omega) return SPMESL_OK;
+    double *B = (which & 1) ? res->B : nullptr;
+    double *Om = (which & 2) ? res->Omega : nullptr;
+    if (!B && !Om) return SPMESL_OK;
     HIPTRY(ctx, hipEventRecord(ctx->fork, s));
     HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork, 0));
     mark(mk, ctx->side, nullptr);
-    if (res->B) {
-        launch_fill_zero(res->B, p * p, ctx->side, fb);
+    if (B) {
+        launch_fill_zero(B, p * p, ctx->side, fb);
         mark(mk, ctx->side, "fill_B");
     }
-    if (res->Omega) {
-        launch_fill_zero(res->Omega, p * p, ctx->side, fb);
+    if (Om) {
+        launch_fill_zero(Om, p * p, ctx->side, fb);
         mark(mk, ctx->side, "fill_Omega");
     }
     HIPTRY(ctx, hipEventRecord(ctx->join, ctx->side));
@@ -504,6 +571,7 @@ static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &
     d.R = (T *)(ws + L.dr);
     d.Bd = (T *)(ws + L.dbd);
     d.Bp = (T *)(ws + L.dbp);
+    d.vcap = L.p;
     d.sk = (T *)(ws + L.dsk);
     d.counters = a.counters;
     d.flags = a.flags;
@@ -630,10 +698,14 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
 
 // Enqueue one full solve.  ws: workspace base laid out by `L`; dctl: this
 // problem's control block.  Records the phase events when `ev` is non-null.
+static int enqueue_data_form(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
+                             const spmesl_result *res, const Plan &L, char *ws, Ctl *dctl, hipEvent_t *ev);
+
 static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
                          const spmesl_result *res, const Plan &L, char *ws, Ctl *dctl,
                          hipEvent_t *ev)
 {
+    if (L.data) return enqueue_data_form(ctx, prob, opt, res, L, ws, dctl, ev);
     hipStream_t s = ctx->stream;
     const int64_t n = prob->n, p = prob->p;
     const int max_outer = opt->max_outer > 0 ? opt->max_outer : 1000;
@@ -676,10 +748,13 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     // of writes beside them.  Measured at p = 5000, mixed: 0.262 ms per solve
     // against 0.269 with the fill after the row-tiled KKT pass (which left the
     // polish at 52-57 us instead of 36) and 0.311 with it under the column
-    // solves at a low rate (the KKT pass doubled).
-    const bool fill_early = true;
-    if (fill_early) {
-        const int v0 = fork_output_fill(ctx, res, p, s, mk);
+    // solves at a low rate (the KKT pass doubled).  The launch shape
+    // fill_split moves Omega's fill (1) or both (2) after the row-tiled KKT
+    // pass instead.
+    const int early = tu.fill_split == 0 ? 3 : (tu.fill_split == 1 ? 1 : 0);
+    const int late = 3 & ~early;
+    if (early) {
+        const int v0 = fork_output_fill(ctx, res, p, s, mk, early);
         if (v0 != SPMESL_OK) return v0;
     }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
@@ -716,7 +791,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
 
 
     const bool fill = res->B || res->Omega;
-    auto fork = [&] { return fill_early ? (int)SPMESL_OK : fork_output_fill(ctx, res, p, s, mk); };
+    auto fork = [&] { return late ? fork_output_fill(ctx, res, p, s, mk, late) : (int)SPMESL_OK; };
     // a warm start: the columns' stored state from B0 and sigma0 (in the
     // scale of the outputs), which the first solves resume from
     const bool warm = prob->B0 || prob->sigma0;
@@ -815,6 +890,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         d.R = (double *)(ws + L.dr);
         d.Bd = (double *)(ws + L.dbd);
         d.Bp = (double *)(ws + L.dbp);
+        d.vcap = L.p;
         d.sk = (double *)(ws + L.dsk);
         d.Svv = (double *)(ws + L.dsvv);
         d.svv_cap = L.svv_cap;
@@ -867,6 +943,124 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
                                        (const double *)(ws + L.wbeta64), (const int *)(ws + L.woff64),
                                        (const double *)(ws + L.sigma64), scale, original, res->B,
                                        res->sigma, res->Omega, &dctl->flags, s);
+    mark(mk, s, "scatter");
+    HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join2, 0));
+    if (ev) HIPTRY(ctx, hipEventRecord(ev[5], s));
+    HIPTRY(ctx, hipGetLastError());
+    return SPMESL_OK;
+}
+
+// The data form (SPMESL_FLAG_DATA_FORM): Algorithm 3 with E = X_K - X_V B
+// instead of S.  Every column runs through the dense tier (dense.hip) with
+// the standardised data as its source of S: groups of 16 columns, S[V, V]
+// formed per group from the data (V = the union of the group's working sets),
+// the blocked covariance-form sweeps on V, and the full gradient g = X^T E / n
+// for the KKT check.  Memory is O(n p + groups |V|^2), never p^2.
+static int enqueue_data_form(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
+                             const spmesl_result *res, const Plan &L, char *ws, Ctl *dctl, hipEvent_t *ev)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t n = prob->n, p = prob->p;
+    const int max_outer = opt->max_outer > 0 ? opt->max_outer : 1000;
+    const int max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 100000;
+    const int max_rounds = opt->max_rounds > 0 ? opt->max_rounds : 64;
+    double *mean = (double *)(ws + L.mean);
+    double *scale = (double *)(ws + L.scale);
+    const int original = opt->output_scale == SPMESL_SCALE_ORIGINAL;
+    const Tune tu = resolve_tune(ctx->tune);
+    if (ev) HIPTRY(ctx, hipEventRecord(ev[0], s));
+    Marker marker(ctx);
+    Marker *mk = ev ? &marker : nullptr;
+    mark(mk, s, nullptr);
+    launch_zero_words((uint32_t *)dctl, sizeof(Ctl) / 4, s);
+    mark(mk, s, "zero_control");
+    if (!launch_stats_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt), (uint16_t *)(ws + L.hi),
+                            (uint16_t *)(ws + L.lo), L.npad, &dctl->flags, (int *)(ws + L.pendcnt), s)) {
+        launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
+                        &dctl->flags, (int *)(ws + L.pendcnt), s);
+        launch_standardize_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
+                                 (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
+    }
+    mark(mk, s, "standardize");
+    const int v0 = fork_output_fill(ctx, res, p, s, mk);
+    if (v0 != SPMESL_OK) return v0;
+    if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
+    if (ev) HIPTRY(ctx, hipEventRecord(ev[2], s));
+    const bool warm = prob->B0 || prob->sigma0;
+    if (warm) {
+        launch_warm_start<double>(prob->B0, prob->sigma0, p, scale, original, opt->lambda0, (int *)(ws + L.wcnt),
+                                  (int *)(ws + L.widx), (double *)(ws + L.wbeta), (double *)(ws + L.sigma),
+                                  (double *)(ws + L.lam), (int *)(ws + L.cstat), s);
+        mark(mk, s, "warm_start");
+    }
+    DenseArgs<double> d{};
+    d.S = nullptr;
+    d.Xt = (const double *)(ws + L.xt);
+    d.n = n;
+    d.p = p;
+    d.pv = p;
+    d.lambda0 = opt->lambda0;
+    d.tol = opt->tol;
+    d.kkt_tol = opt->tol;
+    d.max_outer = max_outer;
+    d.max_sweeps = max_sweeps;
+    d.max_rounds = max_rounds;
+    d.block = tu.dense_block;
+    d.queue = nullptr;
+    d.qcnt = nullptr;
+    d.ncols = p;
+    d.w_cnt = (int *)(ws + L.wcnt);
+    d.w_idx = (int *)(ws + L.widx);
+    d.w_beta = (double *)(ws + L.wbeta);
+    d.w_off = (int *)(ws + L.woff);
+    d.sigma = (double *)(ws + L.sigma);
+    d.lam_used = (double *)(ws + L.lam);
+    d.col_status = (int *)(ws + L.cstat);
+    d.pool_cnt = &dctl->pool;
+    d.pool_cap = L.pool_cap;
+    d.band_cnt = nullptr;
+    d.info = (int *)(ws + L.colinfo);
+    d.info_stride = 4;
+    d.mark = (int *)(ws + L.dmark);
+    d.V = (int *)(ws + L.dv);
+    d.Vold = (int *)(ws + L.dvold);
+    d.R = (double *)(ws + L.dr);
+    d.Bd = (double *)(ws + L.dbd);
+    d.Bp = (double *)(ws + L.dbp);
+    d.sk = (double *)(ws + L.dsk);
+    d.vcap = L.dvcap;
+    d.Svv = (double *)(ws + L.dsvv);
+    d.svv_cap = L.svv_cap;
+    d.E = (double *)(ws + L.de);
+    d.counters = dctl->counters;
+    d.flags = &dctl->flags;
+    DenseSrc<double> src{};
+    if (warm) {
+        src.cnt = d.w_cnt;
+        src.idx = d.w_idx;
+        src.beta = d.w_beta;
+        src.off = d.w_off;
+        src.sigma = d.sigma;
+    }
+    // the per-column counters start at zero (the tier adds to them)
+    launch_zero_words((uint32_t *)(ws + L.colinfo), 4 * p, s);
+    launch_dense<double, double>(d, src, s, L.dgroups);
+    mark(mk, s, "dense_data_form");
+    if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
+    HIPTRY(ctx, hipEventRecord(ctx->fork2, s));
+    HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork2, 0));
+    mark(mk, ctx->side, nullptr);
+    launch_reduce_stats(p, (const int *)(ws + L.colinfo), nullptr, (const int *)(ws + L.wcnt),
+                        (const int *)(ws + L.cstat), dctl->counters, &dctl->status1, ctx->side);
+    mark(mk, ctx->side, "reduce_stats");
+    HIPTRY(ctx, hipEventRecord(ctx->join2, ctx->side));
+    if (ev) HIPTRY(ctx, hipEventRecord(ev[4], s));
+    if (res->B || res->Omega) HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join, 0));
+    mark(mk, s, "wait_fill");
+    launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
+                                   (const double *)(ws + L.wbeta), (const int *)(ws + L.woff),
+                                   (const double *)(ws + L.sigma), scale, original, res->B, res->sigma, res->Omega,
+                                   &dctl->flags, s);
     mark(mk, s, "scatter");
     HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join2, 0));
     if (ev) HIPTRY(ctx, hipEventRecord(ev[5], s));
@@ -1030,7 +1224,8 @@ int spmesl_workspace_size(const spmesl_problem *prob, const spmesl_options *opt,
     int v = validate(nullptr, prob, opt);
     if (v != SPMESL_OK) return v;
     // the plan, then the control block spmesl_solve places after it
-    *bytes = align_up(make_plan(prob->n, prob->p, opt->precision).total, 256) + sizeof(Ctl);
+    *bytes = align_up(make_plan(prob->n, prob->p, opt->precision, opt->flags & SPMESL_FLAG_DATA_FORM).total, 256) +
+             sizeof(Ctl);
     return SPMESL_OK;
 }
 
@@ -1063,7 +1258,7 @@ int spmesl_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_optio
     int v = validate(ctx, prob, opt);
     if (v != SPMESL_OK) return v;
     DevGuard g(ctx->device);
-    Plan L = make_plan(prob->n, prob->p, opt->precision);
+    Plan L = make_plan(prob->n, prob->p, opt->precision, opt->flags & SPMESL_FLAG_DATA_FORM);
     size_t ctl_off = align_up(L.total, 256);
     v = ensure_workspace(ctx, ctl_off + sizeof(Ctl));
     if (v != SPMESL_OK) return v;
@@ -1126,7 +1321,7 @@ int spmesl_solve_async(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl
     int v = validate(ctx, prob, opt);
     if (v != SPMESL_OK) return v;
     DevGuard g(ctx->device);
-    Plan L = make_plan(prob->n, prob->p, opt->precision);
+    Plan L = make_plan(prob->n, prob->p, opt->precision, opt->flags & SPMESL_FLAG_DATA_FORM);
     size_t ctl_off = align_up(L.total, 256);
     v = ensure_workspace(ctx, ctl_off + sizeof(Ctl));
     if (v != SPMESL_OK) return v;
@@ -1159,7 +1354,7 @@ int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     if (!ctx->scratch_dev)
         return fail(ctx, SPMESL_EHIP,
                     std::string("no device address for the scratch array: ") + hipGetErrorString(ctx->scratch_err));
-    const Plan L = make_plan(prob->n, prob->p, opt->precision);
+    const Plan L = make_plan(prob->n, prob->p, opt->precision, opt->flags & SPMESL_FLAG_DATA_FORM);
     const size_t ctl_off = align_up(L.total, 256);
     if (ctl_off + sizeof(Ctl) > (size_t)SPMESL_NOALLOC_SCRATCH_BYTES)
         return fail(ctx, SPMESL_ENOMEM,
@@ -1194,6 +1389,7 @@ int spmesl_set_tuning(spmesl_ctx *ctx, const spmesl_tuning *t)
     if (t->kkt_rows < 0 || t->kkt_rows > 4) return fail(ctx, SPMESL_EINVAL, "kkt_rows must be in 0 .. 4");
     if (t->screen_permille < 0 || t->screen_permille > 4000)
         return fail(ctx, SPMESL_EINVAL, "screen_permille must be in 0 .. 4000");
+    if (t->fill_split < 0 || t->fill_split > 2) return fail(ctx, SPMESL_EINVAL, "fill_split must be 0, 1 or 2");
     ctx->tune = *t;
     return SPMESL_OK;
 }
@@ -1252,6 +1448,7 @@ int spmesl_autotune(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
     cur.dense_block = d.dense_block;
     cur.fill_blocks = d.fill_blocks;
     cur.screen_permille = d.screen_permille;
+    cur.fill_split = d.fill_split;
     const size_t tsz = opt->precision == SPMESL_FP64 ? 8 : 4;
     const int rj_max = kkt_rows_per_block(prob->p, tsz, (size_t)160 * 1024);
     cur.kkt_rows = d.kkt_rows > 0 && d.kkt_rows < rj_max ? d.kkt_rows : rj_max;
@@ -1291,6 +1488,7 @@ int spmesl_autotune(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
         if ((v = search(&spmesl_tuning::kkt_rows, kr)) != SPMESL_OK) return v;
     }
     if ((v = search(&spmesl_tuning::fill_blocks, {32, 64, 128, 256})) != SPMESL_OK) return v;
+    if ((v = search(&spmesl_tuning::fill_split, {0, 1, 2})) != SPMESL_OK) return v;
     if (dense && (v = search(&spmesl_tuning::dense_block, {16, 32, 64})) != SPMESL_OK) return v;
     ctx->tune = cur;
     // the outputs hold a solve with the chosen shapes
@@ -1318,7 +1516,7 @@ int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
             ctx->err = "problem " + std::to_string(i) + ": " + ctx->err;
             return v;
         }
-        plans[(size_t)i] = make_plan(probs[i].n, probs[i].p, opt->precision);
+        plans[(size_t)i] = make_plan(probs[i].n, probs[i].p, opt->precision, opt->flags & SPMESL_FLAG_DATA_FORM);
         need = std::max(need, plans[(size_t)i].total);
     }
     size_t ctl_off = align_up(need, 256);

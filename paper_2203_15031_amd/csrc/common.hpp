@@ -235,7 +235,8 @@ void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s);
 // dense.hip): where their start comes from ...
 template <typename TS>
 struct DenseSrc {
-    const int *cnt;       // [p] start-list lengths (> kWMax: the list is in the pool at off[k])
+    const int *cnt;       // [p] start-list lengths (> kWMax: the list is in the pool at off[k]);
+                          // null: every column starts from beta = 0 (and sigma = 1 without `sigma`)
     const int *idx;       // lists: column k at k * kWMax, or at p * kWMax + off[k]
     const TS *beta;
     const int *off;       // [p] pool offsets (read only for lists longer than kWMax)
@@ -253,8 +254,9 @@ struct DenseArgs {
     T lambda0, tol, kkt_tol;
     int max_outer, max_sweeps, max_rounds;
     int block;            // b: rows per block of the delayed update (16 .. 64)
-    const int *queue;     // columns queue[0 .. *qcnt)
+    const int *queue;     // columns queue[0 .. *qcnt), or (null) the columns 0 .. ncols - 1
     const int *qcnt;
+    int64_t ncols;
     int *w_cnt, *w_idx;   // results: nonzeros in ascending order, at k * kWMax,
     T *w_beta;            // or (more than kWMax) at p * kWMax + w_off[k] in the pool
     int *w_off;
@@ -265,16 +267,20 @@ struct DenseArgs {
     int *band_cnt;        // null, or set to kBandMax + 1 (the polish takes its full pass)
     int *info;            // per-column counters (stride 4: outer, sweeps, updates,
     int info_stride;      // KKT passes; stride 8 adds the rows added), accumulated
-    int *mark, *V, *Vold; // [p] workspace
-    T *R, *Bd, *Bp, *sk;  // [p * 16] workspace
-    double *Svv;          // [svv_cap^2] workspace of the data source
+    // workspace, one slice per workgroup (workgroup w takes the groups w,
+    // w + G, ... of the G launched):
+    int *mark;            // [p] per slice
+    int *V, *Vold;        // [vcap] per slice
+    T *R, *Bd, *Bp, *sk;  // [vcap * 16] per slice
+    int64_t vcap;         // the most rows V may hold (a group beyond it fails)
+    double *Svv;          // [svv_cap^2] per slice (data source)
     int64_t svv_cap;
-    double *E;            // [16 * n] workspace of the data source
+    double *E;            // [16 * n] per slice (data source)
     unsigned long long *counters;
     const int *flags;
 };
 template <typename T, typename TS>
-void launch_dense(const DenseArgs<T> &a, const DenseSrc<TS> &src, hipStream_t s);
+void launch_dense(const DenseArgs<T> &a, const DenseSrc<TS> &src, hipStream_t s, int blocks = 1);
 
 // Warm start of the column solves from a caller's B0 (p x p row-major,
 // column k = beta of response k) and sigma0 (p), on the standardised scale or

@@ -294,25 +294,44 @@ __device__ void kkt_all(const DenseArgs<T> &A, DenseSm<T> &sm, int nv, int m)
 }
 
 template <typename T, typename TS, bool DATA>
-__global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
+__global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A0, DenseSrc<TS> src)
 {
     __shared__ DenseSm<T> sm;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    if (*A.flags) return;
-    const int64_t p = A.p;
-    const int q = *A.qcnt;
-    if (q <= 0) return;
+    if (*A0.flags) return;
+    const int64_t p = A0.p;
+    // the queue, or (no queue) the columns 0 .. ncols - 1
+    const int q = A0.queue ? *A0.qcnt : (int)A0.ncols;
+    if (q <= 0 || (int64_t)blockIdx.x * kDW >= q) return;
+    // this workgroup's slice of the workspace
+    DenseArgs<T> A = A0;
+    {
+        const int64_t bi = blockIdx.x, vc = A0.vcap;
+        A.mark += bi * p;
+        A.V += bi * vc;
+        A.Vold += bi * vc;
+        A.R += bi * vc * kDW;
+        A.Bd += bi * vc * kDW;
+        A.Bp += bi * vc * kDW;
+        A.sk += bi * vc * kDW;
+        if (DATA) {
+            A.Svv += bi * A0.svv_cap * A0.svv_cap;
+            A.E += bi * (int64_t)kDW * A0.n;
+        }
+    }
+    // V may hold vcap rows (and, from the data, svv_cap)
+    const int64_t vlim = DATA && A.svv_cap < A.vcap ? A.svv_cap : A.vcap;
     for (int64_t j = tid; j < p; j += kDT) A.mark[j] = 0;
     __syncthreads();
     const int b = A.block < 16 ? 16 : (A.block > kBMax ? kBMax : A.block);
-    for (int g0 = 0; g0 < q; g0 += kDW) {
+    for (int g0 = (int)blockIdx.x * kDW; g0 < q; g0 += (int)gridDim.x * kDW) {
         const int m = q - g0 < kDW ? q - g0 : kDW;
         // --- the group's columns and their start --------------------------
         if (tid < kDW) {
             const int c = tid;
-            sm.ck[c] = c < m ? A.queue[g0 + c] : 0;
+            sm.ck[c] = c < m ? (A.queue ? A.queue[g0 + c] : g0 + c) : 0;
             const int64_t k = sm.ck[c];
-            double sg = c < m ? src.sigma[k] : 1.0;
+            double sg = c < m && src.sigma ? src.sigma[k] : 1.0;
             sg = sg > 0.0 && sg < 1e300 ? sg : 1.0;
             sm.sig[c] = (T)sg;
             sm.lam[c] = (T)sg * A.lambda0;
@@ -327,7 +346,7 @@ __global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
         // mark the start lists (and pending candidates) of the group's columns
         for (int c = wv; c < m; c += kNW) {
             const int64_t k = sm.ck[c];
-            int cnt = src.cnt[k];
+            int cnt = src.cnt ? src.cnt[k] : 0;
             cnt = cnt < 0 ? 0 : cnt;
             const int64_t base = cnt > kWMax ? p * (int64_t)kWMax + src.off[k] : k * (int64_t)kWMax;
             for (int i = lane; i < cnt; i += kWave) {
@@ -345,16 +364,18 @@ __global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
         }
         __syncthreads();
         int nv = build_v(A, sm);
-        if (DATA && (int64_t)nv > A.svv_cap) {
-            // S[V, V] does not fit its buffer: the group fails (rare)
+        bool gfail = false;
+        if ((int64_t)nv > vlim) {
+            // V does not fit this workgroup's buffers: the group fails (rare)
             if (tid < m) sm.status[tid] = kColWorkset, sm.state[tid] = kDFail;
+            gfail = true;
             nv = 0;
         }
         for (int64_t e = tid; e < (int64_t)nv * kDW; e += kDT) A.Bd[e] = T(0);
         __syncthreads();
         for (int c = wv; c < m && nv > 0; c += kNW) {
             const int64_t k = sm.ck[c];
-            int cnt = src.cnt[k];
+            int cnt = src.cnt ? src.cnt[k] : 0;
             cnt = cnt < 0 ? 0 : cnt;
             const int64_t base = cnt > kWMax ? p * (int64_t)kWMax + src.off[k] : k * (int64_t)kWMax;
             for (int i = lane; i < cnt; i += kWave) {
@@ -374,7 +395,7 @@ __global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
             for (;;) {
                 bool any = false;
                 for (int c = 0; c < kDW; ++c) any |= sm.state[c] == kDSweep;
-                if (!any || nv == 0) break;
+                if (!any) break;
                 T maxd[kCPW];
 #pragma unroll
                 for (int u = 0; u < kCPW; ++u) maxd[u] = T(0);
@@ -559,7 +580,7 @@ __global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
             // --- KKT over all p rows -----------------------------------------
             bool any_done = false;
             for (int c = 0; c < m; ++c) any_done |= sm.state[c] == kDDone;
-            if (!any_done || nv == 0) break;
+            if (!any_done || gfail) break;
             if (tid == 0) sm.viol = 0;
             __syncthreads();
             kkt_all<T, DATA>(A, sm, nv, m);
@@ -596,8 +617,9 @@ __global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
                 sm.added[tid] += nv - nv_old;
                 sm.have[tid] = 0;  // B moved: the secant needs two fresh updates again
             }
-            if (DATA && (int64_t)nv > A.svv_cap) {
+            if ((int64_t)nv > vlim) {
                 if (tid < m) sm.status[tid] = kColWorkset, sm.state[tid] = kDFail;
+                gfail = true;
                 nv = 0;
             }
             for (int64_t e = tid; e < (int64_t)nv * kDW; e += kDT) A.Bd[e] = T(0);
@@ -608,7 +630,7 @@ __global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
                 if (v != T(0)) A.Bd[(int64_t)v_pos(A.V, nv, A.Vold[a]) * kDW + c] = v;
             }
             __syncthreads();
-            if (nv == 0) break;
+            if (gfail) break;
         }
         // --- results: the nonzeros of each column, ascending ---------------
         for (int c = wv; c < m; c += kNW) {
@@ -677,19 +699,19 @@ __global__ __launch_bounds__(kDT) void k_dense(DenseArgs<T> A, DenseSrc<TS> src)
 } // namespace
 
 template <typename T, typename TS>
-void launch_dense(const DenseArgs<T> &a, const DenseSrc<TS> &src, hipStream_t s)
+void launch_dense(const DenseArgs<T> &a, const DenseSrc<TS> &src, hipStream_t s, int blocks)
 {
     if constexpr (sizeof(T) == 8) {
         if (a.Xt) {
-            hipLaunchKernelGGL((k_dense<T, TS, true>), dim3(1), dim3(kDT), 0, s, a, src);
+            hipLaunchKernelGGL((k_dense<T, TS, true>), dim3(blocks), dim3(kDT), 0, s, a, src);
             return;
         }
     }
-    hipLaunchKernelGGL((k_dense<T, TS, false>), dim3(1), dim3(kDT), 0, s, a, src);
+    hipLaunchKernelGGL((k_dense<T, TS, false>), dim3(blocks), dim3(kDT), 0, s, a, src);
 }
 
-template void launch_dense<double, double>(const DenseArgs<double> &, const DenseSrc<double> &, hipStream_t);
-template void launch_dense<float, float>(const DenseArgs<float> &, const DenseSrc<float> &, hipStream_t);
-template void launch_dense<double, float>(const DenseArgs<double> &, const DenseSrc<float> &, hipStream_t);
+template void launch_dense<double, double>(const DenseArgs<double> &, const DenseSrc<double> &, hipStream_t, int);
+template void launch_dense<float, float>(const DenseArgs<float> &, const DenseSrc<float> &, hipStream_t, int);
+template void launch_dense<double, float>(const DenseArgs<double> &, const DenseSrc<float> &, hipStream_t, int);
 
 } // namespace spmesl

@@ -31,6 +31,7 @@ SCALE_ORIGINAL, SCALE_STANDARDIZED = 0, 1
 FLAG_TIMING = 1
 FLAG_EAGER = 2
 FLAG_FULL_KKT = 4
+FLAG_DATA_FORM = 8
 MAX_WORKING_SET = 128
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -72,7 +73,7 @@ class Stats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("dense_block", C.c_int32), ("fill_blocks", C.c_int32), ("kkt_rows", C.c_int32),
-                ("screen_permille", C.c_int32)]
+                ("screen_permille", C.c_int32), ("fill_split", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -243,12 +244,12 @@ class Context:
 
     @staticmethod
     def options(lambda0, tol=1e-8, precision="fp64", output_scale="original", max_outer=0,
-                max_sweeps=0, max_rounds=0, timing=False, eager=False, full_kkt=False):
+                max_sweeps=0, max_rounds=0, timing=False, eager=False, full_kkt=False, data_form=False):
         return Options(float(lambda0), float(tol), int(max_outer), int(max_sweeps),
                        int(max_rounds), _PRECISION[precision] if isinstance(precision, str) else int(precision),
                        _SCALE[output_scale] if isinstance(output_scale, str) else int(output_scale),
                        (FLAG_TIMING if timing else 0) | (FLAG_EAGER if eager else 0)
-                       | (FLAG_FULL_KKT if full_kkt else 0))
+                       | (FLAG_FULL_KKT if full_kkt else 0) | (FLAG_DATA_FORM if data_form else 0))
 
     @staticmethod
     def problem(X):
@@ -267,7 +268,8 @@ class Context:
     # -- entry points -------------------------------------------------------
     def solve(self, X, lambda0, tol=1e-8, precision="fp64", output_scale="original",
               want=("B", "sigma", "Omega"), out=None, max_outer=0, max_sweeps=0, max_rounds=0,
-              timing=False, check=True, eager=False, full_kkt=False, B0=None, sigma0=None) -> SolveResult:
+              timing=False, check=True, eager=False, full_kkt=False, B0=None, sigma0=None,
+              data_form=False) -> SolveResult:
         """Full SPMESL of X (n x p float64 CUDA tensor).
 
         Returns B (p x p, column k = beta of response k), sigma (p) and the
@@ -278,9 +280,10 @@ class Context:
         full_kkt=True (mixed form) makes the double polish prove every column
         with a full KKT pass over S.  B0 (p x p) and sigma0 (p), float64 CUDA
         tensors in the scale of the outputs, warm-start the column solves
-        (either may be None)."""
+        (either may be None).  data_form=True (double only) solves without
+        forming S (Algorithm 3's data form)."""
         opt = self.options(lambda0, tol, precision, output_scale, max_outer, max_sweeps,
-                           max_rounds, timing, eager, full_kkt)
+                           max_rounds, timing, eager, full_kkt, data_form)
         prob, res, out, stats = self._prepare(X, opt, want, out)
         self._warm(prob, X, B0, sigma0)
         st = load().spmesl_solve(self._h, C.byref(prob), C.byref(opt), C.byref(res))
@@ -289,7 +292,7 @@ class Context:
         return SolveResult(out.get("B"), out.get("sigma"), out.get("Omega"), st, stats.as_dict())
 
     def solve_async(self, X, lambda0, status, tol=1e-8, precision="fp64", output_scale="original",
-                    want=("B", "sigma", "Omega"), out=None, eager=False) -> SolveResult:
+                    want=("B", "sigma", "Omega"), out=None, eager=False, data_form=False) -> SolveResult:
         """Enqueue a full solve on torch's current stream without waiting.
 
         `status` is a one-element int32 CUDA tensor that receives the status
@@ -298,7 +301,7 @@ class Context:
         not reported."""
         if status.dtype != torch.int32 or status.device != X.device or status.numel() < 1:
             raise ValueError("status must be an int32 tensor on the device of X")
-        opt = self.options(lambda0, tol, precision, output_scale, eager=eager)
+        opt = self.options(lambda0, tol, precision, output_scale, eager=eager, data_form=data_form)
         prob, res, out, _ = self._prepare(X, opt, want, out)
         st = load().spmesl_solve_async(self._h, C.byref(prob), C.byref(opt), C.byref(res),
                                        C.c_void_p(status.data_ptr()))
@@ -466,10 +469,11 @@ class Context:
             raise SpmeslError(st, self._err())
         return t.as_dict()
 
-    def autotune(self, X, lambda0, tol=1e-8, precision="fp64", output_scale="original", reps=5, out=None):
+    def autotune(self, X, lambda0, tol=1e-8, precision="fp64", output_scale="original", reps=5, out=None,
+                 data_form=False):
         """spmesl_autotune on this problem: returns (tuning dict, ms per solve);
         the context keeps the chosen shapes."""
-        opt = self.options(lambda0, tol, precision, output_scale)
+        opt = self.options(lambda0, tol, precision, output_scale, data_form=data_form)
         prob, res, out, _ = self._prepare(X, opt, ("B", "sigma", "Omega"), out)
         best = Tuning()
         ms = C.c_double()

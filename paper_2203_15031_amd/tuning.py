@@ -14,7 +14,7 @@ from __future__ import annotations
 import json
 import os
 
-FIELDS = ("dense_block", "fill_blocks", "kkt_rows", "screen_permille")
+FIELDS = ("dense_block", "fill_blocks", "kkt_rows", "screen_permille", "fill_split")
 
 
 def cache_path() -> str:

@@ -92,6 +92,20 @@ def test_blockar_p5000_every_column(ctx, blockar_full, prec, bar):
     assert rel_err(host(ro.sigma), ref["sigma"] / c) <= bar
 
 
+def test_blockar_p5000_data_form(ctx, blockar_full):
+    # the data form (no S) on every column of the p = 5000 workload
+    w, X, ref, S = blockar_full
+    r = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision="fp64", output_scale="standardized", data_form=True)
+    assert r.status == 0
+    B, sig, Om = host(r.B), host(r.sigma), host(r.Omega)
+    errs = dict(B=rel_err(B, ref["B"]), sigma=rel_err(sig, ref["sigma"]), Omega=rel_err(Om, ref["Omega"]))
+    _report("blockar p5000 data form", errs)
+    assert max(errs.values()) <= 1e-6, errs
+    mism, excl = support_mismatch(B, ref["B"], S, ref["sigma"], w.lambda0, 1e-6)
+    assert mism == 0, (mism, excl)
+    omega_invariants(Om, B)
+
+
 # ---------------------------------------------------------------------------
 # scale-free tree, p = 20000: sampled columns with their neighbours
 # ---------------------------------------------------------------------------

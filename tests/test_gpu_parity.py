@@ -497,7 +497,9 @@ def test_autotune_and_tuning(ctx, sp):
         assert t["fill_blocks"] in (32, 64, 128, 256) and t["screen_permille"] in (700, 800, 900, 1000)
         assert ctx.get_tuning() == t
         # every candidate shape gives the same minimiser
-        for shapes in (t, dict(t, kkt_rows=1, screen_permille=1000, fill_blocks=32)):
+        assert t["fill_split"] in (0, 1, 2)
+        for shapes in (t, dict(t, kkt_rows=1, screen_permille=1000, fill_blocks=32, fill_split=1),
+                       dict(t, fill_split=2)):
             ctx.set_tuning(shapes)
             r = ctx.solve(Xg, w.lambda0, tol=w.tol, precision="mixed")
             assert rel_err(host(r.Omega), ref["Omega"]) <= 1e-4
@@ -506,7 +508,7 @@ def test_autotune_and_tuning(ctx, sp):
         assert e.value.code == sp.EINVAL
     finally:
         ctx.set_tuning(None)
-    assert ctx.get_tuning() == dict(dense_block=0, fill_blocks=0, kkt_rows=0, screen_permille=0)
+    assert ctx.get_tuning() == dict(dense_block=0, fill_blocks=0, kkt_rows=0, screen_permille=0, fill_split=0)
 
 
 @pytest.mark.parametrize("b", [16, 64])
@@ -521,3 +523,35 @@ def test_dense_tier_block_sizes(ctx, b):
         _check_full(ctx, X, 0.03, "fp64", 1e-6, tol=1e-10, max_outer=200, max_sweeps=20000)
     finally:
         ctx.set_tuning(None)
+
+
+# ---------------------------------------------------------------------------
+# the data form (no S)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["ar1_n100_p200", "er_n200_p1000"])
+def test_data_form(ctx, name):
+    w = W.workload(name)
+    X = W.generate(w.name)
+    errs, st = _check_full(ctx, X, w.lambda0, "fp64", 1e-6, data_form=True)
+    assert st["columns_noconv"] == 0
+
+
+def test_data_form_n_much_smaller_than_p(ctx):
+    # n = 60, p = 700: the regime the data form is for (n << p)
+    rng = np.random.default_rng(21)
+    X = W.sample_from_cov(60, W.ar_cov(700, 0.5), rng)
+    lam = math.sqrt(2 * math.log(700) / 60)
+    _check_full(ctx, X, lam, "fp64", 1e-6, data_form=True)
+
+
+def test_data_form_options(ctx, sp):
+    w = W.workload("ar1_n100_p200")
+    X = gpu(W.generate(w.name))
+    with pytest.raises(sp.SpmeslError) as e:
+        ctx.solve(X, w.lambda0, precision="mixed", data_form=True)
+    assert e.value.code == sp.EINVAL
+    # a warm start in the data form, from the S form's result
+    cold = ctx.solve(X, w.lambda0, tol=w.tol, precision="fp64")
+    warm = ctx.solve(X, w.lambda0, tol=w.tol, precision="fp64", data_form=True, B0=cold.B, sigma0=cold.sigma)
+    assert rel_err(host(warm.Omega), host(cold.Omega)) <= 1e-6

@@ -106,7 +106,7 @@ def test_tuning_cache_roundtrip(tmp_path):
 
         def autotune(self, X, lam, tol, prec, reps=5):
             self.tuned += 1
-            return {"dense_block": 16, "fill_blocks": 128, "kkt_rows": 2, "screen_permille": 900}, 0.25
+            return {"dense_block": 16, "fill_blocks": 128, "kkt_rows": 2, "screen_permille": 900, "fill_split": 1}, 0.25
 
         def set_tuning(self, t):
             self.set = dict(t)
