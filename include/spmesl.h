@@ -244,12 +244,21 @@ int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob,
  * Solve `count` independent problems (uneven n, p) with the same options,
  * except that problem i uses lambda0s[i] when lambda0s (HOST array of count
  * doubles) is not NULL.  status[i] (host) receives each problem's code; the
- * return value is the first non-OK code, or SPMESL_OK.  The problems run one
- * after another on the context's stream, as one graph launch when the call
- * repeats the previous call's pointers, sizes and options. */
+ * return value is the first non-OK code, or SPMESL_OK.  The problems are
+ * dealt, largest first, to the lane with the least work (spmesl_tuning's
+ * batch_lanes lanes, default 1); each lane runs its problems one after
+ * another on a stream of its own, the lanes side by side, each lane as one
+ * graph launch when the call repeats the previous call's pointers, sizes
+ * and options.  The call returns when every lane is done (the context's
+ * stream waits for them). */
 int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                        const spmesl_options *opt, const double *lambda0s,
                        spmesl_result *res, int *status);
+/* Workspace (device bytes) spmesl_solve_batch needs for these problems with
+ * the context's current lanes (a region per lane, and a control block per
+ * problem). */
+int spmesl_batch_workspace_size(const spmesl_ctx *ctx, int count, const spmesl_problem *probs,
+                                const spmesl_options *opt, size_t *bytes);
 
 /* ---- launch shapes and the autotuner ------------------------------------ */
 
@@ -272,6 +281,9 @@ typedef struct {
                                  0 both beside the covariance kernel (default),
                                  1 Omega's after the row-tiled KKT pass, 2 both
                                  after it */
+    int32_t batch_lanes;      /* lanes (stream pairs) spmesl_solve_batch runs
+                                 its data sets on side by side, 1 .. 4
+                                 (default 1); not searched by the autotuner */
 } spmesl_tuning;
 
 /* Set (NULL: reset to the defaults) or read the context's launch shapes. */

@@ -1,6 +1,7 @@
 """Estimation quality of SPMESL, as the paper's simulation study measures it.
 
-Section 4.2 scores an estimate Omega-hat against the true precision matrix
+Section 4.1 defines, and Section 4.3 reports (Tables 3-4), scores of an
+estimate Omega-hat against the true precision matrix
 Omega0 by edge recovery over the pairs j < k (an edge is a nonzero entry):
 
     SEN  = TP / (TP + FN)             SPE = TN / (TN + FP)

@@ -73,7 +73,7 @@ class Stats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("dense_block", C.c_int32), ("fill_blocks", C.c_int32), ("kkt_rows", C.c_int32),
-                ("screen_permille", C.c_int32), ("fill_split", C.c_int32)]
+                ("screen_permille", C.c_int32), ("fill_split", C.c_int32), ("batch_lanes", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -114,6 +114,9 @@ def load():
     lib.spmesl_solve.restype = C.c_int
     lib.spmesl_solve_batch.argtypes = [vp, C.c_int, C.POINTER(Problem), C.POINTER(Options),
                                        C.POINTER(C.c_double), C.POINTER(Result), C.POINTER(C.c_int)]
+    lib.spmesl_batch_workspace_size.argtypes = [vp, C.c_int, C.POINTER(Problem), C.POINTER(Options),
+                                                C.POINTER(C.c_size_t)]
+    lib.spmesl_batch_workspace_size.restype = C.c_int
     lib.spmesl_solve_async.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result), vp]
     lib.spmesl_solve_async.restype = C.c_int
     lib.spmesl_solve_noalloc.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result), vp]
@@ -388,8 +391,12 @@ class Context:
                 outs[i] = o
             ress[i] = Result(_ptr(o.get("B")).value, _ptr(o.get("sigma")).value,
                              _ptr(o.get("Omega")).value, C.pointer(stats[i]))
-            need = max(need, self.workspace_size(X, self.options(lams[i], tol, precision, output_scale)))
-        self._workspace(need + 4096 * (m + 1))
+        sz = C.c_size_t()
+        st = load().spmesl_batch_workspace_size(self._h, m, probs, C.byref(opt), C.byref(sz))
+        if st != OK:
+            raise SpmeslError(st, "batch_workspace_size")
+        need = sz.value
+        self._workspace(need + 4096)
         self._bind_stream()
         status = (C.c_int * max(m, 1))()
         st = load().spmesl_solve_batch(self._h, m, probs, C.byref(opt), lams, ress, status)

@@ -1,4 +1,4 @@
-"""GPU: the estimation-quality measures of Section 4.2 computed from the
+"""GPU: the estimation-quality measures (Section 4.1) computed from the
 library's Omega-hat equal those computed from the oracle's on the same data
 (the four networks of Section 4.1 at p = 100, lambda_univ), and the Table 3
 and 4 study runs end to end on a few datasets."""

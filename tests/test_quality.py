@@ -1,4 +1,4 @@
-"""Edge-recovery measures and Frobenius error of Section 4.2, pinned by hand
+"""Edge-recovery measures and Frobenius error (Section 4.1), pinned by hand
 counts on a small example, by their limiting cases, and the generators by
 the true edge counts the paper prints for its networks (Tables 3 and 4)."""
 import math
