@@ -296,13 +296,11 @@ def bench_batch(args, torch, spmesl, workloads):
     Xs = [torch.from_numpy(X).to("cuda:0") for X in Xs_np]
     lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs_np]
     ctx = spmesl.Context(0)
-    if args.batch_lanes:
-        ctx.set_tuning(dict(batch_lanes=args.batch_lanes))
     line = {"metric": "batched SPMESL data sets/s (64 hub data sets, p~U{256..4096}, n=ceil(p/2))",
             "unit": "datasets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
             "config": {"workload": "hub_batch64", "count": len(Xs), "sum_p": int(sum(X.shape[1] for X in Xs_np)),
-                       "tol": 1e-8, "lanes": ctx.get_tuning()["batch_lanes"] or 1}}
+                       "tol": 1e-8}}
     outs = [dict(B=torch.empty((X.shape[1], X.shape[1]), dtype=torch.float64, device="cuda:0"),
                  sigma=torch.empty((X.shape[1],), dtype=torch.float64, device="cuda:0"),
                  Omega=torch.empty((X.shape[1], X.shape[1]), dtype=torch.float64, device="cuda:0"))
@@ -447,8 +445,6 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batch-lanes", type=int, default=0,
-                    help="hub_batch64: lanes the batch runs on side by side (0: the library's default)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch shapes instead of the autotuner's")
     ap.add_argument("--forms", default="mixed,fp64",

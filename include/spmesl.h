@@ -148,7 +148,7 @@ typedef struct {
  * of the group's working sets formed from the data, blocked sweeps on V, and
  * the full gradient X^T (x_k - X_V beta) / n for the KKT check.  Memory grows
  * with n p, not p^2, so it serves p beyond what an S fits (and n << p).  A
- * group whose V would exceed 256 variables fails with SPMESL_EWORKSET. */
+ * group whose V would exceed 1024 variables fails with SPMESL_EWORKSET. */
 #define SPMESL_FLAG_DATA_FORM 8
 
 typedef struct {
@@ -244,19 +244,14 @@ int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob,
  * Solve `count` independent problems (uneven n, p) with the same options,
  * except that problem i uses lambda0s[i] when lambda0s (HOST array of count
  * doubles) is not NULL.  status[i] (host) receives each problem's code; the
- * return value is the first non-OK code, or SPMESL_OK.  The problems are
- * dealt, largest first, to the lane with the least work (spmesl_tuning's
- * batch_lanes lanes, default 1); each lane runs its problems one after
- * another on a stream of its own, the lanes side by side, each lane as one
- * graph launch when the call repeats the previous call's pointers, sizes
- * and options.  The call returns when every lane is done (the context's
- * stream waits for them). */
+ * return value is the first non-OK code, or SPMESL_OK.  The problems run one
+ * after another on the context's stream, as one graph launch when the call
+ * repeats the previous call's pointers, sizes and options. */
 int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                        const spmesl_options *opt, const double *lambda0s,
                        spmesl_result *res, int *status);
-/* Workspace (device bytes) spmesl_solve_batch needs for these problems with
- * the context's current lanes (a region per lane, and a control block per
- * problem). */
+/* Workspace (device bytes) spmesl_solve_batch needs for these problems (the
+ * largest problem's, and a control block per problem). */
 int spmesl_batch_workspace_size(const spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                                 const spmesl_options *opt, size_t *bytes);
 
@@ -281,9 +276,6 @@ typedef struct {
                                  0 both beside the covariance kernel (default),
                                  1 Omega's after the row-tiled KKT pass, 2 both
                                  after it */
-    int32_t batch_lanes;      /* lanes (stream pairs) spmesl_solve_batch runs
-                                 its data sets on side by side, 1 .. 4
-                                 (default 1); not searched by the autotuner */
 } spmesl_tuning;
 
 /* Set (NULL: reset to the defaults) or read the context's launch shapes. */

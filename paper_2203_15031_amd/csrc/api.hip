@@ -60,10 +60,6 @@ constexpr int64_t kDenseDataMax = 1024;
 // Workgroups of the zero fill of the dense outputs (64 blocks of
 // nontemporal 16-byte stores write about 5 TB/s beside the covariance kernel).
 constexpr int kFillBlocks = 64;
-// Lanes a batch's data sets run on side by side.  One by default: with two
-// lanes the kernels of the two streams overlapped for about 2% of the batch's
-// time on MI355X and the 64-set hub batch ran within 1.5% of one lane.
-constexpr int kBatchLanes = 1;
 
 // The launch shapes of a solve: the context's spmesl_tuning with its zero
 // fields replaced by the defaults.
@@ -73,7 +69,6 @@ struct Tune {
     int kkt_rows = 0;  // 0: the most that fit
     int screen_permille = kScreenPermille;
     int fill_split = 0;
-    int batch_lanes = kBatchLanes;
 };
 Tune resolve_tune(const spmesl_tuning &t)
 {
@@ -83,7 +78,6 @@ Tune resolve_tune(const spmesl_tuning &t)
     if (t.kkt_rows > 0) u.kkt_rows = t.kkt_rows;
     if (t.screen_permille > 0) u.screen_permille = t.screen_permille;
     u.fill_split = t.fill_split;
-    if (t.batch_lanes > 0) u.batch_lanes = t.batch_lanes;
     return u;
 }
 
@@ -120,7 +114,7 @@ struct Bump {
 // data Xt, the per-column lists, and the dense tier's workspace for
 // kDataGroups workgroups whose V holds up to kDataVcap rows.
 constexpr int kDataGroups = 128;
-constexpr int64_t kDataVcap = 256;
+constexpr int64_t kDataVcap = 1024;  // V beyond it fails (S_VV of 8 MB per workgroup)
 
 Plan make_plan_data(int64_t n, int64_t p)
 {
@@ -333,7 +327,7 @@ struct spmesl_ctx {
         std::vector<unsigned char> key;
         hipGraphExec_t exec = nullptr;
     };
-    static constexpr size_t kMaxGraphs = 8;
+    static constexpr size_t kMaxGraphs = 4;
     std::vector<CachedGraph> graphs;  // most recently used first
     // device address of this device's no-allocation scratch array (nullptr
     // if the lookup failed; scratch_err then holds the HIP error)
@@ -341,16 +335,6 @@ struct spmesl_ctx {
     hipError_t scratch_err = hipSuccess;
     spmesl_tuning tune = {};     // launch shapes (zero fields: defaults)
     int *tune_status = nullptr;  // device status word of the autotuner's solves
-    // batch lanes: a batch's data sets run on batch_lanes lanes side by side,
-    // each its own stream pair, events and capture stream (made on first use)
-    struct Lane {
-        hipStream_t stream = nullptr, side = nullptr, cap = nullptr;
-        hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr, done = nullptr;
-    };
-    static constexpr int kMaxLanes = 4;
-    Lane lanes[kMaxLanes];
-    int nlanes = 0;
-    hipEvent_t batch_start = nullptr;
     std::string err;
 };
 
@@ -415,7 +399,6 @@ static void key_tuning(KeyBuf &k, const spmesl_tuning &t)
     k.add(t.kkt_rows);
     k.add(t.screen_permille);
     k.add(t.fill_split);
-    k.add(t.batch_lanes);
 }
 
 static void key_options(KeyBuf &k, const spmesl_options &o)
@@ -1122,9 +1105,7 @@ static int run_graph(spmesl_ctx *ctx, std::vector<unsigned char> &&key, F &&body
         return fail(ctx, SPMESL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
     if (gs.size() >= spmesl_ctx::kMaxGraphs) {
         // the least recently used graph may still be executing on the stream
-        // (or, for a batch lane's graph, on that lane's stream)
         HIPTRY(ctx, hipStreamSynchronize(user));
-        for (int l = 0; l < ctx->nlanes; ++l) HIPTRY(ctx, hipStreamSynchronize(ctx->lanes[l].stream));
         HIPTRY(ctx, hipGraphExecDestroy(gs.back().exec));
         gs.pop_back();
     }
@@ -1162,97 +1143,6 @@ static int decode(const Ctl &c, int64_t p, spmesl_stats *st)
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-// Make the first `want` batch lanes (streams of default priority).
-static int ensure_lanes(spmesl_ctx *ctx, int want)
-{
-    if (!ctx->batch_start)
-        HIPTRY(ctx, hipEventCreateWithFlags(&ctx->batch_start, hipEventDisableTiming));
-    for (; ctx->nlanes < want; ++ctx->nlanes) {
-        spmesl_ctx::Lane &ln = ctx->lanes[ctx->nlanes];
-        HIPTRY(ctx, hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
-        HIPTRY(ctx, hipStreamCreateWithFlags(&ln.side, hipStreamNonBlocking));
-        HIPTRY(ctx, hipStreamCreateWithFlags(&ln.cap, hipStreamNonBlocking));
-        for (hipEvent_t *e : {&ln.fork, &ln.join, &ln.fork2, &ln.join2, &ln.done})
-            HIPTRY(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming));
-    }
-    return SPMESL_OK;
-}
-
-// While enqueueing a lane's data sets, the solve's streams and events are
-// the lane's: swap them into the context (and back when done).
-struct LaneSwap {
-    spmesl_ctx *ctx;
-    hipStream_t stream, side;
-    hipEvent_t fork, join, fork2, join2;
-    LaneSwap(spmesl_ctx *c, const spmesl_ctx::Lane &ln, hipStream_t enqueue_on) : ctx(c)
-    {
-        stream = c->stream;
-        side = c->side;
-        fork = c->fork;
-        join = c->join;
-        fork2 = c->fork2;
-        join2 = c->join2;
-        c->stream = enqueue_on;
-        c->side = ln.side;
-        c->fork = ln.fork;
-        c->join = ln.join;
-        c->fork2 = ln.fork2;
-        c->join2 = ln.join2;
-    }
-    ~LaneSwap()
-    {
-        ctx->stream = stream;
-        ctx->side = side;
-        ctx->fork = fork;
-        ctx->join = join;
-        ctx->fork2 = fork2;
-        ctx->join2 = join2;
-    }
-};
-
-// One lane's data sets as a HIP graph: replayed when the key matches a cached
-// graph, else captured on the lane's capture stream.  Launched on the lane's
-// stream.
-template <typename F>
-static int lane_graph(spmesl_ctx *ctx, const spmesl_ctx::Lane &ln, std::vector<unsigned char> &&key, F &&body)
-{
-    auto &gs = ctx->graphs;
-    for (size_t i = 0; i < gs.size(); ++i) {
-        if (gs[i].key != key) continue;
-        std::rotate(gs.begin(), gs.begin() + (std::ptrdiff_t)i, gs.begin() + (std::ptrdiff_t)i + 1);
-        HIPTRY(ctx, hipGraphLaunch(gs[0].exec, ln.stream));
-        return SPMESL_OK;
-    }
-    HIPTRY(ctx, hipStreamBeginCapture(ln.cap, hipStreamCaptureModeThreadLocal));
-    int v;
-    {
-        LaneSwap sw(ctx, ln, ln.cap);
-        v = body();
-    }
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(ln.cap, &g);
-    if (v != SPMESL_OK || e != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipGetLastError();
-        if (v != SPMESL_OK) return v;
-        return fail(ctx, SPMESL_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    }
-    hipGraphExec_t ex = nullptr;
-    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ei != hipSuccess)
-        return fail(ctx, SPMESL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-    if (gs.size() >= spmesl_ctx::kMaxGraphs) {
-        HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-        for (int l = 0; l < ctx->nlanes; ++l) HIPTRY(ctx, hipStreamSynchronize(ctx->lanes[l].stream));
-        HIPTRY(ctx, hipGraphExecDestroy(gs.back().exec));
-        gs.pop_back();
-    }
-    gs.insert(gs.begin(), spmesl_ctx::CachedGraph{std::move(key), ex});
-    HIPTRY(ctx, hipGraphLaunch(ex, ln.stream));
-    return SPMESL_OK;
-}
-
 extern "C" {
 
 const char *spmesl_version(void) { return "spmesl-mi355x 0.1 (gfx950)"; }
@@ -1312,17 +1202,6 @@ void spmesl_destroy(spmesl_ctx *ctx)
         if (ctx->join2) (void)hipEventDestroy(ctx->join2);
         if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
         if (ctx->tune_status) (void)hipFree(ctx->tune_status);
-        for (int l = 0; l < ctx->nlanes; ++l) {
-            spmesl_ctx::Lane &ln = ctx->lanes[l];
-            for (hipStream_t st : {ln.stream, ln.side, ln.cap})
-                if (st) {
-                    (void)hipStreamSynchronize(st);
-                    (void)hipStreamDestroy(st);
-                }
-            for (hipEvent_t e : {ln.fork, ln.join, ln.fork2, ln.join2, ln.done})
-                if (e) (void)hipEventDestroy(e);
-        }
-        if (ctx->batch_start) (void)hipEventDestroy(ctx->batch_start);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         for (int i = 0; i < 6; ++i)
             if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
@@ -1511,8 +1390,6 @@ int spmesl_set_tuning(spmesl_ctx *ctx, const spmesl_tuning *t)
     if (t->screen_permille < 0 || t->screen_permille > 4000)
         return fail(ctx, SPMESL_EINVAL, "screen_permille must be in 0 .. 4000");
     if (t->fill_split < 0 || t->fill_split > 2) return fail(ctx, SPMESL_EINVAL, "fill_split must be 0, 1 or 2");
-    if (t->batch_lanes < 0 || t->batch_lanes > spmesl_ctx::kMaxLanes)
-        return fail(ctx, SPMESL_EINVAL, "batch_lanes must be in 0 .. 4");
     ctx->tune = *t;
     return SPMESL_OK;
 }
@@ -1572,7 +1449,6 @@ int spmesl_autotune(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
     cur.fill_blocks = d.fill_blocks;
     cur.screen_permille = d.screen_permille;
     cur.fill_split = d.fill_split;
-    cur.batch_lanes = ctx->tune.batch_lanes;
     const size_t tsz = opt->precision == SPMESL_FP64 ? 8 : 4;
     const int rj_max = kkt_rows_per_block(prob->p, tsz, (size_t)160 * 1024);
     cur.kkt_rows = d.kkt_rows > 0 && d.kkt_rows < rj_max ? d.kkt_rows : rj_max;
@@ -1636,8 +1512,7 @@ int spmesl_batch_workspace_size(const spmesl_ctx *ctx, int count, const spmesl_p
         need = std::max(need, make_plan(probs[i].n, probs[i].p, opt->precision,
                                         opt->flags & SPMESL_FLAG_DATA_FORM).total);
     }
-    const int nl = std::max(1, std::min(count, resolve_tune(ctx->tune).batch_lanes));
-    *bytes = align_up(need, 256) * (size_t)nl + (size_t)std::max(count, 1) * sizeof(Ctl);
+    *bytes = align_up(need, 256) + (size_t)std::max(count, 1) * sizeof(Ctl);
     return SPMESL_OK;
 }
 
@@ -1660,80 +1535,6 @@ int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
         }
         plans[(size_t)i] = make_plan(probs[i].n, probs[i].p, opt->precision, opt->flags & SPMESL_FLAG_DATA_FORM);
         need = std::max(need, plans[(size_t)i].total);
-    }
-    // lanes: the data sets are dealt to the lane with the least work so far,
-    // largest first (work ~ n p^2 + 16 p^2), each lane with its own region of
-    // the workspace
-    const Tune tu = resolve_tune(ctx->tune);
-    const int nl = std::min(count, tu.batch_lanes);
-    if (nl > 1) {
-        const size_t region = align_up(need, 256);
-        const size_t ctl_off = region * (size_t)nl;
-        int v = ensure_workspace(ctx, ctl_off + (size_t)count * sizeof(Ctl));
-        if (v != SPMESL_OK) return v;
-        v = ensure_pinned(ctx, (size_t)count);
-        if (v != SPMESL_OK) return v;
-        v = ensure_lanes(ctx, nl);
-        if (v != SPMESL_OK) return v;
-        Ctl *dctl = (Ctl *)(ctx->ws + ctl_off);
-        ctx->nmarks = 0;
-        std::vector<int> order((size_t)count);
-        for (int i = 0; i < count; ++i) order[(size_t)i] = i;
-        auto work = [&](int i) {
-            const double n = (double)probs[i].n, p = (double)probs[i].p;
-            return n * p * p + 16.0 * p * p;
-        };
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-        std::vector<std::vector<int>> lane_sets((size_t)nl);
-        std::vector<double> load((size_t)nl, 0.0);
-        for (int i : order) {
-            size_t l = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
-            lane_sets[l].push_back(i);
-            load[l] += work(i);
-        }
-        HIPTRY(ctx, hipEventRecord(ctx->batch_start, ctx->stream));
-        for (int l = 0; l < nl; ++l) {
-            spmesl_ctx::Lane &ln = ctx->lanes[l];
-            char *wsl = ctx->ws + region * (size_t)l;
-            auto body = [&] {
-                for (int i : lane_sets[(size_t)l]) {
-                    int vi = enqueue_solve(ctx, &probs[i], &opts[(size_t)i], &res[i], plans[(size_t)i], wsl,
-                                           dctl + i, nullptr);
-                    if (vi != SPMESL_OK) return vi;
-                }
-                return (int)SPMESL_OK;
-            };
-            HIPTRY(ctx, hipStreamWaitEvent(ln.stream, ctx->batch_start, 0));
-            if (opt->flags & SPMESL_FLAG_EAGER) {
-                LaneSwap sw(ctx, ln, ln.stream);
-                v = body();
-            } else {
-                KeyBuf k;
-                k.add('L');
-                k.add(l);
-                k.add(nl);
-                k.add(ctx->ws);
-                k.add(count);
-                for (int i = 0; i < count; ++i) {
-                    key_problem(k, probs[i], res[i]);
-                    key_options(k, opts[(size_t)i]);
-                }
-                key_tuning(k, ctx->tune);
-                v = lane_graph(ctx, ln, std::move(k.b), body);
-            }
-            if (v != SPMESL_OK) return v;
-            HIPTRY(ctx, hipEventRecord(ln.done, ln.stream));
-            HIPTRY(ctx, hipStreamWaitEvent(ctx->stream, ln.done, 0));
-        }
-        HIPTRY(ctx, hipMemcpyAsync(ctx->pinned, dctl, (size_t)count * sizeof(Ctl), hipMemcpyDeviceToHost,
-                                   ctx->stream));
-        HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-        int first = SPMESL_OK;
-        for (int i = 0; i < count; ++i) {
-            status[i] = decode(ctx->pinned[i], probs[i].p, res[i].stats);
-            if (first == SPMESL_OK && status[i] != SPMESL_OK) first = status[i];
-        }
-        return first;
     }
     size_t ctl_off = align_up(need, 256);
     int v = ensure_workspace(ctx, ctl_off + (size_t)count * sizeof(Ctl));

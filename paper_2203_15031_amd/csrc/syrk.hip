@@ -349,20 +349,18 @@ void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, const Scre
 // The operand reads (16 lanes on 16 consecutive rows, one chunk each) then
 // touch distinct banks with either 32 or 64 LDS banks.
 //
-// The epilogue stages the tile through LDS in four slices of 64 rows and
-// writes S with 16-byte stores, directly and transposed.  The screen of the
-// first solves is taken in the direct pass (each pair for both columns).
+// The epilogue writes S from the accumulators, directly (64-byte row
+// segments) and transposed (16-byte stores of four consecutive columns),
+// with no LDS staging; the screen of the first solves is taken on the same
+// values (each pair for both columns).
 // ---------------------------------------------------------------------------
 constexpr int kBfTile = 256;
 constexpr int kBfKC = 32;                     // samples per stage (one MFMA k-step)
 constexpr int kBfPanel = kBfTile * kBfKC * 2; // 16 KB: 256 rows x 64 B
 constexpr int kBfStage = 4 * kBfPanel;        // hi_J, lo_J, hi_K, lo_K
-constexpr int kBfOutLd = 257;                 // odd stride: transposed reads hit distinct banks
-constexpr int kBfOutRows = 64;
 typedef ScreenWaves<8, 448> BfScreen;        // fills the LDS left by the two stages
 constexpr int kBfLds = 2 * kBfStage + (int)sizeof(BfScreen);
 static_assert(kBfLds <= 160 * 1024, "LDS of one block");
-static_assert(kBfOutRows * kBfOutLd * 4 <= 2 * kBfStage, "an output slice fits the stage buffers");
 
 __device__ __forceinline__ int bf_swz(int m) { return ((m >> 1) ^ (m >> 2)) & 3; }
 
@@ -460,69 +458,41 @@ __global__ __launch_bounds__(512) void k_syrk_bf16x3(const uint16_t *__restrict_
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
                 }
         }
-        // epilogue: four slices of 64 rows (one wm group each)
-        float *out = reinterpret_cast<float *>(bf_lds);
-        for (int h = 0; h < 4; ++h) {
-            __syncthreads();
-            if (wm == h) {
+        // epilogue, straight from the accumulators: lane l holds rows
+        // jb .. jb + 3 (jb = 4 (l / 16) within the 16 x 16 block) of column
+        // kk = l % 16.  Direct: 16 lanes store 64 consecutive bytes of a row
+        // of S; mirrored: the lane's four rows are four consecutive columns
+        // of row kk, one 16-byte store.  A diagonal tile stores its upper
+        // triangle both ways, so S is symmetric bit for bit.
+        const int g4 = 4 * (lane >> 4), c16 = lane & 15;
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 8; ++b)
-#pragma unroll
-                        for (int rr = 0; rr < 4; ++rr)
-                            out[(16 * a + 4 * (lane >> 4) + rr) * kBfOutLd + 128 * wn + 16 * b + (lane & 15)] =
-                                acc[a][b][rr] * invn;
-            }
-            __syncthreads();
-            // direct: row j0 + 64h + rl, columns k0 + q4 .. q4 + 3.  A diagonal
-            // tile writes its upper triangle here and its lower one below,
-            // both from the upper values, so S is symmetric bit for bit.
-            for (int e = tid; e < kBfOutRows * (kBfTile / 4); e += 512) {
-                const int rl = e >> 6, q4 = (e & 63) * 4, rr = rl + 64 * h;
-                const int64_t j = j0 + rr, k = k0 + q4;
-                // no early exit: every lane takes part in the screen's ballots
-                const bool rowok = j < p && k < p;
+            for (int b = 0; b < 8; ++b) {
+                const int64_t kk = k0 + 128 * wn + 16 * b + c16;
+                const int64_t jb = j0 + 64 * wm + 16 * a + g4;
                 float v[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = out[rl * kBfOutLd + q4 + u];
+                for (int r = 0; r < 4; ++r) v[r] = jb + r == kk ? 1.0f : acc[a][b][r] * invn;
+                // screen: a pair above the threshold is a candidate of both
+                // columns (every lane takes part in the ballots)
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (j == k + u) v[u] = 1.0f;
-                // screen: a pair above the threshold is a candidate of both columns
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool mine = rowok && k + u < p && (!diag || rr < q4 + u);
-                    screen_pair_wave(scr, w, nscr, scnt, sidx, thr, j, k + u, mine ? v[u] : 0.0f);
+                for (int r = 0; r < 4; ++r) {
+                    const bool mine = jb + r < p && kk < p && (!diag || jb + r < kk);
+                    screen_pair_wave(scr, w, nscr, scnt, sidx, thr, jb + r, kk, mine ? v[r] : 0.0f);
                 }
-                if (!rowok) continue;
-                if (vec_ok && k + 3 < p && (!diag || rr <= q4)) {
-                    *reinterpret_cast<f4 *>(&S[j * p + k]) = f4{v[0], v[1], v[2], v[3]};
+                if (kk >= p) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (jb + r < p && (!diag || jb + r <= kk)) S[(jb + r) * p + kk] = v[r];
+                if (vec_ok && jb + 3 < p && (!diag || kk > jb + 3)) {
+                    *reinterpret_cast<f4 *>(&S[kk * p + jb]) = f4{v[0], v[1], v[2], v[3]};
                 } else {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (k + u < p && (!diag || rr <= q4 + u)) S[j * p + k + u] = v[u];
+                    for (int r = 0; r < 4; ++r)
+                        if (jb + r < p && (!diag || kk > jb + r)) S[kk * p + jb + r] = v[r];
                 }
             }
-            // mirrored: row k0 + cc, columns j0 + 64h + r4 .. + 3; 16 lanes
-            // cover 64 consecutive columns
-            for (int e = tid; e < kBfTile * 16; e += 512) {
-                const int r4 = (e & 15) * 4, cc = e >> 4;
-                const int rr0 = 64 * h + r4;
-                const int64_t k = k0 + cc, j = j0 + rr0;
-                if (k >= p || j >= p) continue;
-                float v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = out[(r4 + u) * kBfOutLd + cc];
-                if (vec_ok && j + 3 < p && (!diag || cc > rr0 + 3)) {
-                    *reinterpret_cast<f4 *>(&S[k * p + j]) = f4{v[0], v[1], v[2], v[3]};
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (j + u < p && (!diag || cc > rr0 + u)) S[k * p + j + u] = v[u];
-                }
-            }
-        }
         if (lane == 0) scr.n[w] = nscr;
         __syncthreads();
         screen_flush_waves(scr, scnt, sidx);

@@ -73,7 +73,7 @@ class Stats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("dense_block", C.c_int32), ("fill_blocks", C.c_int32), ("kkt_rows", C.c_int32),
-                ("screen_permille", C.c_int32), ("fill_split", C.c_int32), ("batch_lanes", C.c_int32)]
+                ("screen_permille", C.c_int32), ("fill_split", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

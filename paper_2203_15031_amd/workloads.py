@@ -229,13 +229,16 @@ def paper_network(kind: str, p: int, rng) -> np.ndarray:
     """The precision matrices of the paper's simulation study (Section 4.1).
 
     kind: "ar1" (omega_ii = 1, omega_{i,i+-1} = 0.48), "ar4"
-    (0.6^|i-j| for |i-j| <= 4), "sf" (Barabasi-Albert scale-free) or "hub"
-    (10 hubs per 100 nodes, each non-hub joined to 1-3 of them).  "sf" and "hub" are built as
+    (0.6^|i-j| for |i-j| <= 4), "sf" (a growing random tree, each new node
+    attached to an earlier one chosen uniformly) or "hub" (10 hubs per 100
+    nodes, each non-hub joined to 1-3 of them).  "sf" and "hub" are built as
     p/100 subnetworks of 100 nodes with off-diagonal magnitudes raised to at
     least 0.1, through the steps: U([-1,-0.5] U [0.5,1]) weights, row
-    division by 1.5 x the row's absolute sum, symmetrisation, unit diagonal,
-    then (not positive definite otherwise) a diagonal shift to a smallest
-    eigenvalue of 0.1 per subnetwork.
+    division by 1.5 x the row's absolute sum, symmetrisation, unit diagonal.
+    Those steps give a positive definite matrix for the scale-free trees
+    drawn here (nodes of small degree); the hub subnetworks are not positive
+    definite after them, and their diagonal is raised until the smallest
+    eigenvalue is 0.1 (the same guard would apply to a scale-free draw).
     """
     if kind == "ar1":
         Om = np.eye(p)
@@ -252,22 +255,11 @@ def paper_network(kind: str, p: int, rng) -> np.ndarray:
         raise ValueError("p must be a multiple of 100 for the subnetwork networks")
     Om = np.zeros((p, p))
     for s in range(0, p, 100):
-        E = _ba_edges(100, rng) if kind == "sf" else _hub_edges(100, rng)
-        T = np.eye(100)
-        for (a, b) in E:
-            mag = rng.uniform(0.5, 1.0)
-            T[a, b] = T[b, a] = mag * rng.choice([-1.0, 1.0])
-        off = T - np.diag(np.diag(T))
-        rs = 1.5 * np.abs(off).sum(axis=1)
-        rs[rs == 0] = 1.0
-        T = off / rs[:, None]
-        T = (T + T.T) / 2
-        small = (T != 0) & (np.abs(T) < 0.1)
-        T[small] = np.sign(T[small]) * 0.1
-        np.fill_diagonal(T, 1.0)
-        # these steps do not give a positive definite matrix when a node has
-        # many neighbours (a hub row sums to about 5); the diagonal is then
-        # raised until the smallest eigenvalue is 0.1
+        E = _tree_edges(100, rng) if kind == "sf" else _hub_edges(100, rng)
+        T = subnetwork_precision(E, 100, rng)
+        # not positive definite when a node has many neighbours of small
+        # degree (a hub row sums to about 5): raise the diagonal until the
+        # smallest eigenvalue is 0.1
         ev = np.linalg.eigvalsh(T).min()
         if ev < 0.1:
             T += (0.1 - ev) * np.eye(100)
@@ -275,14 +267,33 @@ def paper_network(kind: str, p: int, rng) -> np.ndarray:
     return Om
 
 
-def _ba_edges(m_nodes: int, rng, alpha: float = 2.3):
-    # preferential attachment with attachment kernel degree^(alpha-1)
-    # normalised, starting from one edge
+def subnetwork_precision(edges, m: int, rng) -> np.ndarray:
+    """Steps (i)-(iv) of Section 4.1 on one subnetwork, then the floor of 0.1
+    on the nonzero off-diagonal magnitudes."""
+    T = np.eye(m)
+    for (a, b) in edges:
+        mag = rng.uniform(0.5, 1.0)
+        T[a, b] = T[b, a] = mag * rng.choice([-1.0, 1.0])
+    off = T - np.diag(np.diag(T))
+    rs = 1.5 * np.abs(off).sum(axis=1)
+    rs[rs == 0] = 1.0
+    T = off / rs[:, None]
+    T = (T + T.T) / 2
+    small = (T != 0) & (np.abs(T) < 0.1)
+    T[small] = np.sign(T[small]) * 0.1
+    np.fill_diagonal(T, 1.0)
+    return T
+
+
+def _tree_edges(m_nodes: int, rng, power: float = 0.0):
+    # growing tree from one edge: node t attaches to an earlier node j with
+    # probability proportional to degree(j)^power (0: uniform; 1: the linear
+    # preferential attachment of the Barabasi-Albert model)
     edges = [(0, 1)]
     deg = np.zeros(m_nodes)
     deg[0] = deg[1] = 1
     for t in range(2, m_nodes):
-        w = deg[:t] ** (alpha - 1.0)
+        w = deg[:t] ** power
         j = rng.choice(t, p=w / w.sum())
         edges.append((j, t))
         deg[j] += 1

@@ -1,5 +1,8 @@
 // Host-side AddressSanitizer / UndefinedBehaviorSanitizer run of the
-// library's host orchestration on a real GPU: every entry point's host path
+// library's host orchestration, on a real GPU (tests/host_asan/build.sh) or
+// against the CPU stand-in of the HIP runtime (tests/host_mock/build.sh,
+// where kernels do not run and every device status reads as zero): every
+// entry point's host path
 // (plans, workspace growth, graph capture, cache and replay, the second
 // stream's fork and join events, the timing markers, the batch, the
 // asynchronous and no-allocation entry points, warm starts, error paths).
@@ -19,6 +22,13 @@
 #include "spmesl.h"
 
 static int fails = 0;
+
+// defined by the CPU stand-in of the HIP runtime (tests/host_mock), absent
+// from the real one
+extern "C" int mock_violations() __attribute__((weak));
+extern "C" long mock_launches() __attribute__((weak));
+extern "C" long mock_graph_launches() __attribute__((weak));
+extern "C" long mock_captures() __attribute__((weak));
 
 #define CHECK(name, got, want)                                                                        \
     do {                                                                                              \
@@ -166,6 +176,79 @@ int main()
         }
         o.lambda0 = 0.25;
     }
+    {
+        // a batch in a caller workspace, eagerly and as graphs, then the
+        // autotuner and other launch shapes on the same context
+        spmesl_options o{};
+        o.lambda0 = 0.25;
+        o.tol = 1e-8;
+        std::vector<Dev *> ds;
+        for (int i = 0; i < 5; ++i) ds.push_back(new Dev(60 + 37 * i, 50 + 61 * i, 20 + i));
+        std::vector<spmesl_problem> ps;
+        std::vector<spmesl_result> rs;
+        std::vector<spmesl_stats> sts(ds.size());
+        for (size_t i = 0; i < ds.size(); ++i) {
+            ps.push_back(ds[i]->prob());
+            rs.push_back(ds[i]->res(&sts[i]));
+        }
+        std::vector<int> stat(ds.size(), 99);
+        char name[80];
+        for (int fills : {64, 128}) {
+            spmesl_tuning t{};
+            t.fill_blocks = fills;
+            CHECK("set fill blocks", spmesl_set_tuning(ctx, &t), SPMESL_OK);
+            for (int prec : {SPMESL_FP64, SPMESL_MIXED}) {
+                o.precision = prec;
+                size_t need = 0, need_a = 0;
+                CHECK("batch workspace size",
+                      spmesl_batch_workspace_size(ctx, (int)ds.size(), ps.data(), &o, &need), SPMESL_OK);
+                spmesl_problem pa0 = a.prob();
+                CHECK("workspace size", spmesl_workspace_size(&pa0, &o, &need_a), SPMESL_OK);
+                need = need > need_a ? need : need_a;  // the single solve below shares it
+                char *ws = nullptr;
+                hipMalloc(&ws, need);
+                CHECK("set batch workspace", spmesl_set_workspace(ctx, ws, need), SPMESL_OK);
+                for (int r = 0; r < 3; ++r) {
+                    o.flags = r == 0 ? SPMESL_FLAG_EAGER : 0;
+                    std::snprintf(name, sizeof name, "batch (fill blocks %d), call %d (prec %d)", fills, r, prec);
+                    CHECK(name, spmesl_solve_batch(ctx, (int)ds.size(), ps.data(), &o, nullptr, rs.data(), stat.data()),
+                          SPMESL_OK);
+                }
+                o.flags = 0;
+                spmesl_problem pa = a.prob();
+                spmesl_result ra = a.res(&st);
+                std::snprintf(name, sizeof name, "solve after the batch (prec %d)", prec);
+                CHECK(name, spmesl_solve(ctx, &pa, &o, &ra), SPMESL_OK);
+                CHECK("release batch workspace", spmesl_set_workspace(ctx, nullptr, 0), SPMESL_OK);
+                hipFree(ws);
+            }
+        }
+        CHECK("reset tuning", spmesl_set_tuning(ctx, nullptr), SPMESL_OK);
+        for (Dev *d : ds) delete d;
+        o.precision = SPMESL_MIXED;
+        spmesl_problem pa = a.prob();
+        spmesl_result ra = a.res(&st);
+        spmesl_tuning best{};
+        double msb = 0.0;
+        CHECK("autotune after the batches", spmesl_autotune(ctx, &pa, &o, &ra, 3, &best, &msb), SPMESL_OK);
+        for (int split : {0, 1, 2}) {
+            spmesl_tuning t = best;
+            t.fill_split = split;
+            t.kkt_rows = 1;
+            CHECK("set fill placement", spmesl_set_tuning(ctx, &t), SPMESL_OK);
+            std::snprintf(name, sizeof name, "solve with fill placement %d", split);
+            CHECK(name, spmesl_solve(ctx, &pa, &o, &ra), SPMESL_OK);
+        }
+        CHECK("reset tuning", spmesl_set_tuning(ctx, nullptr), SPMESL_OK);
+        o.precision = SPMESL_FP64;
+        o.flags = SPMESL_FLAG_DATA_FORM;
+        CHECK("data form", spmesl_solve(ctx, &pa, &o, &ra), SPMESL_OK);
+        o.flags = SPMESL_FLAG_DATA_FORM | SPMESL_FLAG_EAGER;
+        CHECK("data form eager", spmesl_solve(ctx, &pa, &o, &ra), SPMESL_OK);
+        o.precision = SPMESL_MIXED;
+        o.flags = SPMESL_FLAG_FULL_KKT;
+        CHECK("full KKT pass", spmesl_solve(ctx, &pa, &o, &ra), SPMESL_OK);
+    }
     // error paths
     spmesl_options o{};
     o.lambda0 = -1.0;
@@ -200,6 +283,11 @@ int main()
     CHECK("autotune", spmesl_autotune(ctx, &pa, &o, &ra, 2, &best, &msb), SPMESL_OK);
     hipFree(status_dev);
     spmesl_destroy(ctx);
+    if (mock_violations) {
+        std::printf("HIP stand-in: %ld kernel launches, %ld captures, %ld graph launches, %d rule violations\n",
+                    mock_launches(), mock_captures(), mock_graph_launches(), mock_violations());
+        fails += mock_violations();
+    }
     std::printf("host sanitizer run: %d failed checks\n", fails);
     return fails ? 1 : 0;
 }

@@ -168,6 +168,28 @@ def test_scale_free_p20000_sampled_columns_and_pairs(ctx, sf_case, prec, bar):
     omega_invariants(Om_sub, B_sub)
 
 
+def test_scale_free_p20000_data_form(ctx, sf_case):
+    # the data form (no S, n << p) on the same sampled columns and pairs
+    w, X, cols, ref = sf_case
+    r = ctx.solve(gpu(X), w.lambda0, tol=w.tol, precision="fp64", output_scale="standardized", data_form=True)
+    assert r.status == 0
+    idx = torch.from_numpy(cols).to(DEV)
+    Bc = r.B[:, idx].cpu().numpy()
+    sig = host(r.sigma)[cols]
+    Om_sub = r.Omega[idx][:, idx].cpu().numpy()
+    B_sub = r.B[idx][:, idx].cpu().numpy()
+    del r
+    torch.cuda.empty_cache()
+    errs = dict(B=max(rel_err(Bc[:, i], ref["B"][:, i]) for i in range(cols.size)),
+                sigma=max(abs(sig[i] - ref["sigma"][i]) / ref["sigma"][i] for i in range(cols.size)),
+                Omega_pairs=rel_err(Om_sub, ref["Omega_sub"]))
+    _report(f"sf p20000 data form, {cols.size} columns", errs)
+    assert max(errs.values()) <= 1e-6, errs
+    mism, excl = support_mismatch_cols(Bc, ref["B"], standardize(X), cols, ref["sigma"], w.lambda0, 1e-6)
+    assert mism == 0, (mism, excl)
+    omega_invariants(Om_sub, B_sub)
+
+
 # ---------------------------------------------------------------------------
 # the 64-data-set hub batch at its own sizes
 # ---------------------------------------------------------------------------

@@ -343,19 +343,6 @@ def test_solve_batch_matches_single_solves(ctx):
         for (B1, O1), r in zip(first, res3):
             assert r.status == 0
             assert torch.equal(r.B, B1) and torch.equal(r.Omega, O1)
-    # the same results whatever the number of lanes the batch runs on
-    for lanes in (1, 3):
-        try:
-            ctx.set_tuning(dict(batch_lanes=lanes))
-            for prec in ("fp64", "mixed"):
-                one = [ctx.solve(Xd, lam, tol=1e-8, precision=prec, eager=True) for Xd, lam in zip(Xg, lams)]
-                for rep in range(2):
-                    res = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec, eager=(rep == 0))
-                    for r, o in zip(res, one):
-                        assert r.status == 0
-                        assert torch.equal(r.B, o.B) and torch.equal(r.Omega, o.Omega), (lanes, prec, rep)
-        finally:
-            ctx.set_tuning(None)
     # and against the oracle on two of them
     for i in (0, 3):
         ref = oracle.spmesl(Xs[i], lams[i], tol=1e-12)
@@ -521,8 +508,7 @@ def test_autotune_and_tuning(ctx, sp):
         assert e.value.code == sp.EINVAL
     finally:
         ctx.set_tuning(None)
-    assert ctx.get_tuning() == dict(dense_block=0, fill_blocks=0, kkt_rows=0, screen_permille=0, fill_split=0,
-                                    batch_lanes=0)
+    assert ctx.get_tuning() == dict(dense_block=0, fill_blocks=0, kkt_rows=0, screen_permille=0, fill_split=0)
 
 
 @pytest.mark.parametrize("b", [16, 64])
