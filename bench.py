@@ -30,7 +30,7 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 WORKLOAD = "blockar_n400_p5000"
 
 
-def kernel_costs(n, p, prec):
+def kernel_costs(n, p, prec, mean_w=None):
     """Algorithmic work of one launch of each kernel step: (bytes, flops, flop dtype).
 
     S = Xs^T Xs / n needs n p (p + 1) flops (the upper triangle, one
@@ -40,9 +40,11 @@ def kernel_costs(n, p, prec):
     float 4np).  The mixed form's
     standardisation reads X once and writes Xt (double) and the bf16 split
     (8np + 8np + 4 npad p bytes).  The row-tiled KKT pass reads S once; the
-    zero fill writes one dense p x p double output.  The column solves and
-    the polish are latency-bound chains of small gathers and have no such
-    figure.
+    zero fill writes one dense p x p double output.  The double polish of
+    the mixed form reads, for each column, the rows of the standardised data
+    on its working set and its own (8 n (|W| + 1) bytes, with mean_w the mean
+    final working set).  The column solves are latency-bound chains of small
+    gathers and have no such figure.
     """
     tsz = 8 if prec == "fp64" else 4
     fl = float(n) * p * (p + 1)
@@ -58,6 +60,8 @@ def kernel_costs(n, p, prec):
     }
     if prec == "mixed":
         costs["standardize"] = (16.0 * n * p + 4.0 * npad * p, 0.0, None)
+        if mean_w is not None:
+            costs["polish"] = (8.0 * n * (mean_w + 1.0) * p, 0.0, None)
     return costs
 
 
@@ -505,7 +509,8 @@ def main():
 
     head = forms[0]
     ms, ms_sync, ph, kern, r = res[head]
-    costs = kernel_costs(w.n, w.p, FORMS[head][0]) if not FORMS[head][1] else {}
+    mean_w = r.stats["sum_working_set"] / w.p if getattr(r, "stats", None) else None
+    costs = kernel_costs(w.n, w.p, FORMS[head][0], mean_w) if not FORMS[head][1] else {}
     # the kernel step that takes longest per solve, among those on the
     # solver's stream (the output fill overlaps them on the second stream)
     main = {k: v for k, v in kern.items() if not k.startswith(("fill_", "wait_"))}

@@ -96,6 +96,9 @@ struct Plan {
     // the data form (no S): workgroups of its dense tier and rows of V each
     bool data = false;
     int dgroups = 1;
+    // workgroups of the S forms' dense tiers (each with its own slice of
+    // the dense workspace)
+    int sgroups = 1;
     int64_t dvcap = 0;
     size_t total = 0;
 };
@@ -162,9 +165,29 @@ Plan make_plan_data(int64_t n, int64_t p)
     return L;
 }
 
+// The S forms' dense tiers run on G workgroups, each with a slice of the
+// dense workspace: the marks, V and its previous copy (p each), R, B, B_prev
+// and the screen values (16 p each) and, in the mixed form, S[V, V] and E of
+// the double stage.  G is the number of slices that fit a quarter of the
+// rest of the plan (at least 16 MB), from 1 to kDenseGroupsMax.
+constexpr int kDenseGroupsMax = 32;
+constexpr size_t kDenseBudgetFloor = (size_t)16 << 20;
+Plan make_plan_g(int64_t n, int64_t p, int prec, int G);
+
 Plan make_plan(int64_t n, int64_t p, int prec, bool data = false)
 {
     if (data) return make_plan_data(n, p);
+    const Plan one = make_plan_g(n, p, prec, 1);
+    const size_t P = (size_t)p;
+    size_t slice = 4 * P + 8 * P + 4 * 8 * 16 * P;
+    if (prec == SPMESL_MIXED) slice += 8 * (size_t)one.svv_cap * (size_t)one.svv_cap + 8 * 16 * (size_t)n;
+    const size_t budget = std::max(kDenseBudgetFloor, one.total / 4);
+    const int G = (int)std::min<size_t>(kDenseGroupsMax, std::max<size_t>(1, budget / slice));
+    return G == 1 ? one : make_plan_g(n, p, prec, G);
+}
+
+Plan make_plan_g(int64_t n, int64_t p, int prec, int G)
+{
     Plan L;
     L.n = n;
     L.p = p;
@@ -195,13 +218,15 @@ Plan make_plan(int64_t n, int64_t p, int prec, bool data = false)
     L.wbeta = b.take(tsz * lists);
     L.woff = b.take(4 * P);
     L.dq = b.take(4 * P);
-    L.dmark = b.take(4 * P);
-    L.dv = b.take(4 * P);
-    L.dvold = b.take(4 * P);
-    L.dr = b.take(8 * 16 * P);
-    L.dbd = b.take(8 * 16 * P);
-    L.dbp = b.take(8 * 16 * P);
-    L.dsk = b.take(8 * 16 * P);
+    L.sgroups = G;
+    const size_t GG = (size_t)G;
+    L.dmark = b.take(4 * P * GG);
+    L.dv = b.take(4 * P * GG);
+    L.dvold = b.take(4 * P * GG);
+    L.dr = b.take(8 * 16 * P * GG);
+    L.dbd = b.take(8 * 16 * P * GG);
+    L.dbp = b.take(8 * 16 * P * GG);
+    L.dsk = b.take(8 * 16 * P * GG);
     L.dq64 = L.woff64 = L.dsvv = L.de = 0;
     L.sigma = b.take(8 * P);
     L.lam = b.take(8 * P);
@@ -228,8 +253,8 @@ Plan make_plan(int64_t n, int64_t p, int prec, bool data = false)
         L.dq64 = b.take(4 * P);
         // S[V, V] of the double dense tier (formed from the data)
         L.svv_cap = p < kDenseDataMax ? p : kDenseDataMax;
-        L.dsvv = b.take(8 * (size_t)L.svv_cap * (size_t)L.svv_cap);
-        L.de = b.take(8 * 16 * N);
+        L.dsvv = b.take(8 * (size_t)L.svv_cap * (size_t)L.svv_cap * GG);
+        L.de = b.take(8 * 16 * N * GG);
         L.sigma64 = b.take(8 * P);
         L.lam64 = b.take(8 * P);
         L.cstat64 = b.take(4 * P);
@@ -583,7 +608,7 @@ static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &
     src.sigma = a.sigma;
     src.pend_cnt = a.pend_cnt;
     src.pend_idx = a.pend_idx;
-    launch_dense<T, T>(d, src, s);
+    launch_dense<T, T>(d, src, s, L.sgroups);
     mark(mk, s, "dense");
 }
 
@@ -905,7 +930,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         src.sigma = q.sigma32;
         src.pend_cnt = (const int *)(ws + L.pendcnt);
         src.pend_idx = (const int *)(ws + L.pendidx);
-        launch_dense<double, float>(d, src, s);
+        launch_dense<double, float>(d, src, s, L.sgroups);
         mark(mk, s, "dense_polish");
     }
     {

@@ -201,7 +201,7 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
 // changed and coordinate descent runs.  The |A| x |A| system is solved by
 // Gauss-Jordan elimination, one row per lane (S_AA is symmetric positive
 // definite, so no pivoting).
-constexpr int kDirectMax = 8;
+constexpr int kDirectMax = 24;
 
 template <int LW>
 __device__ bool polish_direct(WaveSm<double, LW> &sm, ColState<double, LW> &st, double lambda0, double tol)
@@ -225,20 +225,26 @@ __device__ bool polish_direct(WaveSm<double, LW> &sm, ColState<double, LW> &st, 
     const double s0 = row ? sm.tbeta[qr] : 0.0;  // s_W' as staged by the Gram
     const double z0 = row ? (sm.wbeta[qr] > 0.0 ? 1.0 : -1.0) : 0.0;
     double xs = s0, xz = z0;
+    bool ok = true;
 #pragma unroll
     for (int c = 0; c < kDirectMax; ++c) {
-        if (c >= m) break;
-        const double pc = bcast(a[c], c);
-        if (!(pc > 1e-12)) return false;
-        const double rs = bcast(xs, c), rz = bcast(xz, c);
-        // lane c's own row is left as it is (f = 0), so its entries read
-        // here are those of the pivot row at this step
-        const double f = (row && lane != c) ? a[c] / pc : 0.0;
+        // every step is unrolled (the row stays in registers); steps past m
+        // and entries past m are skipped by wave-uniform tests
+        if (c < m) {
+            const double pc = bcast(a[c], c);
+            ok = ok && pc > 1e-12;
+            const double rs = bcast(xs, c), rz = bcast(xz, c);
+            // lane c's own row is left as it is (f = 0), so its entries read
+            // here are those of the pivot row at this step
+            const double f = (row && lane != c && pc > 1e-12) ? a[c] / pc : 0.0;
 #pragma unroll
-        for (int e = 0; e < kDirectMax; ++e) a[e] -= f * bcast(a[e], c);
-        xs -= f * rs;
-        xz -= f * rz;
+            for (int e = 0; e < kDirectMax; ++e)
+                if (e < m) a[e] -= f * bcast(a[e], c);
+            xs -= f * rs;
+            xz -= f * rz;
+        }
     }
+    if (!ok) return false;
     double d = 1.0;
 #pragma unroll
     for (int c = 0; c < kDirectMax; ++c)
