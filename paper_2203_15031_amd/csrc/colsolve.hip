@@ -38,7 +38,7 @@
 
 namespace spmesl {
 
-template <typename T, int LW, int KCH, int KU, bool FIRST = false>
+template <typename T, int LW, int KCH, int KU, bool FIRST = false, bool DIRECT = true>
 __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier, int part = 0,
                              int nparts = 1, KktCoop *cp = nullptr);
 
@@ -52,6 +52,10 @@ __device__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, 
 // follows (each column is left deferred after one working-set solve), with
 // none of the other paths compiled in; the rare column with more candidates
 // than its list holds is handed to the wide kernel, which screens in the wave.
+// The closed-form step of slow inner loops (direct_fixed_point) is compiled
+// into the first solves and the re-solves, not into the first solves with
+// in-wave KKT passes (large p), where its registers would halve the waves per
+// SIMD.
 template <typename T, int LW, int NW, int KCH, int KU, int MINW = 1, bool FIRST = false>
 __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW))) void k_colsolve(ColArgs<T> A, int tier)
 {
@@ -60,18 +64,19 @@ __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW)
     const int wv = threadIdx.x / kWave;
     WaveSm<T, LW> &sm = smem[wv];
     const int64_t nwork = A.mode ? (int64_t)*A.work_cnt : A.p - A.k0;
+    constexpr bool DIRECT = FIRST || NW > 1;
     if constexpr (NW > 1) {
         if (A.mode && nwork <= (int64_t)gridDim.x) {
             __shared__ KktCoop coop;
             for (int64_t gw = blockIdx.x; gw < nwork; gw += gridDim.x)
-                solve_column<T, LW, KCH, KU>(A, sm, (int64_t)A.work_list[gw], tier, wv, NW, &coop);
+                solve_column<T, LW, KCH, KU, false, DIRECT>(A, sm, (int64_t)A.work_list[gw], tier, wv, NW, &coop);
             return;
         }
     }
     const int64_t gw0 = (int64_t)blockIdx.x * NW + wv;
     for (int64_t gw = gw0; gw < nwork; gw += (int64_t)gridDim.x * NW) {
         const int64_t k = A.mode ? (int64_t)A.work_list[gw] : A.k0 + gw;
-        solve_column<T, LW, KCH, KU, FIRST>(A, sm, k, tier);
+        solve_column<T, LW, KCH, KU, FIRST, DIRECT>(A, sm, k, tier);
     }
 }
 
@@ -118,7 +123,7 @@ __device__ __forceinline__ void escalate(const ColArgs<T> &A, int64_t k, const W
     }
 }
 
-template <typename T, int LW, int KCH, int KU, bool FIRST>
+template <typename T, int LW, int KCH, int KU, bool FIRST, bool DIRECT>
 __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> &sm, int64_t k, int tier,
                                              int part, int nparts, KktCoop *cp)
 {
@@ -217,7 +222,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
                 ++rounds;
                 if (np > 0) merge_pending(sm, st, np);
                 load_working_set(A.S, p, k, sm, st, rlo, rhi);
-                status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+                status = scaled_lasso_W<T, LW, DIRECT>(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
                 if (A.defer_kkt && status == kColOk) deferred = true;
             } else if (A.defer_kkt) {
                 // beta = 0 passes the screen; the row-tiled pass still
@@ -259,12 +264,12 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
             ++rounds;
             merge_pending(sm, st, np);
             load_working_set(A.S, p, k, sm, st, rlo, rhi);
-            status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+            status = scaled_lasso_W<T, LW, DIRECT>(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         } else {
             load_working_set(A.S, p, k, sm, st, rlo, rhi);
             // a warm start handed over unsolved: solve it before the KKT passes
             if (unsolved)
-                status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+                status = scaled_lasso_W<T, LW, DIRECT>(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         }
     }
 
@@ -286,7 +291,7 @@ __device__ __forceinline__ void solve_column(const ColArgs<T> &A, WaveSm<T, LW> 
         ++rounds;
         merge_pending(sm, st, np);
         load_working_set(A.S, p, k, sm, st, rlo, rhi);
-        status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+        status = scaled_lasso_W<T, LW, DIRECT>(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
         if (A.mode == 0 && A.defer_kkt && status == kColOk) {
             deferred = true;
             break;

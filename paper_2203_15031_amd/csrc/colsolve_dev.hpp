@@ -466,6 +466,61 @@ struct SolveCounts {
     int outer, sweeps, updates;
 };
 
+// Inner loops that take this many sweeps try the closed-form fixed point of
+// their support (below) before the next outer pass.
+constexpr int kDirectSweeps = 12;
+
+// The fixed point of the outer iteration for the current support A and
+// signs z of beta, in closed form: with A and z fixed, the lasso solution at
+// lambda = lambda0 sigma is beta_A = u - lambda v, u = S_AA^-1 s_A,
+// v = S_AA^-1 z_A, and the noise update of Eq. (eq:sigma) becomes
+// sigma^2 = 1 - u's_A + lambda0^2 sigma^2 z_A'v, whose fixed point is
+// sigma^2 = (1 - u's_A) / (1 - lambda0^2 z_A'v).  The |A| x |A| system is
+// solved by Gauss-Jordan elimination on the register rows of S_WW (one row
+// per lane, pivots taken in W order; S_AA is symmetric positive definite, so
+// no pivoting), which it overwrites: the caller reloads them.  On success
+// (a usable system and beta_A with the signs z) beta and sigma are set and
+// true is returned; the caller's next coordinate-descent pass, from that
+// start, confirms the conditions on all of W (or moves on from it), so the
+// minimiser reached is the one of Algorithm 1.
+template <typename T, int LW>
+__device__ bool direct_fixed_point(ColState<T, LW> &st, unsigned *rlo, unsigned *rhi, T lambda0)
+{
+    static_assert(ColState<T, LW>::kRegRows && ColState<T, LW>::NS == 1, "register rows, one coordinate per lane");
+    const int lane = lane_id();
+    const bool inA = lane < st.w && st.b[0] != T(0);
+    const unsigned long long mA = __ballot(inA);
+    if (__popcll(mA) < 2) return false;
+    const T s0 = inA ? st.sv[0] : T(0);
+    const T z0 = inA ? (st.b[0] > T(0) ? T(1) : T(-1)) : T(0);
+    T xs = s0, xz = z0, d = T(1);
+    for (unsigned long long rem = mA; rem; rem &= rem - 1) {
+        const int qc = __builtin_ffsll((long long)rem) - 1;  // wave-uniform pivot
+        const T pc = bcast(row_get<T>(rlo, rhi, qc), qc);
+        if (!(pc > DegenerateFloor<T>::v)) return false;
+        if (lane == qc) d = pc;  // later steps leave the pivot's diagonal as it is
+        const T f = (inA && lane != qc) ? row_get<T>(rlo, rhi, qc) / pc : T(0);
+        const T rs = bcast(xs, qc), rz = bcast(xz, qc);
+        for (unsigned long long cols = mA; cols; cols &= cols - 1) {
+            const int qe = __builtin_ffsll((long long)cols) - 1;
+            const T pv = bcast(row_get<T>(rlo, rhi, qe), qc);  // pivot row, column qe
+            row_set(rlo, rhi, qe, row_get<T>(rlo, rhi, qe) - f * pv);
+        }
+        xs -= f * rs;
+        xz -= f * rz;
+    }
+    const T u = inA ? xs / d : T(0), v = inA ? xz / d : T(0);
+    const T us = wave_sum(u * s0), vz = wave_sum(v * z0);
+    const T c0 = T(1) - us, c2 = lambda0 * lambda0 * vz;
+    if (!(c0 > DegenerateFloor<T>::v) || !(c2 < T(1))) return false;
+    const T sigma = sqrt(c0 / (T(1) - c2));
+    const T beta = u - lambda0 * sigma * v;
+    if (__ballot(inA && !(z0 > T(0) ? beta > T(0) : beta < T(0)))) return false;
+    if (inA) st.b[0] = beta;
+    st.sigma = sigma;
+    return true;
+}
+
 // Algorithm 1 on the working set: outer sigma loop around cyclic sweeps,
 // with a secant step on the sigma update.  While the support A and the signs
 // z of beta stay fixed, the lasso solution at lambda = lambda0 sigma is
@@ -479,9 +534,9 @@ struct SolveCounts {
 // so the result is the same minimiser (Eq. (eq:spmesl)), reached in fewer
 // outer passes; a step that fails its checks is not taken.
 // Returns kColOk, kColNoconv or kColDegenerate.
-template <typename T, int LW>
+template <typename T, int LW, bool kDirect = true>
 __device__ __forceinline__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW> &st,
-                                              const unsigned *rlo, const unsigned *rhi,
+                                              unsigned *rlo, unsigned *rhi,
                                               T lambda0, T tol, int max_outer, int max_sweeps,
                                               SolveCounts &cnt)
 {
@@ -501,6 +556,7 @@ __device__ __forceinline__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW>
     for (;;) {
         if (cnt.outer >= max_outer) return kColNoconv;
         ++cnt.outer;
+        const int sweeps0 = cnt.sweeps;
         const T lam = st.sigma * lambda0;
         fresh_gradient(sm, st, rlo, rhi);
         bool inner_ok = false;
@@ -600,7 +656,15 @@ __device__ __forceinline__ int scaled_lasso_W(WaveSm<T, LW> &sm, ColState<T, LW>
             png[s] = ng;
         }
         bool jumped = false;
-        if (same) {
+        if constexpr (kDirect && ColState<T, LW>::kRegRows && ColState<T, LW>::NS == 1) {
+            // a slow inner loop (strongly correlated coordinates): start the
+            // next pass from the closed-form fixed point of this support
+            if (cnt.sweeps - sweeps0 >= kDirectSweeps) {
+                jumped = direct_fixed_point(st, rlo, rhi, lambda0);
+                rows_to_registers(sm, st, rlo, rhi);
+            }
+        }
+        if (same && !jumped) {
             const T c2 = (sn * sn - hp * hp) / (so * so - sp * sp);
             const T c0 = sn * sn - c2 * so * so;
             T dsp = so - sp;

@@ -425,7 +425,9 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
             ++cnt.outer;
         } else {
             rows_to_registers(sm, st, rlo, rhi);
-            status = scaled_lasso_W(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer, A.max_sweeps, cnt);
+            // (the direct solve of this support was tried above)
+            status = scaled_lasso_W<double, LW, false>(sm, st, rlo, rhi, A.lambda0, A.tol, A.max_outer,
+                                                       A.max_sweeps, cnt);
         }
         if (status != kColOk) break;
         // bound on the change of any gradient outside W'

@@ -62,7 +62,7 @@ def test_covariance_fp64(ctx, n, p):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
-@pytest.mark.parametrize("n,p", [(100, 200), (37, 131), (400, 300)])
+@pytest.mark.parametrize("n,p", [(100, 200), (37, 131), (400, 300), (50, 517)])
 def test_covariance_reduced(ctx, prec, n, p):
     rng = np.random.default_rng(7 + n + p)
     X = rng.standard_normal((n, p)) @ np.linalg.cholesky(W.ar_cov(p, 0.5)).T
