@@ -244,14 +244,23 @@ int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob,
  * Solve `count` independent problems (uneven n, p) with the same options,
  * except that problem i uses lambda0s[i] when lambda0s (HOST array of count
  * doubles) is not NULL.  status[i] (host) receives each problem's code; the
- * return value is the first non-OK code, or SPMESL_OK.  The problems run one
- * after another on the context's stream, as one graph launch when the call
+ * return value is the first non-OK code, or SPMESL_OK.
+ * In the mixed form (covariance form, no warm starts, two or more problems,
+ * every p within the row-tiled KKT pass's reach: p up to about 20000) the
+ * problems run grouped: each step of the path is one launch over the work of
+ * every problem (the covariance tiles, the first solves, the KKT pass, the
+ * re-solves, the escalations and the polish), each problem with its own
+ * workspace region; the results equal those of the problems' single solves
+ * bit for bit.  Otherwise the problems run one after another.  Either way the
+ * work goes on the context's stream, as one graph launch when the call
  * repeats the previous call's pointers, sizes and options. */
 int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                        const spmesl_options *opt, const double *lambda0s,
                        spmesl_result *res, int *status);
-/* Workspace (device bytes) spmesl_solve_batch needs for these problems (the
- * largest problem's, and a control block per problem). */
+/* Workspace (device bytes) spmesl_solve_batch needs for these problems:
+ * grouped, every problem's workspace, a control block per problem and the
+ * launch tables; one after another, the largest problem's workspace and a
+ * control block per problem. */
 int spmesl_batch_workspace_size(const spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                                 const spmesl_options *opt, size_t *bytes);
 

@@ -329,6 +329,9 @@ struct spmesl_ctx {
     bool ws_owned = true;
     Ctl *pinned = nullptr;
     size_t pinned_count = 0;
+    // host staging of the grouped batch's launch tables
+    unsigned char *stage = nullptr;
+    size_t stage_bytes = 0;
     hipEvent_t ev[6] = {};
     bool have_events = false;
     // second stream (default priority) for the zero fill of the dense
@@ -618,14 +621,22 @@ static void enqueue_dense(const Plan &L, char *ws, Ctl *dctl, const ColArgs<T> &
 // solves run their own in-wave KKT passes instead.  With k0 > 0 only the
 // columns k0 .. p-1 are solved, each on the predictors 0 .. k0-1 (the scaled
 // lassos of responses appended to a design), with in-wave KKT passes.
-template <typename T, typename F>
-static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt, const Tune &tu,
-                           double tol, double band, int max_outer, int max_sweeps, int max_rounds,
-                           hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0, bool warm = false)
+// Rows of S per tile of the row-tiled KKT pass (0: the pass does not apply).
+template <typename T>
+static int kkt_rows_for(int64_t p, int64_t k0, const Tune &tu)
 {
-    const int64_t p = L.p;
     int rj = k0 > 0 ? 0 : kkt_rows_per_block(p, sizeof(T), (size_t)160 * 1024);
     if (rj > 0 && tu.kkt_rows > 0 && tu.kkt_rows < rj) rj = tu.kkt_rows >= 2 ? 2 : 1;
+    return rj;
+}
+
+// The column solves' arguments for one problem (the phase fields mode,
+// screened, defer_kkt, work list and escalation queue are set per launch).
+template <typename T>
+static ColArgs<T> make_col_args(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt, double tol,
+                                double band, int max_outer, int max_sweeps, int max_rounds, int64_t k0, bool warm)
+{
+    const int64_t p = L.p;
     ColArgs<T> a{};
     a.S = (const T *)(ws + L.S);
     a.p = p;
@@ -657,6 +668,42 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.warm = warm ? 1 : 0;
     a.dense_cnt = &dctl->dense;
     a.dense_list = (int *)(ws + L.dq);
+    return a;
+}
+
+// The row-tiled KKT pass's arguments for one problem.
+template <typename T>
+static KktArgs<T> make_kkt_args(const ColArgs<T> &a, const Plan &L, char *ws, Ctl *dctl)
+{
+    KktArgs<T> k{};
+    k.S = a.S;
+    k.p = L.p;
+    k.kkt_tol = a.kkt_tol;
+    k.band = a.band;
+    k.lam_used = a.lam_used;
+    k.col_status = a.col_status;
+    k.w_cnt = a.w_cnt;
+    k.w_idx = a.w_idx;
+    k.supp_cnt = a.supp_cnt;
+    k.supp_idx = a.supp_idx;
+    k.supp_val = a.supp_val;
+    k.pend_cnt = a.pend_cnt;
+    k.pend_idx = a.pend_idx;
+    k.dirty_cnt = &dctl->dirty;
+    k.dirty_list = (int *)(ws + L.dirtylist);
+    k.band_cnt = a.band_cnt;
+    k.band_idx = a.band_idx;
+    k.flags = &dctl->flags;
+    return k;
+}
+
+template <typename T, typename F>
+static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt, const Tune &tu,
+                           double tol, double band, int max_outer, int max_sweeps, int max_rounds,
+                           hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0, bool warm = false)
+{
+    const int rj = kkt_rows_for<T>(L.p, k0, tu);
+    ColArgs<T> a = make_col_args<T>(L, ws, dctl, opt, tol, band, max_outer, max_sweeps, max_rounds, k0, warm);
     // first solves (their screen lists were written with S).  With the
     // row-tiled pass, the columns they hand to the wide tier join the
     // re-solves' queue: one wide launch after the re-solves finishes both (an
@@ -679,25 +726,7 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
         if (band == 0.0) enqueue_dense<T>(L, ws, dctl, a, tu, s, mk);
         return after_kkt();
     }
-    KktArgs<T> k{};
-    k.S = a.S;
-    k.p = p;
-    k.kkt_tol = a.kkt_tol;
-    k.band = a.band;
-    k.lam_used = a.lam_used;
-    k.col_status = a.col_status;
-    k.w_cnt = a.w_cnt;
-    k.w_idx = a.w_idx;
-    k.supp_cnt = a.supp_cnt;
-    k.supp_idx = a.supp_idx;
-    k.supp_val = a.supp_val;
-    k.pend_cnt = a.pend_cnt;
-    k.pend_idx = a.pend_idx;
-    k.dirty_cnt = &dctl->dirty;
-    k.dirty_list = (int *)(ws + L.dirtylist);
-    k.band_cnt = a.band_cnt;
-    k.band_idx = a.band_idx;
-    k.flags = &dctl->flags;
+    const KktArgs<T> k = make_kkt_args<T>(a, L, ws, dctl);
     launch_kkt_rows(k, rj, s);
     mark(mk, s, "kkt_rows");
     const int v = after_kkt();
@@ -721,6 +750,195 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     return SPMESL_OK;
 }
 
+// Column statistics and the standardised copies of X the form needs.
+static void enqueue_standardize(const Plan &L, const spmesl_problem *prob, char *ws, Ctl *dctl, hipStream_t s,
+                                Marker *mk)
+{
+    const int64_t n = prob->n, p = prob->p;
+    double *mean = (double *)(ws + L.mean);
+    double *scale = (double *)(ws + L.scale);
+    if (L.prec == SPMESL_MIXED &&
+        launch_stats_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
+                           (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, &dctl->flags,
+                           (int *)(ws + L.pendcnt), s)) {
+        mark(mk, s, "standardize");
+        return;
+    }
+    launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
+                    &dctl->flags, (int *)(ws + L.pendcnt), s);
+    mark(mk, s, "colstats");
+    if (L.prec == SPMESL_FP64)
+        launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
+    else if (L.prec == SPMESL_FP32)
+        launch_standardize_f32(prob->X, n, p, prob->ldx, mean, scale, (float *)(ws + L.xs), s);
+    else
+        launch_standardize_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
+                                 (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
+    mark(mk, s, "standardize");
+}
+
+// Tolerance of the column solves: the caller's in double, floored in the
+// float and mixed forms.
+static double column_tol(const Plan &L, const spmesl_options *opt)
+{
+    return L.prec == SPMESL_FP64 ? opt->tol
+                                 : std::max(opt->tol, L.prec == SPMESL_MIXED ? kMixedFloatTol
+                                                                             : (double)SPMESL_FP32_TOL_FLOOR);
+}
+
+// The first solves' working sets, {j : |s_jk| > f lambda0 + tol}, are taken
+// where S is written.  At beta = 0 the KKT test is |s_jk| > lambda0 + tol; the
+// final lambda is sigma lambda0 with sigma < 1, so the lower factor starts
+// most columns on their final support (a strong-rule style start: the
+// row-tiled KKT pass still checks every column, so the factor changes the
+// work, never the result).
+static Screen make_screen(const Plan &L, char *ws, const spmesl_options *opt, const Tune &tu, double tol_cols)
+{
+    const double screen = tu.screen_permille * 1e-3;
+    Screen sc;
+    sc.thr64 = screen * opt->lambda0 + tol_cols;
+    {
+        volatile float a = (float)(screen * opt->lambda0), b = (float)tol_cols;
+        sc.thr32 = a + b;
+    }
+    sc.cnt = (int *)(ws + L.pendcnt);  // zeroed by the column statistics
+    sc.idx = (int *)(ws + L.pendidx);
+    return sc;
+}
+
+// The mixed form's double polish of one problem.
+static PolishArgs make_polish_args(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt, int max_outer,
+                                   int max_sweeps, int max_rounds)
+{
+    const int64_t n = L.n;
+    PolishArgs q{};
+    q.Xt = (const double *)(ws + L.xt);
+    q.S32 = (const float *)(ws + L.S);
+    q.n = n;
+    q.p = L.p;
+    q.lambda0 = opt->lambda0;
+    q.tol = opt->tol;
+    q.max_outer = max_outer;
+    q.max_sweeps = max_sweeps;
+    q.max_rounds = max_rounds;
+    q.band = (float)kMixedBand;
+    q.w_cnt32 = (const int *)(ws + L.wcnt);
+    q.w_idx32 = (const int *)(ws + L.widx);
+    q.w_beta32 = (const float *)(ws + L.wbeta);
+    q.sigma32 = (const double *)(ws + L.sigma);
+    q.lam32 = (const double *)(ws + L.lam);
+    q.band_cnt = (const int *)(ws + L.bandcnt);
+    q.band_idx = (const int *)(ws + L.bandidx);
+    q.col_status32 = (const int *)(ws + L.cstat);
+    // |S32 - S64| per entry: bfloat16 split (3 * 2^-16) plus float
+    // accumulation over n terms; plus float rounding of the gradient
+    q.eps = 3.0 * std::ldexp(1.0, -16) + (double)(n + 2) * std::ldexp(1.0, -24) + 1e-6;
+    q.esc_cnt = &dctl->esc_polish;
+    q.esc_list = (int *)(ws + L.esclist64);
+    q.w_cnt = (int *)(ws + L.wcnt64);
+    q.w_idx = (int *)(ws + L.widx64);
+    q.w_beta = (double *)(ws + L.wbeta64);
+    q.sigma = (double *)(ws + L.sigma64);
+    q.lam_used = (double *)(ws + L.lam64);
+    q.col_status = (int *)(ws + L.cstat64);
+    q.polinfo = (int *)(ws + L.polinfo);
+    q.flags = &dctl->flags;
+    q.full_kkt = (opt->flags & SPMESL_FLAG_FULL_KKT) ? 1 : 0;
+    q.dense_cnt = &dctl->dense64;
+    q.dense_list = (int *)(ws + L.dq64);
+    return q;
+}
+
+// The columns whose double working sets outgrow the polish's: the dense
+// tier in double, from the float solution, with S[V, V] and the gradients
+// taken from the standardised data.
+static void enqueue_dense64(const PolishArgs &q, const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt,
+                            const Tune &tu, hipStream_t s, Marker *mk)
+{
+    DenseArgs<double> d{};
+    d.S = nullptr;
+    d.Xt = q.Xt;
+    d.n = L.n;
+    d.p = L.p;
+    d.pv = L.p;
+    d.lambda0 = opt->lambda0;
+    d.tol = opt->tol;
+    d.kkt_tol = opt->tol;
+    d.max_outer = q.max_outer;
+    d.max_sweeps = q.max_sweeps;
+    d.max_rounds = q.max_rounds;
+    d.block = tu.dense_block;
+    d.queue = q.dense_list;
+    d.qcnt = q.dense_cnt;
+    d.w_cnt = q.w_cnt;
+    d.w_idx = q.w_idx;
+    d.w_beta = q.w_beta;
+    d.w_off = (int *)(ws + L.woff64);
+    d.sigma = q.sigma;
+    d.lam_used = q.lam_used;
+    d.col_status = q.col_status;
+    d.pool_cnt = &dctl->pool64;
+    d.pool_cap = L.pool_cap;
+    d.band_cnt = nullptr;
+    d.info = q.polinfo;
+    d.info_stride = 8;
+    d.mark = (int *)(ws + L.dmark);
+    d.V = (int *)(ws + L.dv);
+    d.Vold = (int *)(ws + L.dvold);
+    d.R = (double *)(ws + L.dr);
+    d.Bd = (double *)(ws + L.dbd);
+    d.Bp = (double *)(ws + L.dbp);
+    d.vcap = L.p;
+    d.sk = (double *)(ws + L.dsk);
+    d.Svv = (double *)(ws + L.dsvv);
+    d.svv_cap = L.svv_cap;
+    d.E = (double *)(ws + L.de);
+    d.counters = dctl->counters;
+    d.flags = &dctl->flags;
+    DenseSrc<float> src{};
+    src.cnt = q.w_cnt32;
+    src.idx = q.w_idx32;
+    src.beta = q.w_beta32;
+    src.off = (const int *)(ws + L.woff);
+    src.sigma = q.sigma32;
+    src.pend_cnt = (const int *)(ws + L.pendcnt);
+    src.pend_idx = (const int *)(ws + L.pendidx);
+    launch_dense<double, float>(d, src, s, L.sgroups);
+    mark(mk, s, "dense_polish");
+}
+
+// The statistics reduction of one problem (reads only the column results).
+static void enqueue_reduce_stats(const Plan &L, char *ws, Ctl *dctl, hipStream_t s)
+{
+    const bool mixed = L.prec == SPMESL_MIXED;
+    launch_reduce_stats(L.p, (const int *)(ws + L.colinfo), mixed ? (const int *)(ws + L.polinfo) : nullptr,
+                        (const int *)(ws + (mixed ? L.wcnt64 : L.wcnt)),
+                        (const int *)(ws + (mixed ? L.cstat64 : L.cstat)), dctl->counters, &dctl->status1, s);
+}
+
+// B, sigma and Omega of one problem from its column results.
+static void enqueue_scatter(const Plan &L, char *ws, Ctl *dctl, const spmesl_result *res, int original,
+                            hipStream_t s)
+{
+    const int64_t p = L.p;
+    const double *scale = (const double *)(ws + L.scale);
+    if (L.prec == SPMESL_FP64)
+        launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
+                                       (const double *)(ws + L.wbeta), (const int *)(ws + L.woff),
+                                       (const double *)(ws + L.sigma), scale, original, res->B, res->sigma,
+                                       res->Omega, &dctl->flags, s);
+    else if (L.prec == SPMESL_FP32)
+        launch_scatter_outputs<float>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
+                                      (const float *)(ws + L.wbeta), (const int *)(ws + L.woff),
+                                      (const double *)(ws + L.sigma), scale, original, res->B, res->sigma,
+                                      res->Omega, &dctl->flags, s);
+    else
+        launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt64), (const int *)(ws + L.widx64),
+                                       (const double *)(ws + L.wbeta64), (const int *)(ws + L.woff64),
+                                       (const double *)(ws + L.sigma64), scale, original, res->B, res->sigma,
+                                       res->Omega, &dctl->flags, s);
+}
+
 // Enqueue one full solve.  ws: workspace base laid out by `L`; dctl: this
 // problem's control block.  Records the phase events when `ev` is non-null.
 static int enqueue_data_form(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
@@ -736,11 +954,9 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     const int max_outer = opt->max_outer > 0 ? opt->max_outer : 1000;
     const int max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 100000;
     const int max_rounds = opt->max_rounds > 0 ? opt->max_rounds : 64;
-    double *mean = (double *)(ws + L.mean);
     double *scale = (double *)(ws + L.scale);
     const int original = opt->output_scale == SPMESL_SCALE_ORIGINAL;
     const Tune tu = resolve_tune(ctx->tune);
-    const double screen = tu.screen_permille * 1e-3;
 
     if (ev) HIPTRY(ctx, hipEventRecord(ev[0], s));
     Marker marker(ctx);
@@ -748,24 +964,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     mark(mk, s, nullptr);
     launch_zero_words((uint32_t *)dctl, sizeof(Ctl) / 4, s);
     mark(mk, s, "zero_control");
-    if (L.prec == SPMESL_MIXED &&
-        launch_stats_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
-                           (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, &dctl->flags,
-                           (int *)(ws + L.pendcnt), s)) {
-        mark(mk, s, "standardize");
-    } else {
-        launch_colstats(prob->X, n, p, prob->ldx, (double *)(ws + L.partial), L.rchunks, mean, scale,
-                        &dctl->flags, (int *)(ws + L.pendcnt), s);
-        mark(mk, s, "colstats");
-        if (L.prec == SPMESL_FP64)
-            launch_standardize_f64(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xs), s);
-        else if (L.prec == SPMESL_FP32)
-            launch_standardize_f32(prob->X, n, p, prob->ldx, mean, scale, (float *)(ws + L.xs), s);
-        else
-            launch_standardize_split(prob->X, n, p, prob->ldx, mean, scale, (double *)(ws + L.xt),
-                                     (uint16_t *)(ws + L.hi), (uint16_t *)(ws + L.lo), L.npad, s);
-        mark(mk, s, "standardize");
-    }
+    enqueue_standardize(L, prob, ws, dctl, s, mk);
     // The zero fill of the outputs goes on the second stream under the
     // covariance kernel, which leaves HBM to it (double: MFMA-bound, 290 us at
     // p = 5000; mixed: it slows that kernel from 86 to about 102 us), so that
@@ -784,24 +983,8 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     }
     if (ev) HIPTRY(ctx, hipEventRecord(ev[1], s));
 
-    // the first solves' working sets, {j : |s_jk| > f lambda0 +
-    // tol}, are taken where S is written.  At beta = 0 the KKT test is
-    // |s_jk| > lambda0 + tol; the final lambda is sigma lambda0 with sigma < 1,
-    // so the lower factor starts most columns on their final support (a
-    // strong-rule style start: the row-tiled KKT pass still checks every
-    // column, so the factor changes the work, never the result)
-    const double tol_cols = L.prec == SPMESL_FP64
-                                ? opt->tol
-                                : std::max(opt->tol, L.prec == SPMESL_MIXED ? kMixedFloatTol
-                                                                            : (double)SPMESL_FP32_TOL_FLOOR);
-    Screen sc;
-    sc.thr64 = screen * opt->lambda0 + tol_cols;
-    {
-        volatile float a = (float)(screen * opt->lambda0), b = (float)tol_cols;
-        sc.thr32 = a + b;
-    }
-    sc.cnt = (int *)(ws + L.pendcnt);  // zeroed by the column statistics
-    sc.idx = (int *)(ws + L.pendidx);
+    const double tol_cols = column_tol(L, opt);
+    const Screen sc = make_screen(L, ws, opt, tu, tol_cols);
     // the covariance kernel's span starts here, after the fork and phase events
     mark(mk, s, nullptr);
     if (L.prec == SPMESL_FP64)
@@ -842,110 +1025,19 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
 
     if (L.prec == SPMESL_MIXED) {
-        PolishArgs q{};
-        q.Xt = (const double *)(ws + L.xt);
-        q.S32 = (const float *)(ws + L.S);
-        q.n = n;
-        q.p = p;
-        q.lambda0 = opt->lambda0;
-        q.tol = opt->tol;
-        q.max_outer = max_outer;
-        q.max_sweeps = max_sweeps;
-        q.max_rounds = max_rounds;
-        q.band = (float)kMixedBand;
-        q.w_cnt32 = (const int *)(ws + L.wcnt);
-        q.w_idx32 = (const int *)(ws + L.widx);
-        q.w_beta32 = (const float *)(ws + L.wbeta);
-        q.sigma32 = (const double *)(ws + L.sigma);
-        q.lam32 = (const double *)(ws + L.lam);
-        q.band_cnt = (const int *)(ws + L.bandcnt);
-        q.band_idx = (const int *)(ws + L.bandidx);
-        q.col_status32 = (const int *)(ws + L.cstat);
-        // |S32 - S64| per entry: bfloat16 split (3 * 2^-16) plus float
-        // accumulation over n terms; plus float rounding of the gradient
-        q.eps = 3.0 * std::ldexp(1.0, -16) + (double)(n + 2) * std::ldexp(1.0, -24) + 1e-6;
-        q.esc_cnt = &dctl->esc_polish;
-        q.esc_list = (int *)(ws + L.esclist64);
-        q.w_cnt = (int *)(ws + L.wcnt64);
-        q.w_idx = (int *)(ws + L.widx64);
-        q.w_beta = (double *)(ws + L.wbeta64);
-        q.sigma = (double *)(ws + L.sigma64);
-        q.lam_used = (double *)(ws + L.lam64);
-        q.col_status = (int *)(ws + L.cstat64);
-        q.polinfo = (int *)(ws + L.polinfo);
-        q.flags = &dctl->flags;
-        q.full_kkt = (opt->flags & SPMESL_FLAG_FULL_KKT) ? 1 : 0;
-        q.dense_cnt = &dctl->dense64;
-        q.dense_list = (int *)(ws + L.dq64);
+        const PolishArgs q = make_polish_args(L, ws, dctl, opt, max_outer, max_sweeps, max_rounds);
         launch_polish(q, s);
         mark(mk, s, "polish");
-        // the columns whose double working sets outgrow the polish's: the
-        // dense tier in double, from the float solution, with S[V, V] and the
-        // gradients taken from the standardised data
-        DenseArgs<double> d{};
-        d.S = nullptr;
-        d.Xt = q.Xt;
-        d.n = n;
-        d.p = p;
-        d.pv = p;
-        d.lambda0 = opt->lambda0;
-        d.tol = opt->tol;
-        d.kkt_tol = opt->tol;
-        d.max_outer = max_outer;
-        d.max_sweeps = max_sweeps;
-        d.max_rounds = max_rounds;
-        d.block = tu.dense_block;
-        d.queue = q.dense_list;
-        d.qcnt = q.dense_cnt;
-        d.w_cnt = q.w_cnt;
-        d.w_idx = q.w_idx;
-        d.w_beta = q.w_beta;
-        d.w_off = (int *)(ws + L.woff64);
-        d.sigma = q.sigma;
-        d.lam_used = q.lam_used;
-        d.col_status = q.col_status;
-        d.pool_cnt = &dctl->pool64;
-        d.pool_cap = L.pool_cap;
-        d.band_cnt = nullptr;
-        d.info = q.polinfo;
-        d.info_stride = 8;
-        d.mark = (int *)(ws + L.dmark);
-        d.V = (int *)(ws + L.dv);
-        d.Vold = (int *)(ws + L.dvold);
-        d.R = (double *)(ws + L.dr);
-        d.Bd = (double *)(ws + L.dbd);
-        d.Bp = (double *)(ws + L.dbp);
-        d.vcap = L.p;
-        d.sk = (double *)(ws + L.dsk);
-        d.Svv = (double *)(ws + L.dsvv);
-        d.svv_cap = L.svv_cap;
-        d.E = (double *)(ws + L.de);
-        d.counters = dctl->counters;
-        d.flags = &dctl->flags;
-        DenseSrc<float> src{};
-        src.cnt = q.w_cnt32;
-        src.idx = q.w_idx32;
-        src.beta = q.w_beta32;
-        src.off = (const int *)(ws + L.woff);
-        src.sigma = q.sigma32;
-        src.pend_cnt = (const int *)(ws + L.pendcnt);
-        src.pend_idx = (const int *)(ws + L.pendidx);
-        launch_dense<double, float>(d, src, s, L.sgroups);
-        mark(mk, s, "dense_polish");
+        enqueue_dense64(q, L, ws, dctl, opt, tu, s, mk);
     }
     {
         // the statistics reduction reads only the column results: it runs on
         // the second stream (behind the fill it may still hold) while the
         // scatter runs here, and the solve ends when both are done
-        const bool mixed = L.prec == SPMESL_MIXED;
         HIPTRY(ctx, hipEventRecord(ctx->fork2, s));
         HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork2, 0));
         mark(mk, ctx->side, nullptr);
-        launch_reduce_stats(p, (const int *)(ws + L.colinfo),
-                            mixed ? (const int *)(ws + L.polinfo) : nullptr,
-                            (const int *)(ws + (mixed ? L.wcnt64 : L.wcnt)),
-                            (const int *)(ws + (mixed ? L.cstat64 : L.cstat)), dctl->counters,
-                            &dctl->status1, ctx->side);
+        enqueue_reduce_stats(L, ws, dctl, ctx->side);
         mark(mk, ctx->side, "reduce_stats");
         HIPTRY(ctx, hipEventRecord(ctx->join2, ctx->side));
     }
@@ -953,21 +1045,7 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
 
     if (fill) HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join, 0));
     mark(mk, s, "wait_fill");
-    if (L.prec == SPMESL_FP64)
-        launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
-                                       (const double *)(ws + L.wbeta), (const int *)(ws + L.woff), (const double *)(ws + L.sigma),
-                                       scale, original, res->B, res->sigma, res->Omega,
-                                       &dctl->flags, s);
-    else if (L.prec == SPMESL_FP32)
-        launch_scatter_outputs<float>(p, (const int *)(ws + L.wcnt), (const int *)(ws + L.widx),
-                                      (const float *)(ws + L.wbeta), (const int *)(ws + L.woff), (const double *)(ws + L.sigma),
-                                      scale, original, res->B, res->sigma, res->Omega,
-                                       &dctl->flags, s);
-    else
-        launch_scatter_outputs<double>(p, (const int *)(ws + L.wcnt64), (const int *)(ws + L.widx64),
-                                       (const double *)(ws + L.wbeta64), (const int *)(ws + L.woff64),
-                                       (const double *)(ws + L.sigma64), scale, original, res->B,
-                                       res->sigma, res->Omega, &dctl->flags, s);
+    enqueue_scatter(L, ws, dctl, res, original, s);
     mark(mk, s, "scatter");
     HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join2, 0));
     if (ev) HIPTRY(ctx, hipEventRecord(ev[5], s));
@@ -1165,6 +1243,294 @@ static int decode(const Ctl &c, int64_t p, spmesl_stats *st)
     return SPMESL_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// The grouped batch (mixed form).  Every step of the path runs once for all
+// problems: the covariance tiles, the first solves, the row-tiled KKT pass,
+// the re-solves, the escalations and the polish each take one launch whose
+// work items span the problems (a table of per-problem arguments, and the
+// offsets of each problem's items), so that small problems and the slow
+// columns of each fill the chip together instead of one problem's tail at a
+// time.  Each problem keeps its own workspace region and control block; a
+// column's arithmetic is that of the single solve.
+// ---------------------------------------------------------------------------
+struct BatchTabs {
+    // uploaded from the host: the tables and the host-known offsets
+    size_t first, resume, wide, kkt, polish, syrk, col_off, tile_off, kkt_off, upload;
+    // written on the device: offsets of the device-counted lists
+    size_t dirty_off, esc_off, escp_off;
+    size_t bytes;
+};
+
+static BatchTabs batch_tabs(int count)
+{
+    BatchTabs t{};
+    Bump b;
+    const size_t c = (size_t)count, offs = (c + 1) * sizeof(int64_t);
+    t.first = b.take(c * sizeof(ColArgs<float>));
+    t.resume = b.take(c * sizeof(ColArgs<float>));
+    t.wide = b.take(c * sizeof(ColArgs<float>));
+    t.kkt = b.take(c * sizeof(KktJob<float>));
+    t.polish = b.take(c * sizeof(PolishArgs));
+    t.syrk = b.take(c * sizeof(SyrkJob));
+    t.col_off = b.take(offs);
+    t.tile_off = b.take(offs);
+    t.kkt_off = b.take(offs);
+    t.upload = b.cur;
+    t.dirty_off = b.take(offs);
+    t.esc_off = b.take(offs);
+    t.escp_off = b.take(offs);
+    t.bytes = b.cur;
+    return t;
+}
+
+// The grouped layout: problem i's workspace at ws_off[i], the control blocks
+// at ctl_off, the tables at tab_off.
+struct BatchLayout {
+    std::vector<size_t> ws_off;
+    size_t ctl_off = 0, tab_off = 0, total = 0;
+    BatchTabs t{};
+};
+
+// Whether these problems run grouped: two or more, the mixed form in the
+// covariance form, no warm starts, and a row of every S within the LDS of
+// the row-tiled KKT pass.
+static bool batch_grouped(int count, const spmesl_problem *probs, const spmesl_options *opt)
+{
+    if (count < 2 || opt->precision != SPMESL_MIXED || (opt->flags & SPMESL_FLAG_DATA_FORM)) return false;
+    for (int i = 0; i < count; ++i) {
+        if (probs[i].B0 || probs[i].sigma0) return false;
+        if (kkt_rows_per_block(probs[i].p, sizeof(float), (size_t)160 * 1024) <= 0) return false;
+    }
+    return true;
+}
+
+static BatchLayout batch_layout(int count, const std::vector<Plan> &plans)
+{
+    BatchLayout b;
+    b.ws_off.resize((size_t)count);
+    size_t o = 0;
+    for (int i = 0; i < count; ++i) {
+        b.ws_off[(size_t)i] = o;
+        o += align_up(plans[(size_t)i].total, 256);
+    }
+    b.ctl_off = o;
+    b.tab_off = align_up(o + (size_t)count * sizeof(Ctl), 256);
+    b.t = batch_tabs(count);
+    b.total = b.tab_off + b.t.bytes;
+    return b;
+}
+
+static int ensure_stage(spmesl_ctx *ctx, size_t bytes)
+{
+    if (ctx->stage_bytes >= bytes) return SPMESL_OK;
+    if (ctx->stage) {
+        // a previous upload from it may still be in flight
+        HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+        (void)hipHostFree(ctx->stage);
+    }
+    ctx->stage = nullptr;
+    ctx->stage_bytes = 0;
+    HIPTRY(ctx, hipHostMalloc((void **)&ctx->stage, bytes, hipHostMallocDefault));
+    ctx->stage_bytes = bytes;
+    return SPMESL_OK;
+}
+
+// Fill the zero of the dense outputs of every problem on the second stream
+// (`which` as in fork_output_fill).
+static int fork_batch_fill(spmesl_ctx *ctx, int count, const spmesl_result *res, const std::vector<Plan> &plans,
+                           hipStream_t s, int which)
+{
+    const int fb = resolve_tune(ctx->tune).fill_blocks;
+    bool any = false;
+    for (int i = 0; i < count; ++i) any = any || ((which & 1) && res[i].B) || ((which & 2) && res[i].Omega);
+    if (!any) return SPMESL_OK;
+    HIPTRY(ctx, hipEventRecord(ctx->fork, s));
+    HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    for (int i = 0; i < count; ++i) {
+        const int64_t p = plans[(size_t)i].p;
+        if ((which & 1) && res[i].B) launch_fill_zero(res[i].B, p * p, ctx->side, fb);
+        if ((which & 2) && res[i].Omega) launch_fill_zero(res[i].Omega, p * p, ctx->side, fb);
+    }
+    HIPTRY(ctx, hipEventRecord(ctx->join, ctx->side));
+    return SPMESL_OK;
+}
+
+// Build the launch tables of a grouped batch into the host staging buffer.
+// Returns the grid sizes the launches need.
+struct BatchGrids {
+    int64_t cols = 0, tiles = 0, kkt_blocks = 0, pmax = 0;
+    int rj = 4;
+};
+
+static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_options *opts,
+                                     const std::vector<Plan> &plans, const BatchLayout &B, unsigned char *h)
+{
+    const Tune tu = resolve_tune(ctx->tune);
+    const BatchTabs &t = B.t;
+    char *ws0 = ctx->ws;
+    Ctl *dctl = (Ctl *)(ws0 + B.ctl_off);
+    BatchGrids gr;
+    for (int i = 0; i < count; ++i) gr.rj = std::min(gr.rj, kkt_rows_for<float>(plans[(size_t)i].p, 0, tu));
+    auto *first = (ColArgs<float> *)(h + t.first);
+    auto *resume = (ColArgs<float> *)(h + t.resume);
+    auto *wide = (ColArgs<float> *)(h + t.wide);
+    auto *kkt = (KktJob<float> *)(h + t.kkt);
+    auto *pol = (PolishArgs *)(h + t.polish);
+    auto *syrk = (SyrkJob *)(h + t.syrk);
+    auto *col_off = (int64_t *)(h + t.col_off);
+    auto *tile_off = (int64_t *)(h + t.tile_off);
+    auto *kkt_off = (int64_t *)(h + t.kkt_off);
+    col_off[0] = tile_off[0] = kkt_off[0] = 0;
+    for (int i = 0; i < count; ++i) {
+        const Plan &L = plans[(size_t)i];
+        const spmesl_options *opt = &opts[i];
+        char *ws = ws0 + B.ws_off[(size_t)i];
+        Ctl *c = dctl + i;
+        const int max_outer = opt->max_outer > 0 ? opt->max_outer : 1000;
+        const int max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 100000;
+        const int max_rounds = opt->max_rounds > 0 ? opt->max_rounds : 64;
+        const double tol_cols = column_tol(L, opt);
+        const Screen sc = make_screen(L, ws, opt, tu, tol_cols);
+        int64_t tiles = 0, blocks = 0;
+        syrk[i] = syrk_job_bf16x3((const uint16_t *)(ws + L.hi), (const uint16_t *)(ws + L.lo), L.n, L.npad, L.p,
+                                  (float *)(ws + L.S), sc, &tiles);
+        ColArgs<float> a = make_col_args<float>(L, ws, c, opt, tol_cols, kMixedBand, max_outer, max_sweeps,
+                                                max_rounds, 0, false);
+        a.mode = 0;
+        a.screened = 1;
+        a.defer_kkt = 1;
+        a.esc_cnt = &c->esc_c;
+        a.esc_list = (int *)(ws + L.esclist2);
+        first[i] = a;
+        kkt[i] = kkt_job<float>(make_kkt_args<float>(a, L, ws, c), gr.rj, &blocks);
+        a.mode = 1;
+        a.screened = 0;
+        a.work_list = (const int *)(ws + L.dirtylist);
+        a.work_cnt = &c->dirty;
+        resume[i] = a;
+        a.work_list = (const int *)(ws + L.esclist2);
+        a.work_cnt = &c->esc_c;
+        wide[i] = a;
+        pol[i] = make_polish_args(L, ws, c, opt, max_outer, max_sweeps, max_rounds);
+        col_off[i + 1] = col_off[i] + L.p;
+        tile_off[i + 1] = tile_off[i] + tiles;
+        kkt_off[i + 1] = kkt_off[i] + blocks;
+        gr.pmax = std::max(gr.pmax, L.p);
+    }
+    gr.cols = col_off[count];
+    gr.tiles = tile_off[count];
+    gr.kkt_blocks = kkt_off[count];
+    return gr;
+}
+
+static int enqueue_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
+                                 const spmesl_options *opts, const spmesl_result *res, const std::vector<Plan> &plans,
+                                 const BatchLayout &B, const BatchGrids &gr)
+{
+    hipStream_t s = ctx->stream;
+    const Tune tu = resolve_tune(ctx->tune);
+    char *ws0 = ctx->ws;
+    Ctl *dctl = (Ctl *)(ws0 + B.ctl_off);
+    const unsigned char *tb = (const unsigned char *)(ws0 + B.tab_off);
+    const BatchTabs &t = B.t;
+    const auto *col_off = (const int64_t *)(tb + t.col_off);
+    auto *dirty_off = (int64_t *)(tb + t.dirty_off);
+    auto *esc_off = (int64_t *)(tb + t.esc_off);
+    auto *escp_off = (int64_t *)(tb + t.escp_off);
+    const int64_t ctl_words = (int64_t)(sizeof(Ctl) / sizeof(int));
+    auto wsi = [&](int i) { return ws0 + B.ws_off[(size_t)i]; };
+
+    launch_zero_words((uint32_t *)dctl, (int64_t)count * (int64_t)(sizeof(Ctl) / 4), s);
+    for (int i = 0; i < count; ++i) enqueue_standardize(plans[(size_t)i], &probs[i], wsi(i), dctl + i, s, nullptr);
+    const int early = tu.fill_split == 0 ? 3 : (tu.fill_split == 1 ? 1 : 0);
+    const int late = 3 & ~early;
+    int v = early ? fork_batch_fill(ctx, count, res, plans, s, early) : (int)SPMESL_OK;
+    if (v != SPMESL_OK) return v;
+    launch_syrk_bf16x3_grouped((const SyrkJob *)(tb + t.syrk), (const int64_t *)(tb + t.tile_off), count, gr.tiles,
+                               s);
+    launch_colsolve_first_grouped<float>((const ColArgs<float> *)(tb + t.first), col_off, count, gr.cols, s);
+    launch_kkt_rows_grouped<float>((const KktJob<float> *)(tb + t.kkt), (const int64_t *)(tb + t.kkt_off), count,
+                                   gr.kkt_blocks, gr.rj, gr.pmax, s);
+    if (late && (v = fork_batch_fill(ctx, count, res, plans, s, late)) != SPMESL_OK) return v;
+    // re-solves of the flagged columns, then every escalated column (the
+    // first solves' and the re-solves') in the wide tier
+    launch_group_offsets(&dctl->dirty, ctl_words, count, dirty_off, s);
+    launch_colsolve_list_grouped<float>((const ColArgs<float> *)(tb + t.resume), dirty_off, count, 0, s);
+    launch_group_offsets(&dctl->esc_c, ctl_words, count, esc_off, s);
+    launch_colsolve_list_grouped<float>((const ColArgs<float> *)(tb + t.wide), esc_off, count, 1, s);
+    // the double polish of every column, then its escalations
+    const PolishArgs *ptab = (const PolishArgs *)(tb + t.polish);
+    launch_polish_grouped(ptab, col_off, count, gr.cols, 0, s);
+    launch_group_offsets(&dctl->esc_polish, ctl_words, count, escp_off, s);
+    launch_polish_grouped(ptab, escp_off, count, gr.cols, 1, s);
+    std::vector<PolishArgs> q((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const spmesl_options *opt = &opts[i];
+        q[(size_t)i] = make_polish_args(plans[(size_t)i], wsi(i), dctl + i, opt,
+                                        opt->max_outer > 0 ? opt->max_outer : 1000,
+                                        opt->max_sweeps > 0 ? opt->max_sweeps : 100000,
+                                        opt->max_rounds > 0 ? opt->max_rounds : 64);
+        enqueue_dense64(q[(size_t)i], plans[(size_t)i], wsi(i), dctl + i, opt, tu, s, nullptr);
+    }
+    HIPTRY(ctx, hipEventRecord(ctx->fork2, s));
+    HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork2, 0));
+    for (int i = 0; i < count; ++i) enqueue_reduce_stats(plans[(size_t)i], wsi(i), dctl + i, ctx->side);
+    HIPTRY(ctx, hipEventRecord(ctx->join2, ctx->side));
+    bool fill = false;
+    for (int i = 0; i < count; ++i) fill = fill || res[i].B || res[i].Omega;
+    if (fill) HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join, 0));
+    for (int i = 0; i < count; ++i)
+        enqueue_scatter(plans[(size_t)i], wsi(i), dctl + i, &res[i], opts[i].output_scale == SPMESL_SCALE_ORIGINAL,
+                        s);
+    HIPTRY(ctx, hipStreamWaitEvent(s, ctx->join2, 0));
+    HIPTRY(ctx, hipGetLastError());
+    return SPMESL_OK;
+}
+
+
+static int solve_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
+                               const std::vector<spmesl_options> &opts, spmesl_result *res, int *status,
+                               const std::vector<Plan> &plans)
+{
+    const BatchLayout B = batch_layout(count, plans);
+    int v = ensure_workspace(ctx, B.total);
+    if (v != SPMESL_OK) return v;
+    if ((v = ensure_pinned(ctx, (size_t)count)) != SPMESL_OK) return v;
+    if ((v = ensure_stage(ctx, B.t.upload)) != SPMESL_OK) return v;
+    ctx->nmarks = 0;
+    // the tables hold workspace addresses: built for this workspace, and
+    // uploaded ahead of the solves (outside any graph)
+    const BatchGrids gr = build_batch_tables(ctx, count, opts.data(), plans, B, ctx->stage);
+    HIPTRY(ctx, hipMemcpyAsync(ctx->ws + B.tab_off, ctx->stage, B.t.upload, hipMemcpyHostToDevice, ctx->stream));
+    const spmesl_options *opt = &opts[0];
+    auto body = [&] { return enqueue_batch_grouped(ctx, count, probs, opts.data(), res, plans, B, gr); };
+    if (opt->flags & SPMESL_FLAG_EAGER) {
+        v = body();
+    } else {
+        KeyBuf k;
+        k.add('G');
+        k.add(ctx->ws);
+        k.add(count);
+        key_tuning(k, ctx->tune);
+        for (int i = 0; i < count; ++i) {
+            key_problem(k, probs[i], res[i]);
+            key_options(k, opts[(size_t)i]);
+        }
+        v = run_graph(ctx, std::move(k.b), body);
+    }
+    if (v != SPMESL_OK) return v;
+    Ctl *dctl = (Ctl *)(ctx->ws + B.ctl_off);
+    HIPTRY(ctx, hipMemcpyAsync(ctx->pinned, dctl, (size_t)count * sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    int first = SPMESL_OK;
+    for (int i = 0; i < count; ++i) {
+        status[i] = decode(ctx->pinned[i], probs[i].p, res[i].stats);
+        if (first == SPMESL_OK && status[i] != SPMESL_OK) first = status[i];
+    }
+    return first;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -1228,6 +1594,7 @@ void spmesl_destroy(spmesl_ctx *ctx)
         if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
         if (ctx->tune_status) (void)hipFree(ctx->tune_status);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        if (ctx->stage) (void)hipHostFree(ctx->stage);
         for (int i = 0; i < 6; ++i)
             if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     }
@@ -1537,6 +1904,12 @@ int spmesl_batch_workspace_size(const spmesl_ctx *ctx, int count, const spmesl_p
         need = std::max(need, make_plan(probs[i].n, probs[i].p, opt->precision,
                                         opt->flags & SPMESL_FLAG_DATA_FORM).total);
     }
+    if (batch_grouped(count, probs, opt)) {
+        std::vector<Plan> plans((size_t)count);
+        for (int i = 0; i < count; ++i) plans[(size_t)i] = make_plan(probs[i].n, probs[i].p, opt->precision);
+        *bytes = batch_layout(count, plans).total;
+        return SPMESL_OK;
+    }
     *bytes = align_up(need, 256) + (size_t)std::max(count, 1) * sizeof(Ctl);
     return SPMESL_OK;
 }
@@ -1561,6 +1934,7 @@ int spmesl_solve_batch(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
         plans[(size_t)i] = make_plan(probs[i].n, probs[i].p, opt->precision, opt->flags & SPMESL_FLAG_DATA_FORM);
         need = std::max(need, plans[(size_t)i].total);
     }
+    if (batch_grouped(count, probs, opt)) return solve_batch_grouped(ctx, count, probs, opts, res, status, plans);
     size_t ctl_off = align_up(need, 256);
     int v = ensure_workspace(ctx, ctl_off + (size_t)count * sizeof(Ctl));
     if (v != SPMESL_OK) return v;

@@ -343,6 +343,67 @@ void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s)
     }
 }
 
+// The first solves of many problems in one launch: block b solves column
+// k0 + b - off[d] of problem d (the row-tiled pass follows, as in the
+// single-problem first solves).
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_colsolve_first_grouped(const ColArgs<T> *__restrict__ tab,
+                                                                  const int64_t *__restrict__ off, int nd)
+{
+    __shared__ WaveSm<T, 32> sm;
+    const int64_t g = blockIdx.x;
+    const int d = group_of(off, nd, g);
+    const ColArgs<T> &A = tab[d];
+    solve_column<T, 32, 4, 2, true, true>(A, sm, A.k0 + (g - off[d]), 0);
+}
+
+// The list-driven solves of many problems: item g is entry g - off[d] of
+// problem d's work list; one wave per column (no shared KKT passes).
+template <typename T, int LW, int NW, int KCH, int KU>
+__global__ __launch_bounds__(kWave *NW) void k_colsolve_list_grouped(const ColArgs<T> *__restrict__ tab,
+                                                                     const int64_t *__restrict__ off, int nd,
+                                                                     int tier)
+{
+    __shared__ WaveSm<T, LW> smem[NW];
+    const int wv = threadIdx.x / kWave;
+    const int64_t total = off[nd];
+    for (int64_t g = (int64_t)blockIdx.x * NW + wv; g < total; g += (int64_t)gridDim.x * NW) {
+        const int d = group_of(off, nd, g);
+        const ColArgs<T> &A = tab[d];
+        solve_column<T, LW, KCH, KU, false, (NW > 1)>(A, smem[wv], (int64_t)A.work_list[g - off[d]], tier);
+    }
+}
+
+template <typename T>
+void launch_colsolve_first_grouped(const ColArgs<T> *tab, const int64_t *off, int nd, int64_t total,
+                                   hipStream_t s)
+{
+    if (total <= 0) return;
+    hipLaunchKernelGGL((k_colsolve_first_grouped<T>), dim3((unsigned)total), dim3(kWave), 0, s, tab, off, nd);
+}
+
+template <typename T>
+void launch_colsolve_list_grouped(const ColArgs<T> *tab, const int64_t *off, int nd, int tier, hipStream_t s)
+{
+    if (tier == 0) {
+        hipLaunchKernelGGL((k_colsolve_list_grouped<T, 32, 4, 4, 4>), dim3(512), dim3(kWave * 4), 0, s, tab, off,
+                           nd, 0);
+    } else if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_colsolve_list_grouped<T, kWMax, 2, 4, 2>), dim3(256), dim3(kWave * 2), 0, s, tab,
+                           off, nd, 1);
+    } else {
+        hipLaunchKernelGGL((k_colsolve_list_grouped<T, kWMax, 1, 4, 2>), dim3(256), dim3(kWave), 0, s, tab, off,
+                           nd, 1);
+    }
+}
+
+template void launch_colsolve_first_grouped<double>(const ColArgs<double> *, const int64_t *, int, int64_t,
+                                                    hipStream_t);
+template void launch_colsolve_first_grouped<float>(const ColArgs<float> *, const int64_t *, int, int64_t,
+                                                   hipStream_t);
+template void launch_colsolve_list_grouped<double>(const ColArgs<double> *, const int64_t *, int, int, hipStream_t);
+template void launch_colsolve_list_grouped<float>(const ColArgs<float> *, const int64_t *, int, int, hipStream_t);
+
 template void launch_colsolve<double>(const ColArgs<double> &, int, hipStream_t);
 template void launch_colsolve<float>(const ColArgs<float> &, int, hipStream_t);
 

@@ -187,6 +187,40 @@ void launch_syrk_f32(const float *Xs, int64_t n, int64_t p, float *S, const Scre
 void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
                         int64_t p, float *S, const Screen &sc, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Grouped launches: one launch runs the same step of many problems (the
+// batched entry point).  Work items of problem d are g in [off[d], off[d+1])
+// (off has nd + 1 entries); a block or wave finds its problem by bisection.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int group_of(const int64_t *off, int nd, int64_t g)
+{
+    int lo = 0, hi = nd;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// off[0] = 0, off[d + 1] = off[d] + max(0, cnt[d * stride]) for d < nd: the
+// offsets of work lists whose lengths are device counts (one per problem).
+void launch_group_offsets(const int *cnt, int64_t stride, int nd, int64_t *off, hipStream_t s);
+
+// One problem's covariance tiles (the mixed form's kernel).
+struct SyrkJob {
+    const uint16_t *hi, *lo;
+    int64_t npad, p;
+    float *S;
+    int Tt;
+    float invn, thr;
+    int *scnt, *sidx;
+};
+SyrkJob syrk_job_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad, int64_t p, float *S,
+                        const Screen &sc, int64_t *tiles);
+void launch_syrk_bf16x3_grouped(const SyrkJob *tab, const int64_t *tile_off, int nd, int64_t tiles,
+                                hipStream_t s);
+
 // Per-column working-set scaled lasso (see colsolve.hip).
 template <typename T>
 struct ColArgs {
@@ -230,6 +264,14 @@ struct ColArgs {
 // tier: 0 = 32-wide working sets (escalating), 1 = 128-wide
 template <typename T>
 void launch_colsolve(const ColArgs<T> &a, int tier, hipStream_t s);
+// The first solves of many problems (columns off[d] .. off[d+1] - 1 are the
+// columns of problem d), and the list-driven solves (re-solves: tier 0;
+// escalations: tier 1) whose lists' offsets off are device prefix sums.
+template <typename T>
+void launch_colsolve_first_grouped(const ColArgs<T> *tab, const int64_t *off, int nd, int64_t total,
+                                   hipStream_t s);
+template <typename T>
+void launch_colsolve_list_grouped(const ColArgs<T> *tab, const int64_t *off, int nd, int tier, hipStream_t s);
 
 // Columns whose working sets outgrow the 128-coordinate LDS tier (see
 // dense.hip): where their start comes from ...
@@ -316,6 +358,18 @@ struct KktArgs {
 int kkt_rows_per_block(int64_t p, size_t elem, size_t lds_budget);
 template <typename T>
 void launch_kkt_rows(const KktArgs<T> &a, int rj, hipStream_t s);
+// One problem's share of a grouped row-tiled pass: its arguments, rows per
+// block and tile stride; kkt_job also gives the problem's block count.
+template <typename T>
+struct KktJob {
+    KktArgs<T> a;
+    int64_t rpb, bstride;
+};
+template <typename T>
+KktJob<T> kkt_job(const KktArgs<T> &a, int rj, int64_t *blocks);
+template <typename T>
+void launch_kkt_rows_grouped(const KktJob<T> *tab, const int64_t *off, int nd, int64_t blocks, int rj,
+                             int64_t pmax, hipStream_t s);
 
 // Double-precision polish of the float solution (mixed form).
 struct PolishArgs {
@@ -349,6 +403,12 @@ struct PolishArgs {
     int full_kkt;           // 1: every column takes the full KKT pass (no band bound)
 };
 void launch_polish(const PolishArgs &a, hipStream_t s);
+// The polish of many problems: every column (tier2 = 0; off: the problems'
+// column offsets, total: all columns), or the escalated columns (tier2 = 1;
+// off: device prefix sums of the problems' escalation counts, total: an upper
+// bound, which sets the grid).
+void launch_polish_grouped(const PolishArgs *tab, const int64_t *off, int nd, int64_t total, int tier2,
+                           hipStream_t s);
 
 // Reduce the per-column counters and final statuses of one solve into the
 // control block: counters[kNumCounters] and status bits (1 no convergence,

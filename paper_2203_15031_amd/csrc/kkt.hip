@@ -135,15 +135,14 @@ __device__ __forceinline__ const T *kkt_issue_tile(const T *src, int64_t tot, T 
 // threshold lowered by twice that, and every flagged pair is recomputed
 // exactly from the double coefficients before anything is recorded.
 template <typename T, int RJ, int CPT, bool PK>
-__global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t rpb, int64_t bstride)
+__device__ __forceinline__ void kkt_rows_body(const KktArgs<T> &A, int64_t rpb, int64_t bstride, int64_t bid,
+                                              unsigned char *kkt_lds, KktFlagList &fl)
 {
-    extern __shared__ __align__(16) unsigned char kkt_lds[];
-    __shared__ KktFlagList fl;
     T *const buf0 = reinterpret_cast<T *>(kkt_lds);
     if (*A.flags) return;
     if (threadIdx.x == 0) fl.n = 0;  // visible after the chunk loop's first barrier
     const int64_t p = A.p;
-    const int64_t rb = (int64_t)blockIdx.x * rpb;
+    const int64_t rb = bid * rpb;
     const int64_t re = rb + rpb < p ? rb + rpb : p;
     if (rb >= p) return;
     const int tid = threadIdx.x;
@@ -294,6 +293,28 @@ __global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t 
     }
 }
 
+template <typename T, int RJ, int CPT, bool PK>
+__global__ __launch_bounds__(kKktThreads) void k_kkt_rows(KktArgs<T> A, int64_t rpb, int64_t bstride)
+{
+    extern __shared__ __align__(16) unsigned char kkt_lds[];
+    __shared__ KktFlagList fl;
+    kkt_rows_body<T, RJ, CPT, PK>(A, rpb, bstride, blockIdx.x, kkt_lds, fl);
+}
+
+// The same pass over many problems in one launch: block b is block
+// b - off[d] of problem d.
+template <typename T, int RJ, int CPT, bool PK>
+__global__ __launch_bounds__(kKktThreads) void k_kkt_rows_grouped(const KktJob<T> *__restrict__ tab,
+                                                                  const int64_t *__restrict__ off, int nd)
+{
+    extern __shared__ __align__(16) unsigned char kkt_lds[];
+    __shared__ KktFlagList fl;
+    const int64_t b = blockIdx.x;
+    const int d = group_of(off, nd, b);
+    const KktJob<T> &J = tab[d];
+    kkt_rows_body<T, RJ, CPT, PK>(J.a, J.rpb, J.bstride, b - off[d], kkt_lds, fl);
+}
+
 template <typename T, int RJ, int CPT>
 static void launch_kkt_rows_c(const KktArgs<T> &a, hipStream_t s)
 {
@@ -336,5 +357,62 @@ void launch_kkt_rows(const KktArgs<T> &a, int rj, hipStream_t s)
 
 template void launch_kkt_rows<double>(const KktArgs<double> &, int, hipStream_t);
 template void launch_kkt_rows<float>(const KktArgs<float> &, int, hipStream_t);
+
+template <typename T>
+KktJob<T> kkt_job(const KktArgs<T> &a, int rj, int64_t *blocks)
+{
+    int64_t nblk = 256;
+    int64_t rpb = (a.p + nblk - 1) / nblk;
+    rpb = (rpb + rj - 1) / rj * rj;
+    nblk = (a.p + rpb - 1) / rpb;
+    KktJob<T> j{};
+    j.a = a;
+    j.rpb = rpb;
+    j.bstride = kkt_buffer_elems(a.p, rj, sizeof(T));
+    *blocks = nblk;
+    return j;
+}
+
+template <typename T, int RJ, int CPT>
+static void launch_kkt_grouped_c(const KktJob<T> *tab, const int64_t *off, int nd, int64_t blocks, int64_t pmax,
+                                 hipStream_t s)
+{
+    const size_t lds = 2 * (size_t)kkt_buffer_elems(pmax, RJ, sizeof(T)) * sizeof(T);
+    if (pmax <= 65535)
+        hipLaunchKernelGGL((k_kkt_rows_grouped<T, RJ, CPT, true>), dim3((unsigned)blocks), dim3(kKktThreads), lds,
+                           s, tab, off, nd);
+    else
+        hipLaunchKernelGGL((k_kkt_rows_grouped<T, RJ, CPT, false>), dim3((unsigned)blocks), dim3(kKktThreads), lds,
+                           s, tab, off, nd);
+}
+
+template <typename T, int RJ>
+static void launch_kkt_grouped_r(const KktJob<T> *tab, const int64_t *off, int nd, int64_t blocks, int64_t pmax,
+                                 hipStream_t s)
+{
+    const int64_t need = (pmax + kKktThreads - 1) / kKktThreads;
+    if (need <= 1) launch_kkt_grouped_c<T, RJ, 1>(tab, off, nd, blocks, pmax, s);
+    else if (need <= 2) launch_kkt_grouped_c<T, RJ, 2>(tab, off, nd, blocks, pmax, s);
+    else if constexpr (sizeof(T) == 8) launch_kkt_grouped_c<T, RJ, 3>(tab, off, nd, blocks, pmax, s);
+    else if (need <= 3) launch_kkt_grouped_c<T, RJ, 3>(tab, off, nd, blocks, pmax, s);
+    else launch_kkt_grouped_c<T, RJ, 5>(tab, off, nd, blocks, pmax, s);
+}
+
+template <typename T>
+void launch_kkt_rows_grouped(const KktJob<T> *tab, const int64_t *off, int nd, int64_t blocks, int rj,
+                             int64_t pmax, hipStream_t s)
+{
+    if (blocks <= 0) return;
+    if (rj >= 4) launch_kkt_grouped_r<T, 4>(tab, off, nd, blocks, pmax, s);
+    else if (rj == 2) launch_kkt_grouped_r<T, 2>(tab, off, nd, blocks, pmax, s);
+    else launch_kkt_grouped_r<T, 1>(tab, off, nd, blocks, pmax, s);
+}
+
+template KktJob<double> kkt_job<double>(const KktArgs<double> &, int, int64_t *);
+template KktJob<float> kkt_job<float>(const KktArgs<float> &, int, int64_t *);
+template void launch_kkt_rows_grouped<double>(const KktJob<double> *, const int64_t *, int, int64_t, int, int64_t,
+                                              hipStream_t);
+template void launch_kkt_rows_grouped<float>(const KktJob<float> *, const int64_t *, int, int64_t, int, int64_t,
+                                             hipStream_t);
 
 } // namespace spmesl

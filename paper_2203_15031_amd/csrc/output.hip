@@ -21,6 +21,42 @@ __global__ __launch_bounds__(256) void k_zero_words(uint32_t *__restrict__ a, in
         a[i] = 0u;
 }
 
+// Prefix sums of nd device counts (stride apart), by one block: the counts
+// are read in parallel, summed in order by one thread from LDS.
+__global__ __launch_bounds__(1024) void k_group_offsets(const int *__restrict__ cnt, int64_t stride, int nd,
+                                                        int64_t *__restrict__ off)
+{
+    __shared__ int c[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        off[0] = 0;
+    }
+    for (int d0 = 0; d0 < nd; d0 += 1024) {
+        const int d = d0 + (int)threadIdx.x;
+        __syncthreads();
+        if (d < nd) {
+            const int v = cnt[(int64_t)d * stride];
+            c[threadIdx.x] = v > 0 ? v : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t a = carry;
+            const int m = nd - d0 < 1024 ? nd - d0 : 1024;
+            for (int i = 0; i < m; ++i) {
+                a += c[i];
+                off[d0 + i + 1] = a;
+            }
+            carry = a;
+        }
+    }
+}
+
+void launch_group_offsets(const int *cnt, int64_t stride, int nd, int64_t *off, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, s, cnt, stride, nd, off);
+}
+
 void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s)
 {
     if (n <= 0) return;

@@ -513,6 +513,34 @@ __device__ __forceinline__ void polish_column(const PolishArgs &A, WaveSm<double
     }
 }
 
+// The polish of many problems in one launch: item g is column g - off[d]
+// of problem d (tier2 = 0), or entry g - off[d] of its escalation list.
+template <int LW, int NW, int MINW = 1>
+__global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MINW))) void k_polish_grouped(
+    const PolishArgs *__restrict__ tab, const int64_t *__restrict__ off, int nd, int tier2)
+{
+    __shared__ WaveSm<double, LW> smem[NW];
+    const int wv = threadIdx.x / kWave;
+    const int64_t total = off[nd];
+    for (int64_t g = (int64_t)blockIdx.x * NW + wv; g < total; g += (int64_t)gridDim.x * NW) {
+        const int d = group_of(off, nd, g);
+        const PolishArgs &A = tab[d];
+        const int64_t k = tier2 ? (int64_t)A.esc_list[g - off[d]] : g - off[d];
+        polish_column<LW>(A, smem[wv], k, tier2);
+    }
+}
+
+void launch_polish_grouped(const PolishArgs *tab, const int64_t *off, int nd, int64_t total, int tier2,
+                           hipStream_t s)
+{
+    if (total <= 0) return;
+    if (tier2 == 0)
+        hipLaunchKernelGGL((k_polish_grouped<32, 1, 3>), dim3((unsigned)total), dim3(kWave), 0, s, tab, off, nd, 0);
+    else
+        hipLaunchKernelGGL((k_polish_grouped<kWMax, 1>), dim3((unsigned)(total < 256 ? total : 256)), dim3(kWave), 0,
+                           s, tab, off, nd, 1);
+}
+
 void launch_polish(const PolishArgs &a, hipStream_t s)
 {
     // one column per workgroup: a column's slot frees as soon as it is done

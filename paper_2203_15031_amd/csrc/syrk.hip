@@ -398,23 +398,18 @@ __device__ __forceinline__ void bf_issue(const uint16_t *__restrict__ hi, const 
     }
 }
 
-__global__ __launch_bounds__(512) void k_syrk_bf16x3(const uint16_t *__restrict__ hi,
-                                                     const uint16_t *__restrict__ lo,
-                                                     int64_t npad, int64_t p,
-                                                     float *__restrict__ S, int Tt, float invn,
-                                                     float thr, int *__restrict__ scnt,
-                                                     int *__restrict__ sidx)
+// One 256 x 256 tile (bj, bk) of one problem's S, by the whole block.
+__device__ __forceinline__ void bf_tile_run(const uint16_t *__restrict__ hi, const uint16_t *__restrict__ lo,
+                                            int64_t npad, int64_t p, float *__restrict__ S, float invn, float thr,
+                                            int *__restrict__ scnt, int *__restrict__ sidx, int bj, int bk,
+                                            unsigned char *bf_lds)
 {
-    extern __shared__ __align__(16) unsigned char bf_lds[];
     BfScreen &scr = *reinterpret_cast<BfScreen *>(bf_lds + 2 * kBfStage);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 3, wn = w >> 2;
-    const int ntiles = Tt * (Tt + 1) / 2;
     const int nst = (int)(npad / kBfKC);
     const bool vec_ok = (p & 3) == 0;  // rows of S 16-byte aligned
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int bj, bk;
-        bf_tile(t, Tt, &bj, &bk);
+    {
         const int64_t j0 = (int64_t)bj * kBfTile, k0 = (int64_t)bk * kBfTile;
         const bool diag = bj == bk;
         const int pk = diag ? 0 : 2;  // panels the column block reads
@@ -497,6 +492,63 @@ __global__ __launch_bounds__(512) void k_syrk_bf16x3(const uint16_t *__restrict_
         __syncthreads();
         screen_flush_waves(scr, scnt, sidx);
     }
+}
+
+__global__ __launch_bounds__(512) void k_syrk_bf16x3(const uint16_t *__restrict__ hi,
+                                                     const uint16_t *__restrict__ lo,
+                                                     int64_t npad, int64_t p,
+                                                     float *__restrict__ S, int Tt, float invn,
+                                                     float thr, int *__restrict__ scnt,
+                                                     int *__restrict__ sidx)
+{
+    extern __shared__ __align__(16) unsigned char bf_lds[];
+    const int ntiles = Tt * (Tt + 1) / 2;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int bj, bk;
+        bf_tile(t, Tt, &bj, &bk);
+        bf_tile_run(hi, lo, npad, p, S, invn, thr, scnt, sidx, bj, bk, bf_lds);
+    }
+}
+
+// The tiles of many problems in one launch: tile g is tile g - off[d] of
+// problem d (its own upper-triangle order).
+__global__ __launch_bounds__(512) void k_syrk_bf16x3_grouped(const SyrkJob *__restrict__ tab,
+                                                             const int64_t *__restrict__ off, int nd)
+{
+    extern __shared__ __align__(16) unsigned char bf_lds[];
+    const int64_t total = off[nd];
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int d = group_of(off, nd, g);
+        const SyrkJob &J = tab[d];
+        int bj, bk;
+        bf_tile((int)(g - off[d]), J.Tt, &bj, &bk);
+        bf_tile_run(J.hi, J.lo, J.npad, J.p, J.S, J.invn, J.thr, J.scnt, J.sidx, bj, bk, bf_lds);
+    }
+}
+
+SyrkJob syrk_job_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad, int64_t p, float *S,
+                        const Screen &sc, int64_t *tiles)
+{
+    SyrkJob j{};
+    j.hi = hi;
+    j.lo = lo;
+    j.npad = npad;
+    j.p = p;
+    j.S = S;
+    j.Tt = (int)((p + kBfTile - 1) / kBfTile);
+    j.invn = (float)(1.0 / (double)n);
+    j.thr = sc.thr32;
+    j.scnt = sc.cnt;
+    j.sidx = sc.idx;
+    *tiles = (int64_t)j.Tt * (j.Tt + 1) / 2;
+    return j;
+}
+
+void launch_syrk_bf16x3_grouped(const SyrkJob *tab, const int64_t *tile_off, int nd, int64_t tiles, hipStream_t s)
+{
+    if (tiles <= 0) return;
+    const int64_t grid = tiles < 256 ? tiles : 256;
+    hipLaunchKernelGGL(k_syrk_bf16x3_grouped, dim3((unsigned)grid), dim3(512), kBfLds, s, tab, tile_off, nd);
 }
 
 void launch_syrk_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad,
