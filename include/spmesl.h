@@ -245,9 +245,9 @@ int spmesl_solve_noalloc(spmesl_ctx *ctx, const spmesl_problem *prob,
  * except that problem i uses lambda0s[i] when lambda0s (HOST array of count
  * doubles) is not NULL.  status[i] (host) receives each problem's code; the
  * return value is the first non-OK code, or SPMESL_OK.
- * In the mixed form (covariance form, no warm starts, two or more problems,
- * every p within the row-tiled KKT pass's reach: p up to about 20000) the
- * problems run grouped: each step of the path is one launch over the work of
+ * In the covariance forms (not SPMESL_FLAG_DATA_FORM; no warm starts; two or
+ * more problems; every p within the row-tiled KKT pass's reach: p up to about
+ * 20000 in float and mixed, 10000 in double) the problems run grouped: each step of the path is one launch over the work of
  * every problem (the covariance tiles, the first solves, the KKT pass, the
  * re-solves, the escalations and the polish), each problem with its own
  * workspace region; the results equal those of the problems' single solves

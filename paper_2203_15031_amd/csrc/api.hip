@@ -1267,12 +1267,15 @@ static BatchTabs batch_tabs(int count)
     BatchTabs t{};
     Bump b;
     const size_t c = (size_t)count, offs = (c + 1) * sizeof(int64_t);
-    t.first = b.take(c * sizeof(ColArgs<float>));
-    t.resume = b.take(c * sizeof(ColArgs<float>));
-    t.wide = b.take(c * sizeof(ColArgs<float>));
-    t.kkt = b.take(c * sizeof(KktJob<float>));
+    const size_t col = std::max(sizeof(ColArgs<float>), sizeof(ColArgs<double>));
+    const size_t kkt = std::max(sizeof(KktJob<float>), sizeof(KktJob<double>));
+    const size_t syrk = std::max({sizeof(SyrkJob), sizeof(SyrkJobT<float>), sizeof(SyrkJobT<double>)});
+    t.first = b.take(c * col);
+    t.resume = b.take(c * col);
+    t.wide = b.take(c * col);
+    t.kkt = b.take(c * kkt);
     t.polish = b.take(c * sizeof(PolishArgs));
-    t.syrk = b.take(c * sizeof(SyrkJob));
+    t.syrk = b.take(c * syrk);
     t.col_off = b.take(offs);
     t.tile_off = b.take(offs);
     t.kkt_off = b.take(offs);
@@ -1292,15 +1295,15 @@ struct BatchLayout {
     BatchTabs t{};
 };
 
-// Whether these problems run grouped: two or more, the mixed form in the
-// covariance form, no warm starts, and a row of every S within the LDS of
-// the row-tiled KKT pass.
+// Whether these problems run grouped: two or more, the covariance form, no
+// warm starts, and a row of every S within the LDS of the row-tiled KKT pass.
 static bool batch_grouped(int count, const spmesl_problem *probs, const spmesl_options *opt)
 {
-    if (count < 2 || opt->precision != SPMESL_MIXED || (opt->flags & SPMESL_FLAG_DATA_FORM)) return false;
+    if (count < 2 || (opt->flags & SPMESL_FLAG_DATA_FORM)) return false;
+    const size_t elem = opt->precision == SPMESL_FP64 ? sizeof(double) : sizeof(float);
     for (int i = 0; i < count; ++i) {
         if (probs[i].B0 || probs[i].sigma0) return false;
-        if (kkt_rows_per_block(probs[i].p, sizeof(float), (size_t)160 * 1024) <= 0) return false;
+        if (kkt_rows_per_block(probs[i].p, elem, (size_t)160 * 1024) <= 0) return false;
     }
     return true;
 }
@@ -1363,6 +1366,30 @@ struct BatchGrids {
     int rj = 4;
 };
 
+static void limits_of(const spmesl_options *opt, int *max_outer, int *max_sweeps, int *max_rounds)
+{
+    *max_outer = opt->max_outer > 0 ? opt->max_outer : 1000;
+    *max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 100000;
+    *max_rounds = opt->max_rounds > 0 ? opt->max_rounds : 64;
+}
+
+// The first solves' arguments of problem i of a grouped batch.
+template <typename T>
+static ColArgs<T> batch_col_args(const Plan &L, char *ws, Ctl *c, const spmesl_options *opt)
+{
+    int mo, ms, mr;
+    limits_of(opt, &mo, &ms, &mr);
+    const double band = L.prec == SPMESL_MIXED ? kMixedBand : 0.0;
+    ColArgs<T> a = make_col_args<T>(L, ws, c, opt, column_tol(L, opt), band, mo, ms, mr, 0, false);
+    a.mode = 0;
+    a.screened = 1;
+    a.defer_kkt = 1;
+    a.esc_cnt = &c->esc_c;
+    a.esc_list = (int *)(ws + L.esclist2);
+    return a;
+}
+
+template <typename T>
 static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_options *opts,
                                      const std::vector<Plan> &plans, const BatchLayout &B, unsigned char *h)
 {
@@ -1371,13 +1398,12 @@ static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_op
     char *ws0 = ctx->ws;
     Ctl *dctl = (Ctl *)(ws0 + B.ctl_off);
     BatchGrids gr;
-    for (int i = 0; i < count; ++i) gr.rj = std::min(gr.rj, kkt_rows_for<float>(plans[(size_t)i].p, 0, tu));
-    auto *first = (ColArgs<float> *)(h + t.first);
-    auto *resume = (ColArgs<float> *)(h + t.resume);
-    auto *wide = (ColArgs<float> *)(h + t.wide);
-    auto *kkt = (KktJob<float> *)(h + t.kkt);
+    for (int i = 0; i < count; ++i) gr.rj = std::min(gr.rj, kkt_rows_for<T>(plans[(size_t)i].p, 0, tu));
+    auto *first = (ColArgs<T> *)(h + t.first);
+    auto *resume = (ColArgs<T> *)(h + t.resume);
+    auto *wide = (ColArgs<T> *)(h + t.wide);
+    auto *kkt = (KktJob<T> *)(h + t.kkt);
     auto *pol = (PolishArgs *)(h + t.polish);
-    auto *syrk = (SyrkJob *)(h + t.syrk);
     auto *col_off = (int64_t *)(h + t.col_off);
     auto *tile_off = (int64_t *)(h + t.tile_off);
     auto *kkt_off = (int64_t *)(h + t.kkt_off);
@@ -1387,23 +1413,18 @@ static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_op
         const spmesl_options *opt = &opts[i];
         char *ws = ws0 + B.ws_off[(size_t)i];
         Ctl *c = dctl + i;
-        const int max_outer = opt->max_outer > 0 ? opt->max_outer : 1000;
-        const int max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 100000;
-        const int max_rounds = opt->max_rounds > 0 ? opt->max_rounds : 64;
-        const double tol_cols = column_tol(L, opt);
-        const Screen sc = make_screen(L, ws, opt, tu, tol_cols);
+        const Screen sc = make_screen(L, ws, opt, tu, column_tol(L, opt));
         int64_t tiles = 0, blocks = 0;
-        syrk[i] = syrk_job_bf16x3((const uint16_t *)(ws + L.hi), (const uint16_t *)(ws + L.lo), L.n, L.npad, L.p,
-                                  (float *)(ws + L.S), sc, &tiles);
-        ColArgs<float> a = make_col_args<float>(L, ws, c, opt, tol_cols, kMixedBand, max_outer, max_sweeps,
-                                                max_rounds, 0, false);
-        a.mode = 0;
-        a.screened = 1;
-        a.defer_kkt = 1;
-        a.esc_cnt = &c->esc_c;
-        a.esc_list = (int *)(ws + L.esclist2);
+        if (L.prec == SPMESL_MIXED)
+            ((SyrkJob *)(h + t.syrk))[i] =
+                syrk_job_bf16x3((const uint16_t *)(ws + L.hi), (const uint16_t *)(ws + L.lo), L.n, L.npad, L.p,
+                                (float *)(ws + L.S), sc, &tiles);
+        else
+            ((SyrkJobT<T> *)(h + t.syrk))[i] =
+                syrk_job_mfma<T>((const T *)(ws + L.xs), L.n, L.p, (T *)(ws + L.S), sc, &tiles);
+        ColArgs<T> a = batch_col_args<T>(L, ws, c, opt);
         first[i] = a;
-        kkt[i] = kkt_job<float>(make_kkt_args<float>(a, L, ws, c), gr.rj, &blocks);
+        kkt[i] = kkt_job<T>(make_kkt_args<T>(a, L, ws, c), gr.rj, &blocks);
         a.mode = 1;
         a.screened = 0;
         a.work_list = (const int *)(ws + L.dirtylist);
@@ -1412,7 +1433,11 @@ static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_op
         a.work_list = (const int *)(ws + L.esclist2);
         a.work_cnt = &c->esc_c;
         wide[i] = a;
-        pol[i] = make_polish_args(L, ws, c, opt, max_outer, max_sweeps, max_rounds);
+        if (L.prec == SPMESL_MIXED) {
+            int mo, ms, mr;
+            limits_of(opt, &mo, &ms, &mr);
+            pol[i] = make_polish_args(L, ws, c, opt, mo, ms, mr);
+        }
         col_off[i + 1] = col_off[i] + L.p;
         tile_off[i + 1] = tile_off[i] + tiles;
         kkt_off[i + 1] = kkt_off[i] + blocks;
@@ -1424,12 +1449,14 @@ static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_op
     return gr;
 }
 
+template <typename T>
 static int enqueue_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                                  const spmesl_options *opts, const spmesl_result *res, const std::vector<Plan> &plans,
                                  const BatchLayout &B, const BatchGrids &gr)
 {
     hipStream_t s = ctx->stream;
     const Tune tu = resolve_tune(ctx->tune);
+    const bool mixed = plans[0].prec == SPMESL_MIXED;
     char *ws0 = ctx->ws;
     Ctl *dctl = (Ctl *)(ws0 + B.ctl_off);
     const unsigned char *tb = (const unsigned char *)(ws0 + B.tab_off);
@@ -1447,31 +1474,40 @@ static int enqueue_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_proble
     const int late = 3 & ~early;
     int v = early ? fork_batch_fill(ctx, count, res, plans, s, early) : (int)SPMESL_OK;
     if (v != SPMESL_OK) return v;
-    launch_syrk_bf16x3_grouped((const SyrkJob *)(tb + t.syrk), (const int64_t *)(tb + t.tile_off), count, gr.tiles,
-                               s);
-    launch_colsolve_first_grouped<float>((const ColArgs<float> *)(tb + t.first), col_off, count, gr.cols, s);
-    launch_kkt_rows_grouped<float>((const KktJob<float> *)(tb + t.kkt), (const int64_t *)(tb + t.kkt_off), count,
-                                   gr.kkt_blocks, gr.rj, gr.pmax, s);
+    if (mixed)
+        launch_syrk_bf16x3_grouped((const SyrkJob *)(tb + t.syrk), (const int64_t *)(tb + t.tile_off), count,
+                                   gr.tiles, s);
+    else
+        launch_syrk_mfma_grouped<T>((const SyrkJobT<T> *)(tb + t.syrk), (const int64_t *)(tb + t.tile_off), count,
+                                    gr.tiles, s);
+    launch_colsolve_first_grouped<T>((const ColArgs<T> *)(tb + t.first), col_off, count, gr.cols, s);
+    launch_kkt_rows_grouped<T>((const KktJob<T> *)(tb + t.kkt), (const int64_t *)(tb + t.kkt_off), count,
+                               gr.kkt_blocks, gr.rj, gr.pmax, s);
     if (late && (v = fork_batch_fill(ctx, count, res, plans, s, late)) != SPMESL_OK) return v;
     // re-solves of the flagged columns, then every escalated column (the
     // first solves' and the re-solves') in the wide tier
     launch_group_offsets(&dctl->dirty, ctl_words, count, dirty_off, s);
-    launch_colsolve_list_grouped<float>((const ColArgs<float> *)(tb + t.resume), dirty_off, count, 0, s);
+    launch_colsolve_list_grouped<T>((const ColArgs<T> *)(tb + t.resume), dirty_off, count, 0, s);
     launch_group_offsets(&dctl->esc_c, ctl_words, count, esc_off, s);
-    launch_colsolve_list_grouped<float>((const ColArgs<float> *)(tb + t.wide), esc_off, count, 1, s);
-    // the double polish of every column, then its escalations
-    const PolishArgs *ptab = (const PolishArgs *)(tb + t.polish);
-    launch_polish_grouped(ptab, col_off, count, gr.cols, 0, s);
-    launch_group_offsets(&dctl->esc_polish, ctl_words, count, escp_off, s);
-    launch_polish_grouped(ptab, escp_off, count, gr.cols, 1, s);
-    std::vector<PolishArgs> q((size_t)count);
-    for (int i = 0; i < count; ++i) {
-        const spmesl_options *opt = &opts[i];
-        q[(size_t)i] = make_polish_args(plans[(size_t)i], wsi(i), dctl + i, opt,
-                                        opt->max_outer > 0 ? opt->max_outer : 1000,
-                                        opt->max_sweeps > 0 ? opt->max_sweeps : 100000,
-                                        opt->max_rounds > 0 ? opt->max_rounds : 64);
-        enqueue_dense64(q[(size_t)i], plans[(size_t)i], wsi(i), dctl + i, opt, tu, s, nullptr);
+    launch_colsolve_list_grouped<T>((const ColArgs<T> *)(tb + t.wide), esc_off, count, 1, s);
+    if (mixed) {
+        // the double polish of every column, then its escalations, then the
+        // double dense tier of each problem
+        const PolishArgs *ptab = (const PolishArgs *)(tb + t.polish);
+        launch_polish_grouped(ptab, col_off, count, gr.cols, 0, s);
+        launch_group_offsets(&dctl->esc_polish, ctl_words, count, escp_off, s);
+        launch_polish_grouped(ptab, escp_off, count, gr.cols, 1, s);
+        for (int i = 0; i < count; ++i) {
+            int mo, ms, mr;
+            limits_of(&opts[i], &mo, &ms, &mr);
+            const PolishArgs q = make_polish_args(plans[(size_t)i], wsi(i), dctl + i, &opts[i], mo, ms, mr);
+            enqueue_dense64(q, plans[(size_t)i], wsi(i), dctl + i, &opts[i], tu, s, nullptr);
+        }
+    } else {
+        // the dense tier of each problem
+        for (int i = 0; i < count; ++i)
+            enqueue_dense<T>(plans[(size_t)i], wsi(i), dctl + i,
+                             batch_col_args<T>(plans[(size_t)i], wsi(i), dctl + i, &opts[i]), tu, s, nullptr);
     }
     HIPTRY(ctx, hipEventRecord(ctx->fork2, s));
     HIPTRY(ctx, hipStreamWaitEvent(ctx->side, ctx->fork2, 0));
@@ -1488,7 +1524,6 @@ static int enqueue_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_proble
     return SPMESL_OK;
 }
 
-
 static int solve_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_problem *probs,
                                const std::vector<spmesl_options> &opts, spmesl_result *res, int *status,
                                const std::vector<Plan> &plans)
@@ -1501,10 +1536,15 @@ static int solve_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_problem 
     ctx->nmarks = 0;
     // the tables hold workspace addresses: built for this workspace, and
     // uploaded ahead of the solves (outside any graph)
-    const BatchGrids gr = build_batch_tables(ctx, count, opts.data(), plans, B, ctx->stage);
+    const bool dbl = plans[0].prec == SPMESL_FP64;
+    const BatchGrids gr = dbl ? build_batch_tables<double>(ctx, count, opts.data(), plans, B, ctx->stage)
+                              : build_batch_tables<float>(ctx, count, opts.data(), plans, B, ctx->stage);
     HIPTRY(ctx, hipMemcpyAsync(ctx->ws + B.tab_off, ctx->stage, B.t.upload, hipMemcpyHostToDevice, ctx->stream));
     const spmesl_options *opt = &opts[0];
-    auto body = [&] { return enqueue_batch_grouped(ctx, count, probs, opts.data(), res, plans, B, gr); };
+    auto body = [&] {
+        return dbl ? enqueue_batch_grouped<double>(ctx, count, probs, opts.data(), res, plans, B, gr)
+                   : enqueue_batch_grouped<float>(ctx, count, probs, opts.data(), res, plans, B, gr);
+    };
     if (opt->flags & SPMESL_FLAG_EAGER) {
         v = body();
     } else {

@@ -216,6 +216,22 @@ struct SyrkJob {
     float invn, thr;
     int *scnt, *sidx;
 };
+// One problem's covariance tiles (the double and float forms' kernel).
+template <typename T>
+struct SyrkJobT {
+    const T *Xs;
+    int64_t n, p;
+    T *S;
+    int Tt;
+    T invn, thr;
+    int64_t pv;
+    int *scnt, *sidx;
+};
+template <typename T>
+SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen &sc, int64_t *tiles);
+template <typename T>
+void launch_syrk_mfma_grouped(const SyrkJobT<T> *tab, const int64_t *tile_off, int nd, int64_t tiles,
+                              hipStream_t s);
 SyrkJob syrk_job_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad, int64_t p, float *S,
                         const Screen &sc, int64_t *tiles);
 void launch_syrk_bf16x3_grouped(const SyrkJob *tab, const int64_t *tile_off, int nd, int64_t tiles,

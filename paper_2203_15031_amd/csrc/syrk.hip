@@ -191,41 +191,54 @@ __device__ __forceinline__ void screen_flush(L &lst, int *cnt, int *idx)
     }
 }
 
-// Map a linear block id to an upper-triangle tile (bj <= bk), with blocks
-// that share a row panel kept on the same XCD (blocks are dispatched to
-// the 8 XCDs round-robin).
-__device__ __forceinline__ void tile_of_block(int T, int *bj, int *bk)
+// Blocks that share a row panel are kept on the same XCD (blocks are
+// dispatched to the 8 XCDs round-robin): the position of block bid of nb in
+// an order that gives each XCD a contiguous run.
+__device__ __forceinline__ int64_t xcd_order(int64_t nb, int64_t bid)
 {
-    int nb = gridDim.x, bid = blockIdx.x;
-    int x = bid & 7, q = nb >> 3, r = nb & 7;
-    int t = x * q + (x < r ? x : r) + (bid >> 3);
+    const int64_t x = bid & 7, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + (bid >> 3);
+}
+
+// Upper-triangle tile t (bj <= bk, row by row) of a T x T tiling.
+__device__ __forceinline__ void tri_tile(int T, int64_t t, int *bj, int *bk)
+{
     int row = 0;
     while (t >= T - row) {
         t -= T - row;
         ++row;
     }
     *bj = row;
-    *bk = row + t;
+    *bk = row + (int)t;
+}
+
+// Map a linear block id to an upper-triangle tile, XCD-aware.
+__device__ __forceinline__ void tile_of_block(int T, int *bj, int *bk)
+{
+    tri_tile(T, xcd_order(gridDim.x, blockIdx.x), bj, bk);
 }
 
 constexpr int kSyrkKC = 32;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int64_t n, int64_t p,
-                                                   T *__restrict__ S, int Tt, T invn, T thr, int64_t pv,
-                                                   int *__restrict__ scnt, int *__restrict__ sidx)
-{
-    typedef typename Acc<T>::type AccT;
-    __shared__ union {
+struct SyrkMfmaSm {
+    union {
         struct {
             T a[kSyrkKC][64];
             T b[kSyrkKC][64];
         } in;
         T out[64][65];
-    } sm;
-    __shared__ ScreenLds<512> scr;  // a 64 x 64 tile: about 6 per row at the workloads here
-    int bj, bk;
-    tile_of_block(Tt, &bj, &bk);
+    };
+};
+
+// One 64 x 64 tile (bj, bk) of S by the block; scr: the screen's list (a
+// 64 x 64 tile: about 6 per row at the workloads here).
+template <typename T>
+__device__ __forceinline__ void syrk_mfma_tile(const T *__restrict__ Xs, int64_t n, int64_t p, T *__restrict__ S,
+                                               int bj, int bk, T invn, T thr, int64_t pv, int *__restrict__ scnt,
+                                               int *__restrict__ sidx, SyrkMfmaSm<T> &sm, ScreenLds<512> &scr)
+{
+    typedef typename Acc<T>::type AccT;
     const int64_t j0 = (int64_t)bj * 64, k0 = (int64_t)bk * 64;
     if (threadIdx.x == 0) scr.n = 0;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -313,6 +326,67 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
     __syncthreads();
     screen_flush(scr, scnt, sidx);
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int64_t n, int64_t p,
+                                                   T *__restrict__ S, int Tt, T invn, T thr, int64_t pv,
+                                                   int *__restrict__ scnt, int *__restrict__ sidx)
+{
+    __shared__ SyrkMfmaSm<T> sm;
+    __shared__ ScreenLds<512> scr;
+    int bj, bk;
+    tile_of_block(Tt, &bj, &bk);
+    syrk_mfma_tile<T>(Xs, n, p, S, bj, bk, invn, thr, pv, scnt, sidx, sm, scr);
+}
+
+// The tiles of many problems in one launch, one tile per block: block b
+// (in the XCD-aware order) is tile b - off[d] of problem d.
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk_mfma_grouped(const SyrkJobT<T> *__restrict__ tab,
+                                                           const int64_t *__restrict__ off, int nd)
+{
+    __shared__ SyrkMfmaSm<T> sm;
+    __shared__ ScreenLds<512> scr;
+    const int64_t t = xcd_order(gridDim.x, blockIdx.x);
+    const int d = group_of(off, nd, t);
+    const SyrkJobT<T> &J = tab[d];
+    int bj, bk;
+    tri_tile(J.Tt, t - off[d], &bj, &bk);
+    syrk_mfma_tile<T>(J.Xs, J.n, J.p, J.S, bj, bk, J.invn, J.thr, J.pv, J.scnt, J.sidx, sm, scr);
+}
+
+template <typename T>
+SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen &sc, int64_t *tiles)
+{
+    SyrkJobT<T> j{};
+    j.Xs = Xs;
+    j.n = n;
+    j.p = p;
+    j.S = S;
+    j.Tt = (int)((p + 63) / 64);
+    j.invn = (T)(1.0 / (double)n);
+    if constexpr (sizeof(T) == 8)
+        j.thr = (T)sc.thr64;
+    else
+        j.thr = (T)sc.thr32;
+    j.pv = sc.pv > 0 ? sc.pv : p;
+    j.scnt = sc.cnt;
+    j.sidx = sc.idx;
+    *tiles = (int64_t)j.Tt * (j.Tt + 1) / 2;
+    return j;
+}
+
+template <typename T>
+void launch_syrk_mfma_grouped(const SyrkJobT<T> *tab, const int64_t *tile_off, int nd, int64_t tiles, hipStream_t s)
+{
+    if (tiles <= 0) return;
+    hipLaunchKernelGGL(k_syrk_mfma_grouped<T>, dim3((unsigned)tiles), dim3(256), 0, s, tab, tile_off, nd);
+}
+
+template SyrkJobT<double> syrk_job_mfma<double>(const double *, int64_t, int64_t, double *, const Screen &, int64_t *);
+template SyrkJobT<float> syrk_job_mfma<float>(const float *, int64_t, int64_t, float *, const Screen &, int64_t *);
+template void launch_syrk_mfma_grouped<double>(const SyrkJobT<double> *, const int64_t *, int, int64_t, hipStream_t);
+template void launch_syrk_mfma_grouped<float>(const SyrkJobT<float> *, const int64_t *, int, int64_t, hipStream_t);
 
 template <typename T>
 static void launch_syrk_t(const T *Xs, int64_t n, int64_t p, T *S, T thr, const Screen &sc, hipStream_t s)

@@ -366,7 +366,7 @@ class Context:
         return prob, res, out, stats
 
     def solve_batch(self, Xs, lambda0s, tol=1e-8, precision="fp64", output_scale="original",
-                    check=True, outs=None, eager=False):
+                    check=True, outs=None, eager=False, data_form=False):
         """Solve several datasets (uneven n, p) in one library call; lambda0s
         is one value or one per dataset.  `outs` may hold one dict of
         preallocated B / sigma / Omega tensors per dataset (a repeated call
@@ -374,7 +374,8 @@ class Context:
         m = len(Xs)
         if not isinstance(lambda0s, (list, tuple)):
             lambda0s = [lambda0s] * m
-        opt = self.options(lambda0s[0] if m else 1.0, tol, precision, output_scale, eager=eager)
+        opt = self.options(lambda0s[0] if m else 1.0, tol, precision, output_scale, eager=eager,
+                           data_form=data_form)
         probs = (Problem * m)(*[self.problem(X) for X in Xs])
         lams = (C.c_double * m)(*[float(v) for v in lambda0s])
         stats = [Stats() for _ in range(m)]

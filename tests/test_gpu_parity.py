@@ -317,7 +317,10 @@ def test_solve_batch_matches_single_solves(ctx):
     Xs = Wk.generate_batch(count=6, seed=3, pmin=64, pmax=300)
     lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs]
     Xg = [gpu(X) for X in Xs]
-    for prec in ("fp64", "mixed"):
+    # every covariance form runs grouped (one launch per step over all six
+    # data sets); each data set's result is that of its single solve, bit for
+    # bit
+    for prec in ("fp64", "mixed", "fp32"):
         res = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec)
         outs = [dict(B=r.B, sigma=r.sigma, Omega=r.Omega) for r in res]
         for X, Xd, lam, r in zip(Xs, Xg, lams, res):
@@ -350,9 +353,24 @@ def test_solve_batch_matches_single_solves(ctx):
         assert rel_err(host(r.Omega), ref["Omega"]) <= 1e-4
 
 
+def test_solve_batch_one_after_another(ctx):
+    """Batches that do not run grouped (the data form) still run one data set
+    after another, each result equal to the single solve's."""
+    from paper_2203_15031_amd import workloads as Wk
+    Xs = Wk.generate_batch(count=3, seed=5, pmin=64, pmax=200)
+    lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs]
+    Xg = [gpu(X) for X in Xs]
+    res = ctx.solve_batch(Xg, lams, tol=1e-8, precision="fp64", data_form=True)
+    for Xd, lam, r in zip(Xg, lams, res):
+        assert r.status == 0
+        one = ctx.solve(Xd, lam, tol=1e-8, precision="fp64", eager=True, data_form=True)
+        assert torch.equal(r.Omega, one.Omega) and torch.equal(r.B, one.B)
+
+
 # ---------------------------------------------------------------------------
 # graph replay and the asynchronous entry point
 # ---------------------------------------------------------------------------
+
 
 def test_graph_replays_match_eager(ctx):
     """A repeated call replays the context's captured graph; every replay,
