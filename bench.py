@@ -294,6 +294,41 @@ def errors_vs_oracle(X_np, lam0, results, m=32):
     return out
 
 
+def batched_replicas(args, torch, spmesl, workloads, forms, tol):
+    """The batched form on the headline shape: `--replicas` independent data
+    sets of the workload's structure and size in one grouped call per step
+    (every step of the path one launch over all of them); time per call and
+    per solve, with the whole-solve roofline per solve."""
+    k = args.replicas
+    w = workloads.workload(args.workload)
+    Xs = [torch.from_numpy(X).to("cuda:0") for X in workloads.generate_replicas(args.workload, k)]
+    ctx = spmesl.Context(0)
+    outs = [dict(B=torch.empty((w.p, w.p), dtype=torch.float64, device="cuda:0"),
+                 sigma=torch.empty((w.p,), dtype=torch.float64, device="cuda:0"),
+                 Omega=torch.empty((w.p, w.p), dtype=torch.float64, device="cuda:0")) for _ in Xs]
+    out = {"count": k, "data": f"{k} independent draws of the workload (its own X and {k - 1} more seeds)"}
+    steps = max(2, args.steps // 2)
+    for prec in forms:
+        for _ in range(max(1, args.warmup)):
+            r = ctx.solve_batch(Xs, w.lambda0, tol, prec, outs=outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = ctx.solve_batch(Xs, w.lambda0, tol, prec, outs=outs)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / steps
+        ent = {"ms_per_call": round(ms, 4), "ms_per_solve": round(ms / k, 4),
+               "solves_per_s": round(1000.0 * k / ms, 2)}
+        if not FORMS[prec][1]:
+            ent["whole_solve"] = whole_solve_roofline(w.n, w.p, prec, r[0].stats, ms / k)
+        out[prec] = ent
+        print(f"[bench] batched {prec}: {k} data sets in {ms:.3f} ms, {ms / k:.4f} ms per solve",
+              file=sys.stderr, flush=True)
+    del outs, Xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(args, torch, spmesl, workloads):
     """The batched hub workload: 64 data sets of uneven shape, one library call per step."""
     Xs_np = workloads.generate_batch()
@@ -451,6 +486,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch shapes instead of the autotuner's")
+    ap.add_argument("--replicas", type=int, default=8,
+                    help="data sets of the headline shape in the batched figure (0 or 1: none)")
     ap.add_argument("--forms", default="mixed,fp64",
                     help="comma list of mixed, fp64, fp32, data (the double data form, no S)")
     ap.add_argument("--table2", action="store_true",
@@ -551,7 +588,8 @@ def main():
         "stats": {k: r.stats[k] for k in ("total_outer", "max_outer", "total_sweeps",
                                           "total_updates", "total_rounds", "max_working_set",
                                           "columns_noconv", "polish_kkt_checks", "polish_added",
-                                          "sum_working_set")},
+                                          "sum_working_set", "resolved_columns",
+                                          "escalated_columns")},
     }
     for prec in forms[1:]:
         ms2, ms2_sync, ph2, kern2, r2 = res[prec]
@@ -562,6 +600,8 @@ def main():
         line[prec]["whole_solve"] = (whole_solve_roofline(w.n, w.p, prec, r2.stats, ms2)
                                      if not FORMS[prec][1] else None)
         line["speedup_vs_" + prec] = round(ms2 / ms, 3)
+    if args.replicas > 1 and args.workload == WORKLOAD:
+        line["batched"] = batched_replicas(args, torch, spmesl, workloads, forms, tol)
     if not args.no_cpu:
         line["errors_vs_oracle"] = errors_vs_oracle(X_np, lam0, outs)
         line["cpu_baseline"] = cpu_baseline(X_np, lam0, tol)

@@ -166,6 +166,9 @@ typedef struct {
     int64_t polish_added;     /* variables the polish added (mixed form) */
     int64_t sum_working_set;  /* sum over columns of the final working-set
                                  sizes (in the mixed form, the polish's) */
+    int64_t resolved_columns; /* columns the row-tiled KKT pass sent back for
+                                 a re-solve */
+    int64_t escalated_columns;/* columns handed to the 128-coordinate tier */
     /* phase times in milliseconds (only with SPMESL_FLAG_TIMING) */
     double ms_standardize, ms_covariance, ms_solve, ms_polish, ms_output, ms_total;
 } spmesl_stats;

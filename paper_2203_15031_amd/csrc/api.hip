@@ -1233,6 +1233,8 @@ static int decode(const Ctl &c, int64_t p, spmesl_stats *st)
         st->polish_kkt_checks = (int64_t)c.counters[kCntPolishChecks];
         st->polish_added = (int64_t)c.counters[kCntPolishAdded];
         st->sum_working_set = (int64_t)c.counters[kCntSumW];
+        st->resolved_columns = (int64_t)c.dirty;
+        st->escalated_columns = (int64_t)c.counters[kCntEscalated];
     }
     if (c.flags & 1) return SPMESL_ENONFINITE;
     if (c.flags & 2) return SPMESL_EZEROVAR;

@@ -63,7 +63,7 @@ class Stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in (
         "columns", "total_outer", "max_outer", "total_sweeps", "total_updates", "total_rounds",
         "max_working_set", "nnz_B", "columns_noconv", "polish_kkt_checks", "polish_added",
-        "sum_working_set")] + \
+        "sum_working_set", "resolved_columns", "escalated_columns")] + \
         [(f, C.c_double) for f in (
             "ms_standardize", "ms_covariance", "ms_solve", "ms_polish", "ms_output", "ms_total")]
 

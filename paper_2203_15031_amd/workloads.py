@@ -470,6 +470,21 @@ def generate(name: str, n: int | None = None, p: int | None = None) -> np.ndarra
     raise ValueError(f"{name} is a batch workload; use generate_batch")
 
 
+def generate_replicas(name: str, count: int) -> list[np.ndarray]:
+    """`count` independent data sets of a named single-set workload: the
+    workload's own X first, then draws of the same structure and size from
+    seeds spawned from the workload's seed."""
+    w = WORKLOADS[name]
+    out = [generate(name)]
+    for ss in np.random.SeedSequence(w.seed).spawn(count - 1):
+        rng = np.random.default_rng(ss)
+        if name == "blockar_n400_p5000":
+            out.append(sample_from_cov(w.n, block_ar_cov(w.p // 100, 100, 0.6), rng, centre=False))
+        else:
+            raise ValueError(f"no replicas defined for {name}")
+    return out
+
+
 def batch_shapes(count: int = 64, seed: int = 3, pmin: int = 256, pmax: int = 4096):
     """(n_i, p_i) of the batched hub workload: p ~ U{pmin..pmax}, n = ceil(p/2)."""
     rng = _rng(seed)

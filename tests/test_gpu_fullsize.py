@@ -106,6 +106,22 @@ def test_blockar_p5000_data_form(ctx, blockar_full):
     omega_invariants(Om, B)
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_blockar_p5000_grouped_batch_equals_single_solves(ctx, blockar_full, prec):
+    # the batched form at the full shape: three draws of the workload in one
+    # grouped call give each draw's single-solve result bit for bit, so the
+    # oracle comparison above covers the batched figure of the benchmark
+    w = blockar_full[0]
+    Xs = [gpu(X) for X in W.generate_replicas(w.name, 3)]
+    res = ctx.solve_batch(Xs, w.lambda0, tol=w.tol, precision=prec)
+    for Xg, r in zip(Xs, res):
+        assert r.status == 0
+        one = ctx.solve(Xg, w.lambda0, tol=w.tol, precision=prec)
+        assert torch.equal(r.B, one.B) and torch.equal(r.Omega, one.Omega) and torch.equal(r.sigma, one.sigma)
+    del res
+    torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------------------
 # scale-free tree, p = 20000: sampled columns with their neighbours
 # ---------------------------------------------------------------------------
