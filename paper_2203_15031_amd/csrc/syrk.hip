@@ -339,6 +339,180 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const T *__restrict__ Xs, int
     syrk_mfma_tile<T>(Xs, n, p, S, bj, bk, invn, thr, pv, scnt, sidx, sm, scr);
 }
 
+// ---------------------------------------------------------------------------
+// double form: 128 x 128 tiles.  Four waves of 64 x 64 (sixteen 16 x 16
+// accumulator blocks each): per 4-sample step a wave reads 8 operands from
+// LDS for 16 matrix-core operations, twice the 64 x 64 tile's ratio, and the
+// panels of a stage (16 samples) give 16 flops per byte read from L2.  Each
+// entry takes its products in the same sample order as the 64 x 64 kernel,
+// so S is the same to the bit.  The epilogue stages the tile through LDS in
+// two halves of 64 rows (two blocks per CU fit), each written directly and
+// transposed; a diagonal tile writes its lower-left block as the mirror of
+// its upper-right one in the first half and takes its upper triangle for
+// both halves of each diagonal block, so S is symmetric bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kD = 128;   // tile edge
+constexpr int kDKC = 16;  // samples per stage
+constexpr int kDPad = 16; // LDS row padding of the stage panels (doubles)
+
+struct SyrkD128Sm {
+    union {
+        struct {
+            double a[kDKC][kD + kDPad];
+            double b[kDKC][kD + kDPad];
+        } in;
+        double out[64][kD + 1];  // one half of the tile
+    };
+};
+
+__device__ __forceinline__ void syrk_d128_tile(const double *__restrict__ Xs, int64_t n, int64_t p,
+                                               double *__restrict__ S, int bj, int bk, double invn, double thr,
+                                               int64_t pv, int *__restrict__ scnt, int *__restrict__ sidx,
+                                               SyrkD128Sm &sm, ScreenLds<1024> &scr)
+{
+    const int64_t j0 = (int64_t)bj * kD, k0 = (int64_t)bk * kD;
+    if (threadIdx.x == 0) scr.n = 0;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+
+    // loader: 32 threads per sample row, 4 consecutive variables each; rows
+    // lr and lr + 8 of the stage
+    const int lr = tid >> 5, lc = (tid & 31) * 4;
+    constexpr int NL = kDKC / 8;
+    const bool even = (p & 1) == 0;  // 16-byte aligned pairs (j0, lc even)
+    double ra[NL][4], rb[NL][4];
+    auto fetch1 = [&](int64_t i, int64_t c0, double *r) {
+        if (i < n && c0 + 3 < p && even) {
+            const double2 x0 = *reinterpret_cast<const double2 *>(Xs + i * p + c0);
+            const double2 x1 = *reinterpret_cast<const double2 *>(Xs + i * p + c0 + 2);
+            r[0] = x0.x;
+            r[1] = x0.y;
+            r[2] = x1.x;
+            r[3] = x1.y;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) r[e] = (i < n && c0 + e < p) ? Xs[i * p + c0 + e] : 0.0;
+        }
+    };
+    auto fetch = [&](int64_t i0) {
+#pragma unroll
+        for (int h = 0; h < NL; ++h) {
+            const int64_t i = i0 + lr + 8 * h;
+            fetch1(i, j0 + lc, ra[h]);
+            fetch1(i, k0 + lc, rb[h]);
+        }
+    };
+    fetch(0);
+    for (int64_t i0 = 0; i0 < n; i0 += kDKC) {
+#pragma unroll
+        for (int h = 0; h < NL; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sm.in.a[lr + 8 * h][lc + e] = ra[h][e];
+                sm.in.b[lr + 8 * h][lc + e] = rb[h][e];
+            }
+        __syncthreads();
+        if (i0 + kDKC < n) fetch(i0 + kDKC);  // in flight during the MFMAs below
+#pragma unroll
+        for (int kk = 0; kk < kDKC; kk += 4) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = sm.in.a[kk + (lane >> 4)][64 * wm + 16 * a + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = sm.in.b[kk + (lane >> 4)][64 * wn + 16 * b + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+
+    const bool diag = bj == bk;
+    for (int h = 0; h < 2; ++h) {
+        // rows 64h .. 64h + 63 of the tile (scaled by 1/n), from the waves
+        // that hold them
+        if (wm == h) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        sm.out[16 * a + acc_row<double>(lane, r)][64 * wn + 16 * b + (lane & 15)] =
+                            acc[a][b][r] * invn;
+        }
+        __syncthreads();
+        // direct rows j = j0 + 64h + rr; a diagonal tile's second half leaves
+        // columns 0..63 to the first half's mirror
+        const int c0 = (diag && h == 1) ? 64 : 0;
+        for (int e = tid; e < 64 * kD; e += 256) {
+            const int rr = e >> 7, cc = e & (kD - 1);
+            const int R = 64 * h + rr;
+            const int64_t j = j0 + R, k = k0 + cc;
+            if (cc >= c0 && j < p && k < p) {
+                double v;
+                if (j == k)
+                    v = 1.0;
+                else if (diag && R > cc)
+                    v = sm.out[cc - 64 * h][R];  // the upper-triangle value
+                else
+                    v = sm.out[rr][cc];
+                S[j * p + k] = v;
+                screen_entry(scr, scnt, sidx, thr, pv, j, k, v);
+            }
+        }
+        // mirrored: S[k][j] for the half's 64 columns j; a diagonal tile
+        // mirrors only its upper-right block (first half)
+        if (!diag || h == 0) {
+            const int kc0 = diag ? 64 : 0;
+            for (int e = tid; e < kD * 64; e += 256) {
+                const int kc = e >> 6, jc = e & 63;
+                const int64_t k = k0 + kc, j = j0 + 64 * h + jc;
+                if (kc >= kc0 && j < p && k < p) {
+                    const double v = sm.out[jc][kc];
+                    S[k * p + j] = v;
+                    screen_entry(scr, scnt, sidx, thr, pv, k, j, v);
+                }
+            }
+        }
+        __syncthreads();  // the half is read before the next one is staged
+    }
+    screen_flush(scr, scnt, sidx);
+}
+
+__global__ __launch_bounds__(256, 2) void k_syrk_d128(const double *__restrict__ Xs, int64_t n, int64_t p,
+                                                      double *__restrict__ S, int Tt, double invn, double thr,
+                                                      int64_t pv, int *__restrict__ scnt, int *__restrict__ sidx)
+{
+    __shared__ SyrkD128Sm sm;
+    __shared__ ScreenLds<1024> scr;
+    int bj, bk;
+    tile_of_block(Tt, &bj, &bk);
+    syrk_d128_tile(Xs, n, p, S, bj, bk, invn, thr, pv, scnt, sidx, sm, scr);
+}
+
+__global__ __launch_bounds__(256, 2) void k_syrk_d128_grouped(const SyrkJobT<double> *__restrict__ tab,
+                                                              const int64_t *__restrict__ off, int nd)
+{
+    __shared__ SyrkD128Sm sm;
+    __shared__ ScreenLds<1024> scr;
+    const int64_t t = xcd_order(gridDim.x, blockIdx.x);
+    const int d = group_of(off, nd, t);
+    const SyrkJobT<double> &J = tab[d];
+    int bj, bk;
+    tri_tile(J.Tt, t - off[d], &bj, &bk);
+    syrk_d128_tile(J.Xs, J.n, J.p, J.S, bj, bk, J.invn, J.thr, J.pv, J.scnt, J.sidx, sm, scr);
+}
+
+// the tile edge of each form's kernel
+template <typename T> constexpr int syrk_edge() { return sizeof(T) == 8 ? kD : 64; }
+
 // The tiles of many problems in one launch, one tile per block: block b
 // (in the XCD-aware order) is tile b - off[d] of problem d.
 template <typename T>
@@ -363,7 +537,7 @@ SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen 
     j.n = n;
     j.p = p;
     j.S = S;
-    j.Tt = (int)((p + 63) / 64);
+    j.Tt = (int)((p + syrk_edge<T>() - 1) / syrk_edge<T>());
     j.invn = (T)(1.0 / (double)n);
     if constexpr (sizeof(T) == 8)
         j.thr = (T)sc.thr64;
@@ -380,7 +554,10 @@ template <typename T>
 void launch_syrk_mfma_grouped(const SyrkJobT<T> *tab, const int64_t *tile_off, int nd, int64_t tiles, hipStream_t s)
 {
     if (tiles <= 0) return;
-    hipLaunchKernelGGL(k_syrk_mfma_grouped<T>, dim3((unsigned)tiles), dim3(256), 0, s, tab, tile_off, nd);
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(k_syrk_d128_grouped, dim3((unsigned)tiles), dim3(256), 0, s, tab, tile_off, nd);
+    else
+        hipLaunchKernelGGL(k_syrk_mfma_grouped<T>, dim3((unsigned)tiles), dim3(256), 0, s, tab, tile_off, nd);
 }
 
 template SyrkJobT<double> syrk_job_mfma<double>(const double *, int64_t, int64_t, double *, const Screen &, int64_t *);
@@ -391,10 +568,14 @@ template void launch_syrk_mfma_grouped<float>(const SyrkJobT<float> *, const int
 template <typename T>
 static void launch_syrk_t(const T *Xs, int64_t n, int64_t p, T *S, T thr, const Screen &sc, hipStream_t s)
 {
-    int Tt = (int)((p + 63) / 64);
-    int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
-    hipLaunchKernelGGL(k_syrk_mfma<T>, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
-                       (T)(1.0 / (double)n), thr, sc.pv > 0 ? sc.pv : p, sc.cnt, sc.idx);
+    const int Tt = (int)((p + syrk_edge<T>() - 1) / syrk_edge<T>());
+    const int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(k_syrk_d128, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
+                           1.0 / (double)n, (double)thr, sc.pv > 0 ? sc.pv : p, sc.cnt, sc.idx);
+    else
+        hipLaunchKernelGGL(k_syrk_mfma<T>, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
+                           (T)(1.0 / (double)n), thr, sc.pv > 0 ? sc.pv : p, sc.cnt, sc.idx);
 }
 
 void launch_syrk_f64(const double *Xs, int64_t n, int64_t p, double *S, const Screen &sc, hipStream_t s)
