@@ -61,7 +61,11 @@ def kernel_costs(n, p, prec, mean_w=None):
     if prec == "mixed":
         costs["standardize"] = (16.0 * n * p + 4.0 * npad * p, 0.0, None)
         if mean_w is not None:
+            # the polish runs on its own, or together with the re-solves of
+            # the flagged columns (one launch; the re-solves add their
+            # in-wave KKT passes, left out here)
             costs["polish"] = (8.0 * n * (mean_w + 1.0) * p, 0.0, None)
+            costs["resume_polish"] = costs["polish"]
     return costs
 
 
