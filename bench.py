@@ -78,6 +78,7 @@ TRAFFIC_ROWS = {
     ("kkt_rows", "fp64"): ("kkt_rows (double)", ["kkt.hip"]),
     ("kkt_rows", "mixed"): ("kkt_rows (float)", ["kkt.hip"]),
     ("standardize", "mixed"): ("standardize (mixed)", ["standardize.hip"]),
+    ("resume_polish", None): ("resume_polish", ["polish.hip", "colsolve_column.hpp"]),
     ("fill_B", None): ("fill_B / fill_Omega", ["output.hip"]),
     ("fill_Omega", None): ("fill_B / fill_Omega", ["output.hip"]),
 }
