@@ -230,7 +230,16 @@ int main()
         spmesl_result ra = a.res(&st);
         spmesl_tuning best{};
         double msb = 0.0;
-        CHECK("autotune after the batches", spmesl_autotune(ctx, &pa, &o, &ra, 3, &best, &msb), SPMESL_OK);
+        // a context that has run grouped batches is refused; tune on a
+        // second context and carry the shapes over
+        CHECK("autotune refused after grouped batches", spmesl_autotune(ctx, &pa, &o, &ra, 3, &best, &msb),
+              SPMESL_EINVAL);
+        {
+            spmesl_ctx *tctx = nullptr;
+            CHECK("create tuning context", spmesl_create(&tctx, 0, nullptr), SPMESL_OK);
+            CHECK("autotune on a fresh context", spmesl_autotune(tctx, &pa, &o, &ra, 3, &best, &msb), SPMESL_OK);
+            spmesl_destroy(tctx);
+        }
         for (int split : {0, 1, 2}) {
             spmesl_tuning t = best;
             t.fill_split = split;
@@ -280,7 +289,8 @@ int main()
     CHECK("solve tuned", spmesl_solve(ctx, &pa, &o, &ra), SPMESL_OK);
     spmesl_tuning best{};
     double msb = 0.0;
-    CHECK("autotune", spmesl_autotune(ctx, &pa, &o, &ra, 2, &best, &msb), SPMESL_OK);
+    CHECK("autotune refused (grouped batches ran)", spmesl_autotune(ctx, &pa, &o, &ra, 2, &best, &msb),
+          SPMESL_EINVAL);
     hipFree(status_dev);
     spmesl_destroy(ctx);
     if (mock_violations) {

@@ -312,7 +312,17 @@ def test_strided_input_and_skipped_outputs(ctx):
 # batched data sets (the full-size workloads are in test_gpu_fullsize.py)
 # ---------------------------------------------------------------------------
 
-def test_solve_batch_matches_single_solves(ctx):
+def test_solve_batch_matches_single_solves(sp):
+    # a context of its own: the autotuner refuses a context that has run a
+    # grouped batch (test_autotune_refused_after_a_grouped_batch)
+    ctx = sp.Context(0)
+    try:
+        _batch_matches_single_solves(ctx)
+    finally:
+        ctx.close()
+
+
+def _batch_matches_single_solves(ctx):
     from paper_2203_15031_amd import workloads as Wk
     Xs = Wk.generate_batch(count=6, seed=3, pmin=64, pmax=300)
     lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs]
@@ -351,6 +361,24 @@ def test_solve_batch_matches_single_solves(ctx):
         ref = oracle.spmesl(Xs[i], lams[i], tol=1e-12)
         r = ctx.solve(Xg[i], lams[i], tol=1e-8, precision="mixed")
         assert rel_err(host(r.Omega), ref["Omega"]) <= 1e-4
+
+
+def test_autotune_refused_after_a_grouped_batch(sp):
+    # an autotune on a context that had run grouped batches ended in a host
+    # crash of unknown cause; the library refuses that sequence up front
+    from paper_2203_15031_amd import workloads as Wk
+    Xs = Wk.generate_batch(count=2, seed=3, pmin=64, pmax=120)
+    lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs]
+    Xg = [gpu(X) for X in Xs]
+    ctx = sp.Context(0)
+    try:
+        res = ctx.solve_batch(Xg, lams, tol=1e-8, precision="mixed")
+        assert all(r.status == 0 for r in res)
+        with pytest.raises(sp.SpmeslError) as e:
+            ctx.autotune(Xg[0], lams[0], 1e-8, "mixed", reps=1)
+        assert e.value.code == sp.EINVAL
+    finally:
+        ctx.close()
 
 
 def test_solve_batch_one_after_another(ctx):
