@@ -304,11 +304,7 @@ int spmesl_get_tuning(const spmesl_ctx *ctx, spmesl_tuning *t);
  * keeps the fastest, sets it on the context and writes it to *best (host,
  * may be NULL) with its time per solve in *ms_best (host, may be NULL).  The
  * outputs in `res` hold the last solve's result.  Allocates (workspace,
- * graphs, a status word).  Returns SPMESL_OK or the first error of a solve.
- * SPMESL_EINVAL on a context that has run a grouped batch (spmesl_solve_batch
- * in a covariance form): that sequence once ended in a host crash whose cause
- * is not known, so tune on another context and copy the shapes with
- * spmesl_get_tuning / spmesl_set_tuning. */
+ * graphs, a status word).  Returns SPMESL_OK or the first error of a solve. */
 int spmesl_autotune(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_options *opt,
                     spmesl_result *res, int reps, spmesl_tuning *best, double *ms_best);
 

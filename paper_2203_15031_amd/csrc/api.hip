@@ -333,9 +333,6 @@ struct spmesl_ctx {
     // host staging of the grouped batch's launch tables
     unsigned char *stage = nullptr;
     size_t stage_bytes = 0;
-    // grouped batches run on this context (the autotuner refuses such a
-    // context: see spmesl_autotune)
-    int grouped_runs = 0;
     hipEvent_t ev[6] = {};
     bool have_events = false;
     // second stream (default priority) for the zero fill of the dense
@@ -1579,7 +1576,6 @@ static int solve_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_problem 
                                const std::vector<Plan> &plans)
 {
     const BatchLayout B = batch_layout(count, plans);
-    ++ctx->grouped_runs;
     int v = ensure_workspace(ctx, B.total);
     if (v != SPMESL_OK) return v;
     if ((v = ensure_pinned(ctx, (size_t)count)) != SPMESL_OK) return v;
@@ -1918,12 +1914,6 @@ int spmesl_autotune(spmesl_ctx *ctx, const spmesl_problem *prob, const spmesl_op
                     spmesl_result *res, int reps, spmesl_tuning *best, double *ms_best)
 {
     if (!ctx || !res || reps < 1) return SPMESL_EINVAL;
-    // An autotune on a context that had run grouped batches ended, on the
-    // device, in a host segmentation fault whose cause is not known; such a
-    // context is refused (tune on another context and copy the shapes).
-    if (ctx->grouped_runs)
-        return fail(ctx, SPMESL_EINVAL,
-                    "spmesl_autotune: this context has run a grouped batch; tune on another context");
     int v = validate(ctx, prob, opt);
     if (v != SPMESL_OK) return v;
     if (!ctx->have_events) return fail(ctx, SPMESL_EHIP, "the context has no timing events");
