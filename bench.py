@@ -61,11 +61,7 @@ def kernel_costs(n, p, prec, mean_w=None):
     if prec == "mixed":
         costs["standardize"] = (16.0 * n * p + 4.0 * npad * p, 0.0, None)
         if mean_w is not None:
-            # the polish runs on its own, or together with the re-solves of
-            # the flagged columns (one launch; the re-solves add their
-            # in-wave KKT passes, left out here)
             costs["polish"] = (8.0 * n * (mean_w + 1.0) * p, 0.0, None)
-            costs["resume_polish"] = costs["polish"]
     return costs
 
 
@@ -78,7 +74,7 @@ TRAFFIC_ROWS = {
     ("kkt_rows", "fp64"): ("kkt_rows (double)", ["kkt.hip"]),
     ("kkt_rows", "mixed"): ("kkt_rows (float)", ["kkt.hip"]),
     ("standardize", "mixed"): ("standardize (mixed)", ["standardize.hip"]),
-    ("resume_polish", None): ("resume_polish", ["polish.hip", "colsolve_column.hpp"]),
+    ("polish", None): ("polish", ["polish.hip"]),
     ("fill_B", None): ("fill_B / fill_Omega", ["output.hip"]),
     ("fill_Omega", None): ("fill_B / fill_Omega", ["output.hip"]),
 }

@@ -88,7 +88,7 @@ struct Plan {
     int prec = 0, rchunks = 1;
     size_t mean, scale, partial, xs, xt, hi, lo, S;
     size_t wcnt, widx, wbeta, sigma, lam, cstat, esclist, bandcnt, bandidx;
-    size_t suppcnt, suppidx, suppval, pendcnt, pendidx, dirtylist, esclist2, colinfo, polinfo, pmark;
+    size_t suppcnt, suppidx, suppval, pendcnt, pendidx, dirtylist, esclist2, colinfo, polinfo;
     size_t wcnt64, widx64, wbeta64, sigma64, lam64, cstat64, esclist64;
     // the dense tier: queues, result offsets into the pools, workspace
     size_t dq, dq64, woff, woff64, dmark, dv, dvold, dr, dbd, dbp, dsk, dsvv, de;
@@ -241,7 +241,6 @@ Plan make_plan_g(int64_t n, int64_t p, int prec, int G)
     L.esclist2 = b.take(4 * P);
     L.colinfo = b.take(16 * P);
     L.polinfo = prec == SPMESL_MIXED ? b.take(32 * P) : 0;
-    L.pmark = prec == SPMESL_MIXED ? b.take(4 * P) : 0;
     L.bandcnt = L.bandidx = 0;
     L.wcnt64 = L.widx64 = L.wbeta64 = L.sigma64 = L.lam64 = L.cstat64 = L.esclist64 = 0;
     if (prec == SPMESL_MIXED) {
@@ -669,7 +668,6 @@ static ColArgs<T> make_col_args(const Plan &L, char *ws, Ctl *dctl, const spmesl
     a.warm = warm ? 1 : 0;
     a.dense_cnt = &dctl->dense;
     a.dense_list = (int *)(ws + L.dq);
-    a.mark = L.prec == SPMESL_MIXED ? (int *)(ws + L.pmark) : nullptr;
     return a;
 }
 
@@ -696,18 +694,13 @@ static KktArgs<T> make_kkt_args(const ColArgs<T> &a, const Plan &L, char *ws, Ct
     k.band_cnt = a.band_cnt;
     k.band_idx = a.band_idx;
     k.flags = &dctl->flags;
-    k.mark = a.mark;
     return k;
 }
 
-// pol (mixed form): the re-solves run together with the double polish (one
-// launch), and the columns the wide tier finished are polished after it; the
-// polish's own escalations are left to the caller.
 template <typename T, typename F>
 static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_options *opt, const Tune &tu,
                            double tol, double band, int max_outer, int max_sweeps, int max_rounds,
-                           hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0, bool warm = false,
-                           const PolishArgs *pol = nullptr)
+                           hipStream_t s, Marker *mk, F &&after_kkt, int64_t k0 = 0, bool warm = false)
 {
     const int rj = kkt_rows_for<T>(L.p, k0, tu);
     ColArgs<T> a = make_col_args<T>(L, ws, dctl, opt, tol, band, max_outer, max_sweeps, max_rounds, k0, warm);
@@ -745,26 +738,12 @@ static int enqueue_columns(const Plan &L, char *ws, Ctl *dctl, const spmesl_opti
     a.work_cnt = &dctl->dirty;
     a.esc_cnt = &dctl->esc_c;
     a.esc_list = (int *)(ws + L.esclist2);
-    if constexpr (sizeof(T) == 4) {
-        if (pol) {
-            launch_resume_polish(a, *pol, s);
-            mark(mk, s, "resume_polish");
-        } else {
-            launch_colsolve(a, 0, s);
-            mark(mk, s, "colsolve_resume");
-        }
-    } else {
-        launch_colsolve(a, 0, s);
-        mark(mk, s, "colsolve_resume");
-    }
+    launch_colsolve(a, 0, s);
+    mark(mk, s, "colsolve_resume");
     a.work_list = (const int *)(ws + L.esclist2);
     a.work_cnt = &dctl->esc_c;
     launch_colsolve(a, 1, s);
     mark(mk, s, "colsolve_resume_wide");
-    if (pol) {
-        launch_polish_list(*pol, s);
-        mark(mk, s, "polish_late");
-    }
     // the dense tier; in the mixed form (band > 0) its columns go to the
     // double polish's dense tier instead
     if (band == 0.0) enqueue_dense<T>(L, ws, dctl, a, tu, s, mk);
@@ -867,8 +846,6 @@ static PolishArgs make_polish_args(const Plan &L, char *ws, Ctl *dctl, const spm
     q.full_kkt = (opt->flags & SPMESL_FLAG_FULL_KKT) ? 1 : 0;
     q.dense_cnt = &dctl->dense64;
     q.dense_list = (int *)(ws + L.dq64);
-    q.late_list = (const int *)(ws + L.esclist2);
-    q.late_cnt = &dctl->esc_c;
     return q;
 }
 
@@ -1038,29 +1015,19 @@ static int enqueue_solve(spmesl_ctx *ctx, const spmesl_problem *prob, const spme
         mark(mk, s, "warm_start");
     }
     int vc;
-    const bool mixed = L.prec == SPMESL_MIXED;
-    // the mixed form with the row-tiled KKT pass polishes beside the
-    // re-solves (enqueue_columns); otherwise every column after them
-    const bool merged = mixed && kkt_rows_for<float>(p, 0, tu) > 0;
-    PolishArgs q{};
-    if (mixed) q = make_polish_args(L, ws, dctl, opt, max_outer, max_sweeps, max_rounds);
     if (L.prec == SPMESL_FP64)
         vc = enqueue_columns<double>(L, ws, dctl, opt, tu, tol_cols, 0.0, max_outer, max_sweeps, max_rounds, s,
                                      mk, fork, 0, warm);
     else
-        vc = enqueue_columns<float>(L, ws, dctl, opt, tu, tol_cols, mixed ? kMixedBand : 0.0, max_outer,
-                                    max_sweeps, max_rounds, s, mk, fork, 0, warm, merged ? &q : nullptr);
+        vc = enqueue_columns<float>(L, ws, dctl, opt, tu, tol_cols, L.prec == SPMESL_MIXED ? kMixedBand : 0.0,
+                                    max_outer, max_sweeps, max_rounds, s, mk, fork, 0, warm);
     if (vc != SPMESL_OK) return vc;
     if (ev) HIPTRY(ctx, hipEventRecord(ev[3], s));
 
-    if (mixed) {
-        if (merged) {
-            launch_polish_escalated(q, s);
-            mark(mk, s, "polish_escalated");
-        } else {
-            launch_polish(q, s);
-            mark(mk, s, "polish");
-        }
+    if (L.prec == SPMESL_MIXED) {
+        const PolishArgs q = make_polish_args(L, ws, dctl, opt, max_outer, max_sweeps, max_rounds);
+        launch_polish(q, s);
+        mark(mk, s, "polish");
         enqueue_dense64(q, L, ws, dctl, opt, tu, s, mk);
     }
     {
@@ -1519,29 +1486,17 @@ static int enqueue_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_proble
     launch_kkt_rows_grouped<T>((const KktJob<T> *)(tb + t.kkt), (const int64_t *)(tb + t.kkt_off), count,
                                gr.kkt_blocks, gr.rj, gr.pmax, s);
     if (late && (v = fork_batch_fill(ctx, count, res, plans, s, late)) != SPMESL_OK) return v;
-    const PolishArgs *ptab = (const PolishArgs *)(tb + t.polish);
-    // re-solves of the flagged columns (in the mixed form together with the
-    // double polish of every column the KKT pass left final), then every
-    // escalated column (the first solves' and the re-solves') in the wide
-    // tier (and its polish)
-    bool merged = false;
-    if constexpr (sizeof(T) == 4) {
-        if (mixed) {
-            launch_group_offsets(&dctl->dirty, ctl_words, count, dirty_off, s, col_off);
-            launch_resume_polish_grouped((const ColArgs<float> *)(tb + t.resume), ptab, dirty_off, count, gr.cols, s);
-            merged = true;
-        }
-    }
-    if (!merged) {
-        launch_group_offsets(&dctl->dirty, ctl_words, count, dirty_off, s);
-        launch_colsolve_list_grouped<T>((const ColArgs<T> *)(tb + t.resume), dirty_off, count, 0, s);
-    }
+    // re-solves of the flagged columns, then every escalated column (the
+    // first solves' and the re-solves') in the wide tier
+    launch_group_offsets(&dctl->dirty, ctl_words, count, dirty_off, s);
+    launch_colsolve_list_grouped<T>((const ColArgs<T> *)(tb + t.resume), dirty_off, count, 0, s);
     launch_group_offsets(&dctl->esc_c, ctl_words, count, esc_off, s);
     launch_colsolve_list_grouped<T>((const ColArgs<T> *)(tb + t.wide), esc_off, count, 1, s);
     if (mixed) {
-        // the polish of the columns the wide tier finished, then the
-        // polish's escalations, then the double dense tier of each problem
-        launch_polish_list_grouped(ptab, esc_off, count, gr.cols, s);
+        // the double polish of every column, then its escalations, then the
+        // double dense tier of each problem
+        const PolishArgs *ptab = (const PolishArgs *)(tb + t.polish);
+        launch_polish_grouped(ptab, col_off, count, gr.cols, 0, s);
         launch_group_offsets(&dctl->esc_polish, ctl_words, count, escp_off, s);
         launch_polish_grouped(ptab, escp_off, count, gr.cols, 1, s);
         for (int i = 0; i < count; ++i) {

@@ -205,10 +205,7 @@ __device__ __forceinline__ int group_of(const int64_t *off, int nd, int64_t g)
 
 // off[0] = 0, off[d + 1] = off[d] + max(0, cnt[d * stride]) for d < nd: the
 // offsets of work lists whose lengths are device counts (one per problem).
-// With plus (a prefix array of nd + 1 entries), plus[d + 1] - plus[d] is
-// added to each problem's count.
-void launch_group_offsets(const int *cnt, int64_t stride, int nd, int64_t *off, hipStream_t s,
-                          const int64_t *plus = nullptr);
+void launch_group_offsets(const int *cnt, int64_t stride, int nd, int64_t *off, hipStream_t s);
 
 // One problem's covariance tiles (the mixed form's kernel).
 struct SyrkJob {
@@ -279,8 +276,6 @@ struct ColArgs {
     int *colinfo;        // [p * 4] per column: sigma updates, sweeps, updates, rounds
     unsigned long long *counters;
     const int *flags;    // nonzero: bad input, every wave exits at once
-    int *mark;           // [p] or null: 0 the first solve stored the column final,
-                         // 1 the row-tiled KKT pass flagged it, 2 handed to the next tier
 };
 // tier: 0 = 32-wide working sets (escalating), 1 = 128-wide
 template <typename T>
@@ -374,7 +369,6 @@ struct KktArgs {
     int *dirty_cnt, *dirty_list;
     int *band_cnt, *band_idx;
     const int *flags;
-    int *mark;  // [p] or null: set to 1 for each flagged column
 };
 // rows per block that fit `lds_budget` bytes, 0 if one row does not fit
 int kkt_rows_per_block(int64_t p, size_t elem, size_t lds_budget);
@@ -423,20 +417,8 @@ struct PolishArgs {
     int *polinfo;           // [p * 8] per column: sigma updates, sweeps, updates, checks, added
     const int *flags;
     int full_kkt;           // 1: every column takes the full KKT pass (no band bound)
-    const int *late_list;   // columns the 128-coordinate float tier finished
-    const int *late_cnt;
 };
-// The polish of every column, then of its own escalations (128-wide).
 void launch_polish(const PolishArgs &a, hipStream_t s);
-void launch_polish_escalated(const PolishArgs &a, hipStream_t s);
-// The re-solves of the flagged columns and the polish in one launch (the
-// re-solve arguments c: mode 1 over the flagged list, with the marks); then
-// the polish of the late list (after the 128-coordinate float tier).
-void launch_resume_polish(const ColArgs<float> &c, const PolishArgs &a, hipStream_t s);
-void launch_polish_list(const PolishArgs &a, hipStream_t s);
-void launch_resume_polish_grouped(const ColArgs<float> *ctab, const PolishArgs *ptab, const int64_t *off, int nd,
-                                  int64_t cols, hipStream_t s);
-void launch_polish_list_grouped(const PolishArgs *tab, const int64_t *off, int nd, int64_t cols, hipStream_t s);
 // The polish of many problems: every column (tier2 = 0; off: the problems'
 // column offsets, total: all columns), or the escalated columns (tier2 = 1;
 // off: device prefix sums of the problems' escalation counts, total: an upper

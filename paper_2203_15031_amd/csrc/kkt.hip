@@ -83,7 +83,6 @@ __device__ __forceinline__ void kkt_flagged(const KktArgs<T> &A, int64_t k, int6
         if (slot == 0) {
             int d = atomicAdd(A.dirty_cnt, 1);
             A.dirty_list[d] = (int)k;
-            if (A.mark) A.mark[k] = 1;
         }
     }
     if (near) {

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_zero_words(uint32_t *__restrict__ a, in
 // Prefix sums of nd device counts (stride apart), by one block: the counts
 // are read in parallel, summed in order by one thread from LDS.
 __global__ __launch_bounds__(1024) void k_group_offsets(const int *__restrict__ cnt, int64_t stride, int nd,
-                                                        int64_t *__restrict__ off, const int64_t *__restrict__ plus)
+                                                        int64_t *__restrict__ off)
 {
     __shared__ int c[1024];
     __shared__ int64_t carry;
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(const int *__restrict__ 
         __syncthreads();
         if (d < nd) {
             const int v = cnt[(int64_t)d * stride];
-            c[threadIdx.x] = (v > 0 ? v : 0) + (plus ? (int)(plus[d + 1] - plus[d]) : 0);
+            c[threadIdx.x] = v > 0 ? v : 0;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -52,10 +52,9 @@ __global__ __launch_bounds__(1024) void k_group_offsets(const int *__restrict__ 
     }
 }
 
-void launch_group_offsets(const int *cnt, int64_t stride, int nd, int64_t *off, hipStream_t s,
-                          const int64_t *plus)
+void launch_group_offsets(const int *cnt, int64_t stride, int nd, int64_t *off, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, s, cnt, stride, nd, off, plus);
+    hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, s, cnt, stride, nd, off);
 }
 
 void launch_zero_words(uint32_t *a, int64_t n, hipStream_t s)

@@ -15,7 +15,7 @@
 //   violate.  Otherwise a full pass over the float S with the double
 //   coefficients flags every j within the error margin of lambda64, adds
 //   them to W' (where the double solve decides them exactly), and repeats.
-#include "colsolve_column.hpp"
+#include "colsolve_dev.hpp"
 
 namespace spmesl {
 
@@ -204,7 +204,7 @@ __device__ __forceinline__ void load_working_set_xt(const double *__restrict__ X
 constexpr int kDirectMax = 24;
 
 template <int LW>
-__device__ __forceinline__ bool polish_direct(WaveSm<double, LW> &sm, ColState<double, LW> &st, double lambda0, double tol)
+__device__ bool polish_direct(WaveSm<double, LW> &sm, ColState<double, LW> &st, double lambda0, double tol)
 {
     static_assert(ColState<double, LW>::NS == 1, "one coordinate per lane");
     const int lane = lane_id();
@@ -547,118 +547,8 @@ void launch_polish(const PolishArgs &a, hipStream_t s)
     constexpr int NW = 1;
     hipLaunchKernelGGL((k_polish<32, NW, 3>), dim3((unsigned)((a.p + NW - 1) / NW)),
                        dim3(kWave * NW), 0, s, a, 0);
-    launch_polish_escalated(a, s);
-}
-
-void launch_polish_escalated(const PolishArgs &a, hipStream_t s)
-{
     hipLaunchKernelGGL((k_polish<kWMax, 1>), dim3((unsigned)(a.p < 256 ? a.p : 256)), dim3(kWave), 0,
                        s, a, 1);
-}
-
-// ---------------------------------------------------------------------------
-// The re-solves and the polish in one launch (mixed form, after the
-// row-tiled KKT pass).  Item g < ndirty re-solves flagged column
-// work_list[g] in float (one wave, in-wave KKT passes) and then polishes it
-// in double; item ndirty + c polishes column c when its first solve left it
-// final (mark 0).  So the polish of the columns that pass the KKT check runs
-// beside the re-solves of the flagged ones instead of after them.  Columns
-// handed to the 128-coordinate tier (mark 2, or escalated by their re-solve)
-// are polished by the list launch after that tier.  A column's arithmetic is
-// that of the separate launches.
-// ---------------------------------------------------------------------------
-union ResumePolishSm {
-    WaveSm<float, 32> f;
-    WaveSm<double, 32> d;
-};
-
-__device__ __forceinline__ void resume_polish_item(const ColArgs<float> &C, const PolishArgs &P, int64_t g,
-                                                   int64_t nd, ResumePolishSm &sm)
-{
-    int64_t k;
-    if (g < nd) {
-        k = C.work_list[g];
-        if (!solve_column<float, 32, 4, 4, false, true>(C, sm.f, k, 0)) return;
-        // the column's float state, just stored by this wave, is read back
-        // by the polish
-        __threadfence();
-        __syncthreads();
-    } else {
-        k = g - nd;
-        if (C.mark[k] != 0) return;
-    }
-    polish_column<32>(P, sm.d, k, 0);
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_resume_polish(ColArgs<float> C,
-                                                                                               PolishArgs P)
-{
-    __shared__ ResumePolishSm sm;
-    const int64_t nd = *C.work_cnt;
-    const int64_t total = nd + P.p;
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) resume_polish_item(C, P, g, nd, sm);
-}
-
-// Grouped: item g is item g - off[d] of problem d (off: prefix sums of
-// ndirty + p).
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_resume_polish_grouped(
-    const ColArgs<float> *__restrict__ ctab, const PolishArgs *__restrict__ ptab, const int64_t *__restrict__ off,
-    int nd)
-{
-    __shared__ ResumePolishSm sm;
-    const int64_t total = off[nd];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const int d = group_of(off, nd, g);
-        const ColArgs<float> &C = ctab[d];
-        resume_polish_item(C, ptab[d], g - off[d], (int64_t)*C.work_cnt, sm);
-    }
-}
-
-// The polish of listed columns (those the 128-coordinate tier finished).
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_polish_list(PolishArgs A)
-{
-    __shared__ WaveSm<double, 32> sm;
-    const int64_t nwork = *A.late_cnt;
-    for (int64_t g = blockIdx.x; g < nwork; g += gridDim.x) polish_column<32>(A, sm, (int64_t)A.late_list[g], 0);
-}
-
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_polish_list_grouped(
-    const PolishArgs *__restrict__ tab, const int64_t *__restrict__ off, int nd)
-{
-    __shared__ WaveSm<double, 32> sm;
-    const int64_t total = off[nd];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const int d = group_of(off, nd, g);
-        const PolishArgs &A = tab[d];
-        polish_column<32>(A, sm, (int64_t)A.late_list[g - off[d]], 0);
-    }
-}
-
-void launch_resume_polish(const ColArgs<float> &c, const PolishArgs &a, hipStream_t s)
-{
-    const int64_t grid = a.p + (a.p < 1024 ? a.p : 1024);
-    hipLaunchKernelGGL(k_resume_polish, dim3((unsigned)grid), dim3(kWave), 0, s, c, a);
-}
-
-void launch_resume_polish_grouped(const ColArgs<float> *ctab, const PolishArgs *ptab, const int64_t *off, int nd,
-                                  int64_t cols, hipStream_t s)
-{
-    if (cols <= 0) return;
-    const int64_t grid = cols + (cols < 4096 ? cols : 4096);
-    hipLaunchKernelGGL(k_resume_polish_grouped, dim3((unsigned)grid), dim3(kWave), 0, s, ctab, ptab, off, nd);
-}
-
-void launch_polish_list(const PolishArgs &a, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_polish_list, dim3((unsigned)(a.p < 512 ? a.p : 512)), dim3(kWave), 0, s, a);
-}
-
-void launch_polish_list_grouped(const PolishArgs *tab, const int64_t *off, int nd, int64_t cols, hipStream_t s)
-{
-    if (cols <= 0) return;
-    hipLaunchKernelGGL(k_polish_list_grouped, dim3((unsigned)(cols < 1024 ? cols : 1024)), dim3(kWave), 0, s, tab,
-                       off, nd);
 }
 
 } // namespace spmesl
