@@ -399,9 +399,12 @@ class Context:
         need = sz.value
         self._workspace(need + 4096)
         self._bind_stream()
-        status = (C.c_int * max(m, 1))()
+        unset = 1  # no status code is positive: a slot the call did not write
+        status = (C.c_int * max(m, 1))(*([unset] * max(m, 1)))
         st = load().spmesl_solve_batch(self._h, m, probs, C.byref(opt), lams, ress, status)
-        if st != OK and (check or st != ENOCONV):
+        # check=False returns the per-data-set statuses when the call reached
+        # every data set (a data set's own error does not stop the others)
+        if st != OK and (check or any(status[i] == unset for i in range(m))):
             raise SpmeslError(st, self._err())
         return [SolveResult(outs[i].get("B"), outs[i].get("sigma"), outs[i].get("Omega"), status[i],
                             stats[i].as_dict()) for i in range(m)]

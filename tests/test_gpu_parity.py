@@ -362,6 +362,30 @@ def _batch_matches_single_solves(ctx):
         assert rel_err(host(r.Omega), ref["Omega"]) <= 1e-4
 
 
+def test_solve_batch_isolates_a_bad_data_set(sp):
+    # a NaN in one data set of a grouped batch fails that data set alone:
+    # the others equal their single solves bit for bit
+    from paper_2203_15031_amd import workloads as Wk
+    Xs = Wk.generate_batch(count=3, seed=7, pmin=64, pmax=160)
+    Xs[1] = Xs[1].copy()
+    Xs[1][3, 2] = np.nan
+    lams = [math.sqrt(2 * math.log(X.shape[1]) / X.shape[0]) for X in Xs]
+    Xg = [gpu(X) for X in Xs]
+    ctx = sp.Context(0)
+    try:
+        for prec in ("mixed", "fp64"):
+            res = ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec, check=False)
+            assert [r.status for r in res] == [0, sp.ENONFINITE, 0]
+            for i in (0, 2):
+                one = ctx.solve(Xg[i], lams[i], tol=1e-8, precision=prec, eager=True)
+                assert torch.equal(res[i].B, one.B) and torch.equal(res[i].Omega, one.Omega)
+            with pytest.raises(sp.SpmeslError) as e:
+                ctx.solve_batch(Xg, lams, tol=1e-8, precision=prec)
+            assert e.value.code == sp.ENONFINITE
+    finally:
+        ctx.close()
+
+
 def test_solve_batch_one_after_another(ctx):
     """Batches that do not run grouped (the data form) still run one data set
     after another, each result equal to the single solve's."""
