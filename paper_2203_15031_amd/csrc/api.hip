@@ -1366,6 +1366,7 @@ static int fork_batch_fill(spmesl_ctx *ctx, int count, const spmesl_result *res,
 struct BatchGrids {
     int64_t cols = 0, tiles = 0, kkt_blocks = 0, pmax = 0;
     int rj = 4;
+    int syrk_edge = 64;  // covariance tile edge of the double and float forms
 };
 
 static void limits_of(const spmesl_options *opt, int *max_outer, int *max_sweeps, int *max_rounds)
@@ -1401,6 +1402,16 @@ static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_op
     Ctl *dctl = (Ctl *)(ws0 + B.ctl_off);
     BatchGrids gr;
     for (int i = 0; i < count; ++i) gr.rj = std::min(gr.rj, kkt_rows_for<T>(plans[(size_t)i].p, 0, tu));
+    if (sizeof(T) == 8) {
+        // 128 x 128 double tiles when the batch's tiles of that edge fill the
+        // chip (the same rule as one problem's, on the batch's total)
+        int64_t t128 = 0;
+        for (int i = 0; i < count; ++i) {
+            const int64_t e = (plans[(size_t)i].p + 127) / 128;
+            t128 += e * (e + 1) / 2;
+        }
+        gr.syrk_edge = t128 >= 256 ? 128 : 64;
+    }
     auto *first = (ColArgs<T> *)(h + t.first);
     auto *resume = (ColArgs<T> *)(h + t.resume);
     auto *wide = (ColArgs<T> *)(h + t.wide);
@@ -1423,7 +1434,7 @@ static BatchGrids build_batch_tables(spmesl_ctx *ctx, int count, const spmesl_op
                                 (float *)(ws + L.S), sc, &tiles);
         else
             ((SyrkJobT<T> *)(h + t.syrk))[i] =
-                syrk_job_mfma<T>((const T *)(ws + L.xs), L.n, L.p, (T *)(ws + L.S), sc, &tiles);
+                syrk_job_mfma<T>((const T *)(ws + L.xs), L.n, L.p, (T *)(ws + L.S), sc, gr.syrk_edge, &tiles);
         ColArgs<T> a = batch_col_args<T>(L, ws, c, opt);
         first[i] = a;
         kkt[i] = kkt_job<T>(make_kkt_args<T>(a, L, ws, c), gr.rj, &blocks);
@@ -1481,7 +1492,7 @@ static int enqueue_batch_grouped(spmesl_ctx *ctx, int count, const spmesl_proble
                                    gr.tiles, s);
     else
         launch_syrk_mfma_grouped<T>((const SyrkJobT<T> *)(tb + t.syrk), (const int64_t *)(tb + t.tile_off), count,
-                                    gr.tiles, s);
+                                    gr.tiles, gr.syrk_edge, s);
     launch_colsolve_first_grouped<T>((const ColArgs<T> *)(tb + t.first), col_off, count, gr.cols, s);
     launch_kkt_rows_grouped<T>((const KktJob<T> *)(tb + t.kkt), (const int64_t *)(tb + t.kkt_off), count,
                                gr.kkt_blocks, gr.rj, gr.pmax, s);

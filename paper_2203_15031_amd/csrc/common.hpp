@@ -227,10 +227,12 @@ struct SyrkJobT {
     int64_t pv;
     int *scnt, *sidx;
 };
+// Tiles of `edge` (the double form: 128 or 64, see syrk_f64_edge; float: 64).
+int syrk_f64_edge(int64_t p);
 template <typename T>
-SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen &sc, int64_t *tiles);
+SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen &sc, int edge, int64_t *tiles);
 template <typename T>
-void launch_syrk_mfma_grouped(const SyrkJobT<T> *tab, const int64_t *tile_off, int nd, int64_t tiles,
+void launch_syrk_mfma_grouped(const SyrkJobT<T> *tab, const int64_t *tile_off, int nd, int64_t tiles, int edge,
                               hipStream_t s);
 SyrkJob syrk_job_bf16x3(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t npad, int64_t p, float *S,
                         const Screen &sc, int64_t *tiles);

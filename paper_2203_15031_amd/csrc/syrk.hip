@@ -510,8 +510,15 @@ __global__ __launch_bounds__(256, 2) void k_syrk_d128_grouped(const SyrkJobT<dou
     syrk_d128_tile(J.Xs, J.n, J.p, J.S, bj, bk, J.invn, J.thr, J.pv, J.scnt, J.sidx, sm, scr);
 }
 
-// the tile edge of each form's kernel
-template <typename T> constexpr int syrk_edge() { return sizeof(T) == 8 ? kD : 64; }
+// Tile edge of the double form: 128 when its upper-triangle tiles fill the
+// chip (at least 256), else 64 (small p: the 64 x 64 kernel keeps more CUs
+// busy).  Both kernels give each entry its products in the same sample order,
+// so S is the same to the bit either way.
+int syrk_f64_edge(int64_t p)
+{
+    const int64_t t = (p + kD - 1) / kD;
+    return t * (t + 1) / 2 >= 256 ? kD : 64;
+}
 
 // The tiles of many problems in one launch, one tile per block: block b
 // (in the XCD-aware order) is tile b - off[d] of problem d.
@@ -530,14 +537,14 @@ __global__ __launch_bounds__(256) void k_syrk_mfma_grouped(const SyrkJobT<T> *__
 }
 
 template <typename T>
-SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen &sc, int64_t *tiles)
+SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen &sc, int edge, int64_t *tiles)
 {
     SyrkJobT<T> j{};
     j.Xs = Xs;
     j.n = n;
     j.p = p;
     j.S = S;
-    j.Tt = (int)((p + syrk_edge<T>() - 1) / syrk_edge<T>());
+    j.Tt = (int)((p + edge - 1) / edge);
     j.invn = (T)(1.0 / (double)n);
     if constexpr (sizeof(T) == 8)
         j.thr = (T)sc.thr64;
@@ -551,28 +558,35 @@ SyrkJobT<T> syrk_job_mfma(const T *Xs, int64_t n, int64_t p, T *S, const Screen 
 }
 
 template <typename T>
-void launch_syrk_mfma_grouped(const SyrkJobT<T> *tab, const int64_t *tile_off, int nd, int64_t tiles, hipStream_t s)
+void launch_syrk_mfma_grouped(const SyrkJobT<T> *tab, const int64_t *tile_off, int nd, int64_t tiles, int edge,
+                              hipStream_t s)
 {
     if (tiles <= 0) return;
-    if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(k_syrk_d128_grouped, dim3((unsigned)tiles), dim3(256), 0, s, tab, tile_off, nd);
+    if (sizeof(T) == 8 && edge == kD)
+        hipLaunchKernelGGL(k_syrk_d128_grouped, dim3((unsigned)tiles), dim3(256), 0, s,
+                           (const SyrkJobT<double> *)tab, tile_off, nd);
     else
         hipLaunchKernelGGL(k_syrk_mfma_grouped<T>, dim3((unsigned)tiles), dim3(256), 0, s, tab, tile_off, nd);
 }
 
-template SyrkJobT<double> syrk_job_mfma<double>(const double *, int64_t, int64_t, double *, const Screen &, int64_t *);
-template SyrkJobT<float> syrk_job_mfma<float>(const float *, int64_t, int64_t, float *, const Screen &, int64_t *);
-template void launch_syrk_mfma_grouped<double>(const SyrkJobT<double> *, const int64_t *, int, int64_t, hipStream_t);
-template void launch_syrk_mfma_grouped<float>(const SyrkJobT<float> *, const int64_t *, int, int64_t, hipStream_t);
+template SyrkJobT<double> syrk_job_mfma<double>(const double *, int64_t, int64_t, double *, const Screen &, int,
+                                                int64_t *);
+template SyrkJobT<float> syrk_job_mfma<float>(const float *, int64_t, int64_t, float *, const Screen &, int,
+                                              int64_t *);
+template void launch_syrk_mfma_grouped<double>(const SyrkJobT<double> *, const int64_t *, int, int64_t, int,
+                                               hipStream_t);
+template void launch_syrk_mfma_grouped<float>(const SyrkJobT<float> *, const int64_t *, int, int64_t, int,
+                                              hipStream_t);
 
 template <typename T>
 static void launch_syrk_t(const T *Xs, int64_t n, int64_t p, T *S, T thr, const Screen &sc, hipStream_t s)
 {
-    const int Tt = (int)((p + syrk_edge<T>() - 1) / syrk_edge<T>());
+    const int edge = sizeof(T) == 8 ? syrk_f64_edge(p) : 64;
+    const int Tt = (int)((p + edge - 1) / edge);
     const int64_t ntiles = (int64_t)Tt * (Tt + 1) / 2;
-    if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(k_syrk_d128, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
-                           1.0 / (double)n, (double)thr, sc.pv > 0 ? sc.pv : p, sc.cnt, sc.idx);
+    if (sizeof(T) == 8 && edge == kD)
+        hipLaunchKernelGGL(k_syrk_d128, dim3((unsigned)ntiles), dim3(256), 0, s, (const double *)Xs, n, p,
+                           (double *)S, Tt, 1.0 / (double)n, (double)thr, sc.pv > 0 ? sc.pv : p, sc.cnt, sc.idx);
     else
         hipLaunchKernelGGL(k_syrk_mfma<T>, dim3((unsigned)ntiles), dim3(256), 0, s, Xs, n, p, S, Tt,
                            (T)(1.0 / (double)n), thr, sc.pv > 0 ? sc.pv : p, sc.cnt, sc.idx);
